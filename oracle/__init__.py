@@ -1,0 +1,111 @@
+"""CPU oracle -- test infrastructure only.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library
+(``paper_2105_04419_amd``) never imports it and shares no code with it.
+
+Contents
+  edt_bruteforce / edt_points / edt_separable
+      The truncated squared Euclidean distance transform of the VDB-EDT paper
+      (section III, Eq. 1, limited to the transform radius d_max), written in
+      plain C in ``edt_oracle.c`` and called through ctypes.
+  clearance (module ``oracle.clearance``)
+      The trajectory clearance cost built on the distance field (section III,
+      Eq. 2 clearance term, squared hinge form), its analytic gradient and a
+      central finite-difference gradient, all in float64 numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "edt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile edt_oracle.c with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                        "-Wall", "-o", tmp, _SRC], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        ci = ctypes.c_int
+        L.oracle_edt_bruteforce.argtypes = [u8p, ci, ci, ci, ci, i32p]
+        L.oracle_edt_points.argtypes = [u8p, ci, ci, ci, ci, i32p, ctypes.c_int64, i32p]
+        L.oracle_edt_separable.argtypes = [u8p, ci, ci, ci, ci, i32p]
+        L.oracle_threads.argtypes = [ci]
+        for f in (L.oracle_edt_bruteforce, L.oracle_edt_points,
+                  L.oracle_edt_separable, L.oracle_threads):
+            f.restype = ci
+        _lib = L
+    return _lib
+
+
+def _u8(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _grid(occ):
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    assert occ.ndim == 3
+    nz, ny, nx = occ.shape
+    return occ, nx, ny, nz
+
+
+def edt_bruteforce(occ: np.ndarray, dmax: int) -> np.ndarray:
+    """s = min(D, min_y |x-y|^2) for every voxel; occ is (nz, ny, nx)."""
+    occ, nx, ny, nz = _grid(occ)
+    out = np.empty(occ.shape, dtype=np.int32)
+    rc = lib().oracle_edt_bruteforce(_u8(occ), nx, ny, nz, int(dmax), _i32(out))
+    if rc:
+        raise ValueError(f"oracle_edt_bruteforce: bad arguments ({rc})")
+    return out
+
+
+def edt_points(occ: np.ndarray, dmax: int, xyz: np.ndarray) -> np.ndarray:
+    """The definition evaluated at voxels xyz int[n, 3] given as (x, y, z)."""
+    occ, nx, ny, nz = _grid(occ)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    out = np.empty(len(xyz), dtype=np.int32)
+    rc = lib().oracle_edt_points(_u8(occ), nx, ny, nz, int(dmax), _i32(xyz),
+                                 len(xyz), _i32(out))
+    if rc:
+        raise ValueError(f"oracle_edt_points: bad arguments ({rc})")
+    return out
+
+
+def edt_separable(occ: np.ndarray, dmax: int) -> np.ndarray:
+    """Same field as edt_bruteforce, one axis at a time (fast enough for
+    the 1024x1024x128 extent)."""
+    occ, nx, ny, nz = _grid(occ)
+    out = np.empty(occ.shape, dtype=np.int32)
+    rc = lib().oracle_edt_separable(_u8(occ), nx, ny, nz, int(dmax), _i32(out))
+    if rc:
+        raise ValueError(f"oracle_edt_separable: failed ({rc})")
+    return out
+
+
+def threads(n: int = 0) -> int:
+    """Set (n > 0) and return the OpenMP thread count of the oracle."""
+    return int(lib().oracle_threads(int(n)))
