@@ -1,0 +1,289 @@
+#!/usr/bin/env python
+"""Benchmark of the exact truncated EDT on one MI355X.
+
+One step = one global transform (edt_global) of the sparse tunnel map,
+1024 x 1024 x 128 voxels stored as 8^3 leaf blocks (~5% of blocks hold
+walls), d_max = 32, int32 output, with the block list already resident in
+HBM.  `value` is extent voxels per second.  The same JSON line also reports:
+  roofline       dominant kernel of the step, algorithmic bytes / its mean
+                 HIP-event duration, against 8 TB/s;
+  cpu_baseline   the CPU oracle (separable windowed minimum, OpenMP) on the
+                 same map;
+  incremental    p50 / p99 latency of edt_update over simulated range scans
+                 along the tunnels, plus an incremental == global check;
+  clearance      clearance cost forward + backward on the 64x64x32 map field
+                 with 4096 x 64 waypoints, points per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("voxels/s global EDT + p50/p99 incremental update latency; "
+          "clearance fwd+bwd pts/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q))
+
+
+def traffic_record(kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_tunnel_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b:
+        return None
+    src = open(os.path.join(ROOT, "paper_2105_04419_amd", "csrc", "edt_kernels.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != m.group(1):
+        return None
+    return float(b.group(1))
+
+
+def bench_global(args, torch, np):
+    import workloads
+    from paper_2105_04419_amd import Field
+    occ = workloads.tunnels(args.seed)
+    nz, ny, nx = occ.shape
+    bxyz, bocc = workloads.dense_to_blocks(occ)
+    xyz_d = torch.from_numpy(bxyz).cuda()
+    occ_d = torch.from_numpy(bocc).cuda()
+    f = Field((nx, ny, nz), args.dmax)
+    for _ in range(args.warmup):
+        f.global_blocks(xyz_d, occ_d)
+    torch.cuda.synchronize()
+    st = f.stats()
+    assert st["error"] == 0, st
+    f.timing_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f.global_blocks(xyz_d, occ_d)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = f.timing_read()
+    f.timing_begin(0)
+    ms = (t1 - t0) * 1e3 / args.steps
+    n_ext = nx * ny * nz
+    n_c = st["blocks"] * 512
+    return dict(f=f, occ=occ, st=st, ms=ms, phases=ph, n_ext=n_ext, n_c=n_c,
+                n_obst_blocks=len(bxyz), xyz_d=xyz_d, occ_d=occ_d)
+
+
+def roofline(g):
+    """Dominant kernel of the global step and its algorithmic HBM bytes:
+    pass_z reads g2 (2 B) and writes s (4 B) per voxel of the region, plus
+    one int32 block maximum per block; pass_y reads dist (1 B) and writes g2
+    (2 B); pass_x reads 64 B of bits and writes 512 B of dist per block."""
+    ph = g["phases"]
+    nb = g["st"]["blocks"]
+    per_launch = {
+        "pass_z": nb * 512 * 6 + nb * 4,
+        "pass_y": nb * 512 * 3,
+        "pass_x": nb * (64 + 512),
+    }
+    kern = max(per_launch, key=lambda k: ph[k])
+    ms = ph[kern]
+    achieved = per_launch[kern] / (ms * 1e-3) / 1e9
+    tr = traffic_record(kern)
+    return {
+        "kernel": f"k_{kern}",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": tr,
+        "algorithmic_bytes_per_launch": per_launch[kern],
+        "mean_ms": round(ms, 5),
+    }
+
+
+def bench_cpu(g, args, np):
+    import oracle
+    oracle.build(force=False)
+    nthreads = oracle.threads(args.cpu_threads) if args.cpu_threads else oracle.threads()
+    occ = g["occ"]
+    reps, t_total, ref = 0, 0.0, None
+    while t_total < args.cpu_seconds and reps < 20:
+        t0 = time.perf_counter()
+        ref = oracle.edt_separable(occ, args.dmax)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return {
+        "value": g["n_ext"] * reps / t_total,
+        "unit": "voxels/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"separable oracle on the full {occ.shape[2]}x{occ.shape[1]}x{occ.shape[0]} "
+                  f"tunnel extent, d_max {args.dmax}, {reps} run(s), {t_total:.1f} s",
+        "ms_per_map": round(t_total / reps * 1e3, 1),
+    }, ref
+
+
+def bench_incremental(g, args, torch, np):
+    import workloads
+    from workloads.scans import ScanSim, tunnel_path
+    from paper_2105_04419_amd import Field
+    cache = os.path.join(workloads.cache_dir(), f"scans_tunnel_s{args.seed}_{args.scans}.npz")
+    if os.path.exists(cache):
+        z = np.load(cache)
+        lists = [(z[f"x{i}"], z[f"s{i}"]) for i in range(args.scans)]
+        final = z["final"]
+    else:
+        sim = ScanSim(g["occ"], tunnel_path(args.seed), seed=args.seed)
+        lists = []
+        for _ in range(args.scans):
+            x, s, _ = sim.step()
+            lists.append((x, s))
+        final = sim.map
+        np.savez(cache + ".tmp.npz", final=final,
+                 **{f"x{i}": x for i, (x, _) in enumerate(lists)},
+                 **{f"s{i}": s for i, (_, s) in enumerate(lists)})
+        os.replace(cache + ".tmp.npz", cache)
+    f = g["f"]
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    dev = [(torch.from_numpy(x).cuda(), torch.from_numpy(s).cuda()) for x, s in lists]
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dev_ms, wall_ms, changed, dirty = [], [], [], []
+    for i, (x, s) in enumerate(dev):
+        t0 = time.perf_counter()
+        e0.record()
+        f.update(x, s)
+        e1.record()
+        e1.synchronize()
+        t1 = time.perf_counter()
+        if i >= args.scan_warmup:
+            dev_ms.append(e0.elapsed_time(e1))
+            wall_ms.append((t1 - t0) * 1e3)
+            st = f.stats()
+            changed.append(st["changed"])
+            dirty.append(st["dirty_blocks"])
+    h = Field(f.shape, args.dmax)
+    h.global_(torch.from_numpy(final).cuda())
+    same = bool(torch.equal(h.dense(), f.dense()))
+    return {
+        "scans": len(dev_ms),
+        "p50_ms": round(pct(dev_ms, 50), 4),
+        "p99_ms": round(pct(dev_ms, 99), 4),
+        "host_p50_ms": round(pct(wall_ms, 50), 4),
+        "host_p99_ms": round(pct(wall_ms, 99), 4),
+        "changed_voxels_mean": round(float(np.mean(changed)), 1),
+        "dirty_blocks_mean": round(float(np.mean(dirty)), 1),
+        "incremental_equals_global": same,
+    }
+
+
+def bench_clearance(args, torch, np):
+    import workloads
+    from paper_2105_04419_amd import ClearanceCost, Field
+    occ = workloads.dense_boxes(0)
+    f = Field((64, 64, 32), 20)
+    f.global_(torch.from_numpy(occ).cuda())
+    s = f.dense()
+    wp = torch.from_numpy(workloads.trajectories(0, occ)).cuda()
+    n = wp.shape[0] * wp.shape[1]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    times = []
+    for r in range(args.clear_reps + 5):
+        x = wp.detach().requires_grad_(True)
+        e0.record()
+        c = ClearanceCost.apply(s, x, 0.2, 1.0)
+        c.sum().backward()
+        e1.record()
+        e1.synchronize()
+        if r >= 5:
+            times.append(e0.elapsed_time(e1))
+    med = pct(times, 50)
+    return {"points": n, "median_ms": round(med, 4), "pts_per_s": n / (med * 1e-3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--dmax", type=int, default=32)
+    ap.add_argument("--scans", type=int, default=200)
+    ap.add_argument("--scan-warmup", type=int, default=5)
+    ap.add_argument("--clear-reps", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log(f"[bench] global transform, tunnel map seed {args.seed}, d_max {args.dmax}")
+    g = bench_global(args, torch, np)
+    rl = roofline(g)
+    out = {
+        "metric": METRIC,
+        "value": g["n_ext"] / (g["ms"] * 1e-3),
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(g["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sparse tunnel map 1024x1024x128, 12 tubes, 8^3 leaf blocks, "
+                        f"d_max {args.dmax}, int32 squared distances, seed {args.seed}",
+            "obstacle_blocks": g["n_obst_blocks"],
+            "region_blocks": g["st"]["blocks"],
+            "region_voxels": g["n_c"],
+            "extent_voxels": g["n_ext"],
+        },
+        "region_voxels_per_s": g["n_c"] / (g["ms"] * 1e-3),
+        "phases_ms": {k: round(v, 5) for k, v in g["phases"].items() if k != "calls"},
+        "roofline": rl,
+    }
+    if not args.no_cpu:
+        log("[bench] cpu oracle baseline")
+        cb, ref = bench_cpu(g, args, np)
+        out["cpu_baseline"] = cb
+        got = g["f"].dense().cpu().numpy()
+        out["parity_global_vs_oracle"] = bool(np.array_equal(got, ref))
+    if not args.no_extra:
+        log(f"[bench] incremental: {args.scans} scans")
+        out["incremental"] = bench_incremental(g, args, torch, np)
+        log("[bench] clearance 4096 x 64")
+        out["clearance"] = bench_clearance(args, torch, np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

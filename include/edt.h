@@ -1,0 +1,195 @@
+/*
+ * edt.h -- C ABI of libedt, an exact truncated squared Euclidean distance
+ * transform (EDT) of voxel occupancy maps on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is VDB-EDT (Zhu et al., "VDB-EDT: An Efficient Euclidean Distance
+ * Transform Algorithm Based on VDB Data Structure").  What is computed is the
+ * paper's distance field: Eq. 1 (section III) with the squared Euclidean
+ * distance, limited to the transform radius d_max (section III, the LIDT
+ * restriction); cells beyond the radius hold the background value, as the
+ * Initialize procedure of Algorithm 1 sets it.  Distances are squared and in
+ * voxel units, so for every voxel x of the map extent
+ *
+ *     s(x) = min( D, min over occupied y of |x - y|^2 ),   D = d_max^2,
+ *
+ * 0 on obstacles, D where no obstacle lies within d_max.  Results are exact
+ * int32; a global transform and any sequence of incremental updates give the
+ * same bits.
+ *
+ * Conventions
+ *  - Every pointer named d_* is a device pointer (HIP global memory); the
+ *    caller owns all of them.  The library never allocates device memory: the
+ *    caller passes one workspace buffer at create time (edt_workspace_bytes).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    calls except edt_create, edt_destroy, edt_workspace_bytes and
+ *    edt_status_str enqueue work on that stream and return without waiting,
+ *    unless stated otherwise.
+ *  - Grid layout of dense arrays: x fastest, index x + nx*(y + ny*z).
+ *  - Occupancy bytes: nonzero = occupied.
+ *  - Coordinates outside [0,nx)x[0,ny)x[0,nz) are never obstacles and read as
+ *    D.
+ *  - A context is not thread-safe; use it from one host thread and one
+ *    stream at a time.
+ *  - Every call returns an edt_status; nothing aborts, throws or prints.
+ */
+#ifndef EDT_H_
+#define EDT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EDT_OK = 0,
+    EDT_ERR_ARG = -1,       /* invalid argument (null pointer, bad size)      */
+    EDT_ERR_RANGE = -2,     /* coordinates outside the map extent             */
+    EDT_ERR_CAPACITY = -3,  /* workspace / block pool / change list too small */
+    EDT_ERR_HIP = -4,       /* a HIP runtime call failed                      */
+    EDT_ERR_STATE = -5      /* call not valid in the context's current state  */
+} edt_status;
+
+/* Human-readable name of a status code (static string). */
+const char* edt_status_str(int status);
+
+/* Map configuration, fixed for the life of a context.
+ *   nx, ny, nz   extent in voxels, each 1 .. 2^20.
+ *   d_max        transform radius in voxels, 1 .. 255 (so D <= 65025).
+ *   max_blocks   capacity of the leaf-block pool (8x8x8 voxels per block);
+ *                0 = one slot per block of the extent.  Blocks are created
+ *                only where the field can differ from D: blocks holding an
+ *                obstacle and the blocks within ceil(d_max/8) blocks of them
+ *                (Chebyshev distance).
+ *   max_changes  capacity for one edt_update call (entries), 0 = 2^20.       */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t d_max;
+    int64_t max_blocks;
+    int64_t max_changes;
+} edt_config;
+
+typedef struct edt_ctx edt_ctx;
+
+/* Bytes of device workspace that edt_create needs for `cfg`, or a negative
+ * edt_status if cfg is invalid. */
+int64_t edt_workspace_bytes(const edt_config* cfg);
+
+/* Creates a context over the caller's device workspace d_ws (at least
+ * edt_workspace_bytes(cfg) bytes, 256-byte aligned, owned by the caller and
+ * kept alive until edt_destroy).  The field starts empty: s = D everywhere
+ * (Algorithm 1, Initialize).  Initialisation is enqueued on `stream`.
+ * On success *out receives a host object owned by the library. */
+edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes,
+                      void* stream, edt_ctx** out);
+
+/* Frees the host object.  Does not touch the caller's workspace. */
+edt_status edt_destroy(edt_ctx* ctx);
+
+/* Input of a global transform: either a dense grid or a list of leaf blocks.
+ *   EDT_MAP_DENSE   d_occ: nx*ny*nz bytes, grid layout.
+ *   EDT_MAP_BLOCKS  d_block_xyz: int32[n_blocks][3] block coordinates
+ *                   (bx, by, bz), voxel (8bx+i, 8by+j, 8bz+k) for in-block
+ *                   offsets i, j, k in 0..7; d_block_occ: uint8[n_blocks][512]
+ *                   in-block occupancy, index i + 8j + 64k.  Voxels of a block
+ *                   that fall outside the extent are ignored.  Repeated block
+ *                   coordinates are merged (union of occupancy).  Blocks with
+ *                   coordinates outside the extent set the device error word
+ *                   (EDT_ERR_RANGE, see edt_get_error) and are skipped.     */
+typedef enum { EDT_MAP_DENSE = 0, EDT_MAP_BLOCKS = 1 } edt_map_kind;
+typedef struct {
+    int32_t kind;
+    const uint8_t* d_occ;
+    const int32_t* d_block_xyz;
+    const uint8_t* d_block_occ;
+    int64_t n_blocks;
+} edt_map;
+
+/* Global transform: replaces the context's occupancy with `map` and computes
+ * s everywhere (paper section V-A, global transform; Eq. 1).  Exact. */
+edt_status edt_global(edt_ctx* ctx, const edt_map* map, void* stream);
+
+/* Incremental transform (Algorithm 1: SetObstacle / RemoveObstacle followed
+ * by DistanceTransform).  d_xyz: int32[n][3] voxel coordinates (x, y, z);
+ * d_state: uint8[n] target state, nonzero = occupied.  States are absolute:
+ * an entry equal to the current occupancy is a no-op (as SetObstacle on an
+ * obstacle, RemoveObstacle on a free cell); when a voxel appears several
+ * times the last entry wins (the same result as applying the entries in
+ * order).  Afterwards s equals edt_global of the new occupancy, bit for bit.
+ * n == 0 is a no-op.  n > max_changes returns EDT_ERR_CAPACITY with nothing
+ * enqueued.  Entries outside the extent make the whole call a no-op and set
+ * the device error word to EDT_ERR_RANGE.  If the block pool fills up the
+ * error word becomes EDT_ERR_CAPACITY and the field must be rebuilt with
+ * edt_global. */
+edt_status edt_update(edt_ctx* ctx, const int32_t* d_xyz, const uint8_t* d_state,
+                      int64_t n, void* stream);
+
+/* s at n voxel coordinates d_xyz (int32[n][3]) into d_out (int32[n]);
+ * out-of-extent coordinates and voxels of blocks that hold no field read D
+ * (the VDB background value). */
+edt_status edt_query(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
+                     int32_t* d_out, void* stream);
+
+/* Dense readback: s for the whole extent into d_out (int32[nx*ny*nz]). */
+edt_status edt_read_dense(edt_ctx* ctx, int32_t* d_out, void* stream);
+
+/* Dense occupancy readback into d_occ (uint8[nx*ny*nz], 0/1). */
+edt_status edt_read_occupancy(edt_ctx* ctx, uint8_t* d_occ, void* stream);
+
+/* Counters of the context (host struct).  Synchronises `stream`.
+ *   blocks         leaf blocks holding field values (the computed region)
+ *   obstacle_blocks blocks whose neighbourhood has been added to the region
+ *   changed        voxels whose occupancy changed in the last edt_update
+ *   added, removed split of `changed`
+ *   seed_blocks    blocks holding those voxels (the wave centres)
+ *   raise_blocks   blocks marked by the raise front in the last update
+ *   lower_blocks   blocks marked by the lower front in the last update
+ *   dirty_blocks   union of the two: blocks whose values were recomputed
+ *   error          device error word (EDT_OK or a negative edt_status)     */
+typedef struct {
+    int64_t blocks, obstacle_blocks;
+    int64_t changed, added, removed;
+    int64_t seed_blocks, raise_blocks, lower_blocks, dirty_blocks;
+    int32_t error, d_max;
+} edt_stats;
+edt_status edt_get_stats(edt_ctx* ctx, edt_stats* host_out, void* stream);
+
+/* Synchronises `stream`, returns the device error word and clears it. */
+edt_status edt_get_error(edt_ctx* ctx, void* stream);
+
+/* Profiling.  edt_timing_begin arms HIP events around the phases of the
+ * next n_calls calls of edt_global on this context (0 disarms and frees
+ * them).  edt_timing_read waits for the recorded events and writes into
+ * ms[0..5] the mean duration in milliseconds of each phase over the recorded
+ * calls: ingest, region growth, work lists, pass x, pass y, pass z;
+ * *n_recorded receives the number of calls recorded.  The events are recorded
+ * on the stream the calls were made on. */
+edt_status edt_timing_begin(edt_ctx* ctx, int32_t n_calls);
+edt_status edt_timing_read(edt_ctx* ctx, float* ms, int32_t* n_recorded);
+
+/* ------------------------------------------------------------------------ */
+/* Clearance cost on a dense field (paper section III, Eq. 2, clearance
+ * term, in the squared-hinge form  c(p) = max(0, margin - d(p))^2).
+ *   d_s        int32[nz][ny][nx] squared voxel distances (e.g. from
+ *              edt_read_dense); each side >= 2.
+ *   h          voxel edge in metres; voxel center (i,j,k) sits at (i,j,k)*h.
+ *   d(p)       trilinear interpolation of h*sqrt(s) at p (metres), with the
+ *              cell index clamped to [0, n-2] and the cell coordinate to
+ *              [0, 1] per axis.
+ *   d_wp       float[T][W][3] waypoints (x, y, z) in metres.
+ *   d_cost     float[T]: sum over the W waypoints of c(p), accumulated in
+ *              fp32 in a fixed order (deterministic).
+ * edt_clearance_bwd writes d_gwp (float[T][W][3]) = d_gcost[t] * dc/dp,
+ * zero on axes whose cell coordinate was clamped and where d >= margin.    */
+edt_status edt_clearance_fwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz,
+                             float h, float margin, const float* d_wp,
+                             int64_t T, int32_t W, float* d_cost, void* stream);
+edt_status edt_clearance_bwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz,
+                             float h, float margin, const float* d_wp,
+                             int64_t T, int32_t W, const float* d_gcost,
+                             float* d_gwp, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDT_H_ */

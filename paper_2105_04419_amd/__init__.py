@@ -1,0 +1,286 @@
+"""Python binding of libedt: exact truncated squared EDT on an MI355X.
+
+The binding only marshals arguments: every step of the transform runs in the
+HIP kernels of ``libedt.so`` (built from ``csrc/`` by ``build.py``).  PyTorch
+supplies device memory (the workspace and result tensors) and the stream.
+There is no CPU fallback: if the library or a GPU is missing, calls raise.
+
+    f = Field((nx, ny, nz), d_max)
+    f.global_(occ)              # occ: torch.uint8 (nz, ny, nx) on the GPU
+    f.update(xyz, state)        # xyz: int32 (n, 3) as (x, y, z); state: uint8 (n,)
+    s = f.dense()               # int32 (nz, ny, nx): min(d_max^2, squared distance)
+    v = f.query(xyz)
+    c = ClearanceCost.apply(s, waypoints, h, margin)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["Field", "ClearanceCost", "clearance_cost", "lib", "EdtError", "LIB_PATH",
+           "batch_global"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libedt.so")
+
+EDT_OK, EDT_ERR_ARG, EDT_ERR_RANGE, EDT_ERR_CAPACITY, EDT_ERR_HIP, EDT_ERR_STATE = 0, -1, -2, -3, -4, -5
+STATUS = {0: "EDT_OK", -1: "EDT_ERR_ARG", -2: "EDT_ERR_RANGE", -3: "EDT_ERR_CAPACITY",
+          -4: "EDT_ERR_HIP", -5: "EDT_ERR_STATE"}
+
+
+class EdtError(RuntimeError):
+    def __init__(self, where, code):
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class EdtConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("d_max", ctypes.c_int32), ("max_blocks", ctypes.c_int64),
+                ("max_changes", ctypes.c_int64)]
+
+
+class EdtMap(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("d_occ", ctypes.c_void_p),
+                ("d_block_xyz", ctypes.c_void_p), ("d_block_occ", ctypes.c_void_p),
+                ("n_blocks", ctypes.c_int64)]
+
+
+class EdtStats(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int64), ("obstacle_blocks", ctypes.c_int64),
+                ("changed", ctypes.c_int64), ("added", ctypes.c_int64),
+                ("removed", ctypes.c_int64), ("seed_blocks", ctypes.c_int64),
+                ("raise_blocks", ctypes.c_int64), ("lower_blocks", ctypes.c_int64),
+                ("dirty_blocks", ctypes.c_int64), ("error", ctypes.c_int32),
+                ("d_max", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libedt.so (built in-tree); raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2105_04419_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+    sig = {
+        "edt_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "edt_workspace_bytes": ([ctypes.POINTER(EdtConfig)], i64),
+        "edt_create": ([ctypes.POINTER(EdtConfig), vp, i64, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "edt_destroy": ([vp], ctypes.c_int),
+        "edt_global": ([vp, ctypes.POINTER(EdtMap), vp], ctypes.c_int),
+        "edt_update": ([vp, vp, vp, i64, vp], ctypes.c_int),
+        "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "edt_read_dense": ([vp, vp, vp], ctypes.c_int),
+        "edt_read_occupancy": ([vp, vp, vp], ctypes.c_int),
+        "edt_get_stats": ([vp, ctypes.POINTER(EdtStats), vp], ctypes.c_int),
+        "edt_get_error": ([vp, vp], ctypes.c_int),
+        "edt_timing_begin": ([vp, i32], ctypes.c_int),
+        "edt_timing_read": ([vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)],
+                            ctypes.c_int),
+        "edt_clearance_fwd": ([vp, i32, i32, i32, f32, f32, vp, i64, i32, vp, vp], ctypes.c_int),
+        "edt_clearance_bwd": ([vp, i32, i32, i32, f32, f32, vp, i64, i32, vp, vp, vp],
+                              ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return _lib
+
+
+def _check(where, rc):
+    if rc != EDT_OK:
+        raise EdtError(where, rc)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+class Field:
+    """Distance field of one voxel map: a context of libedt plus its
+    workspace (a torch uint8 tensor that owns the device memory)."""
+
+    def __init__(self, shape, d_max: int, max_blocks: int = 0, max_changes: int = 0,
+                 device=None, stream=None):
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self.d_max = int(d_max)
+        self.D = self.d_max * self.d_max
+        self.cfg = EdtConfig(nx, ny, nz, self.d_max, int(max_blocks), int(max_changes))
+        L = lib()
+        nbytes = L.edt_workspace_bytes(ctypes.byref(self.cfg))
+        if nbytes < 0:
+            raise EdtError("edt_workspace_bytes", int(nbytes))
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check("edt_create", L.edt_create(ctypes.byref(self.cfg), _ptr(self.workspace),
+                                          int(nbytes), _stream(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().edt_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- transforms ---------------------------------------------------------
+    def global_(self, occ: torch.Tensor, stream=None):
+        """Global transform of a dense occupancy grid (nz, ny, nx) uint8."""
+        nx, ny, nz = self.shape
+        occ = _dev_tensor(occ, torch.uint8, (nz, ny, nx))
+        m = EdtMap(0, occ.data_ptr(), None, None, 0)
+        _check("edt_global", lib().edt_global(self._ctx, ctypes.byref(m), _stream(stream)))
+        self._keep = occ
+        return self
+
+    def global_blocks(self, block_xyz: torch.Tensor, block_occ: torch.Tensor, stream=None):
+        """Global transform of a leaf-block list: block_xyz int32 (n, 3) as
+        (bx, by, bz), block_occ uint8 (n, 512) with in-block index x+8y+64z."""
+        n = int(block_xyz.shape[0])
+        xyz = _dev_tensor(block_xyz, torch.int32, (n, 3))
+        data = _dev_tensor(block_occ, torch.uint8, (n, 512))
+        m = EdtMap(1, None, xyz.data_ptr() if n else None, data.data_ptr() if n else None, n)
+        _check("edt_global", lib().edt_global(self._ctx, ctypes.byref(m), _stream(stream)))
+        self._keep = (xyz, data)
+        return self
+
+    def update(self, xyz: torch.Tensor, state: torch.Tensor, stream=None):
+        """Incremental transform: set voxels xyz (int32 (n, 3)) to the
+        absolute occupancy `state` (uint8 (n,)); the last entry wins."""
+        n = int(xyz.shape[0])
+        if n == 0:
+            return self
+        xyz = _dev_tensor(xyz, torch.int32, (n, 3))
+        state = _dev_tensor(state, torch.uint8, (n,))
+        _check("edt_update", lib().edt_update(self._ctx, _ptr(xyz), _ptr(state), n,
+                                              _stream(stream)))
+        self._keep = (xyz, state)
+        return self
+
+    # -- reads ----------------------------------------------------------------
+    def query(self, xyz: torch.Tensor, stream=None) -> torch.Tensor:
+        n = int(xyz.shape[0])
+        out = torch.empty(n, dtype=torch.int32, device=self.device)
+        if n:
+            xyz = _dev_tensor(xyz, torch.int32, (n, 3))
+            _check("edt_query", lib().edt_query(self._ctx, _ptr(xyz), n, _ptr(out),
+                                                _stream(stream)))
+        return out
+
+    def dense(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+        out = _dev_tensor(out, torch.int32, (nz, ny, nx))
+        _check("edt_read_dense", lib().edt_read_dense(self._ctx, _ptr(out), _stream(stream)))
+        return out
+
+    def occupancy(self, stream=None) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        out = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+        _check("edt_read_occupancy", lib().edt_read_occupancy(self._ctx, _ptr(out), _stream(stream)))
+        return out
+
+    def stats(self, stream=None) -> dict:
+        st = EdtStats()
+        _check("edt_get_stats", lib().edt_get_stats(self._ctx, ctypes.byref(st), _stream(stream)))
+        return {k: getattr(st, k) for k, _ in EdtStats._fields_}
+
+    PHASES = ("ingest", "region", "items", "pass_x", "pass_y", "pass_z")
+
+    def timing_begin(self, n_calls: int):
+        """Record HIP events around the phases of the next n_calls global
+        transforms (profiling)."""
+        _check("edt_timing_begin", lib().edt_timing_begin(self._ctx, int(n_calls)))
+
+    def timing_read(self) -> dict:
+        """Mean phase durations (ms) over the recorded calls."""
+        ms = (ctypes.c_float * 6)()
+        n = ctypes.c_int32()
+        _check("edt_timing_read", lib().edt_timing_read(self._ctx, ms, ctypes.byref(n)))
+        d = {k: float(ms[i]) for i, k in enumerate(self.PHASES)}
+        d["calls"] = int(n.value)
+        return d
+
+    def error(self, stream=None) -> int:
+        """Device error word (0 or a negative status); reading clears it."""
+        return int(lib().edt_get_error(self._ctx, _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# clearance cost
+# ---------------------------------------------------------------------------
+def _clearance_args(s, wp):
+    if s.dim() != 3:
+        raise ValueError("field must be (nz, ny, nx)")
+    s = _dev_tensor(s, torch.int32)
+    wp = _dev_tensor(wp, torch.float32)
+    if wp.dim() != 3 or wp.shape[-1] != 3:
+        raise ValueError("waypoints must be (T, W, 3)")
+    nz, ny, nx = s.shape
+    return s, wp, nx, ny, nz
+
+
+class ClearanceCost(torch.autograd.Function):
+    """C[t] = sum_w max(0, margin - d(wp[t, w]))^2 with d the trilinear
+    interpolant of h*sqrt(s); forward and backward are HIP kernels."""
+
+    @staticmethod
+    def forward(ctx, s, wp, h: float, margin: float):
+        s, wp, nx, ny, nz = _clearance_args(s, wp)
+        T, W = int(wp.shape[0]), int(wp.shape[1])
+        cost = torch.empty(T, dtype=torch.float32, device=wp.device)
+        _check("edt_clearance_fwd", lib().edt_clearance_fwd(
+            _ptr(s), nx, ny, nz, float(h), float(margin), _ptr(wp), T, W, _ptr(cost), _stream()))
+        ctx.save_for_backward(s, wp)
+        ctx.h, ctx.margin = float(h), float(margin)
+        return cost
+
+    @staticmethod
+    def backward(ctx, gcost):
+        s, wp = ctx.saved_tensors
+        nz, ny, nx = s.shape
+        T, W = int(wp.shape[0]), int(wp.shape[1])
+        gcost = gcost.contiguous().to(torch.float32)
+        gwp = torch.empty_like(wp)
+        _check("edt_clearance_bwd", lib().edt_clearance_bwd(
+            _ptr(s), nx, ny, nz, ctx.h, ctx.margin, _ptr(wp), T, W, _ptr(gcost), _ptr(gwp),
+            _stream()))
+        return None, gwp, None, None
+
+
+def clearance_cost(s, wp, h: float = 0.2, margin: float = 1.0):
+    return ClearanceCost.apply(s, wp, h, margin)
+
+
+def batch_global(*args, **kwargs):
+    raise NotImplementedError("batched transform is not built yet")

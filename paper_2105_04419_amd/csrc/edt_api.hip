@@ -1,0 +1,447 @@
+// edt_api.hip -- host runtime and C ABI of libedt (see include/edt.h).
+//
+// The host side owns no device memory: edt_create carves the caller's
+// workspace into the block pool, the block hash table, work lists and the
+// update scratch; every entry point only enqueues kernels on the caller's
+// stream.  Kernels whose amount of work is only known on the device (block
+// counts, list lengths) run on fixed grids and read their counts from device
+// counters, so no call waits on the GPU except edt_get_stats / edt_get_error.
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "edt.h"
+
+// The kernels live in one translation unit with their launches.
+#include "edt_kernels.hip"
+
+using namespace edt;
+
+constexpr int NPHASE = 6;   // ingest, region, items, pass_x, pass_y, pass_z
+
+struct edt_ctx {
+    edt_config cfg;
+    Grid g;
+    hipEvent_t* ev;     // timing events, (NPHASE + 1) per recorded call
+    int ev_calls;       // calls to record
+    int ev_used;        // calls recorded so far
+    int cap;            // envelope ring capacity (entries per lane)
+    size_t env_lds;     // dynamic LDS bytes of the envelope passes
+    int64_t hcap;       // block hash capacity
+    int64_t ucap;       // update hash capacity
+    int64_t stats_host[C_N];
+};
+
+namespace {
+
+int64_t next_pow2(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+struct Layout {
+    int64_t max_blocks, max_changes, hcap, ucap;
+    int64_t off[32];
+    int64_t total;
+};
+
+enum {
+    O_HKEYS, O_HVALS, O_BKEY, O_OCC, O_DIST, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
+    O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
+    O_UKEYS, O_UVALS, O_UPOS, O_N
+};
+
+bool valid_cfg(const edt_config* c) {
+    if (!c) return false;
+    const int32_t lim = 1 << 20;
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1 || c->nx > lim || c->ny > lim || c->nz > lim)
+        return false;
+    if (c->d_max < 1 || c->d_max > 255) return false;
+    if (c->max_blocks < 0 || c->max_changes < 0) return false;
+    return true;
+}
+
+bool layout_of(const edt_config* c, Layout* L) {
+    if (!valid_cfg(c)) return false;
+    const int64_t nbx = (c->nx + 7) / 8, nby = (c->ny + 7) / 8, nbz = (c->nz + 7) / 8;
+    int64_t mb = c->max_blocks ? c->max_blocks : nbx * nby * nbz;
+    if (mb > nbx * nby * nbz) mb = nbx * nby * nbz;
+    if (mb > (1 << 22)) return false;                   // slot*512 stays in int32
+    const int64_t mc = c->max_changes ? c->max_changes : (1 << 20);
+    if (mc > (1 << 28)) return false;
+    L->max_blocks = mb;
+    L->max_changes = mc;
+    L->hcap = next_pow2(mb * 2 < 64 ? 64 : mb * 2);
+    L->ucap = next_pow2(mc * 2 < 64 ? 64 : mc * 2);
+    const int64_t sz[O_N] = {
+        L->hcap * 8, L->hcap * 4, mb * 8, mb * 64, mb * 512, mb * 1024, mb * 2048, mb * 4,
+        mb * 4, 64 * 4,
+        mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
+        L->ucap * 8, L->ucap * 4, mc * 4};
+    int64_t o = 0;
+    for (int i = 0; i < O_N; ++i) {
+        L->off[i] = o;
+        o += (sz[i] + 255) & ~(int64_t)255;
+    }
+    L->total = o;
+    return true;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// Event k of the current timed call (no-op unless timing is armed).
+inline void mark(edt_ctx* c, int k, hipStream_t st) {
+    if (c->ev && c->ev_used < c->ev_calls)
+        hipEventRecord(c->ev[c->ev_used * (NPHASE + 1) + k], st);
+}
+
+void free_events(edt_ctx* c) {
+    if (!c->ev) return;
+    for (int i = 0; i < c->ev_calls * (NPHASE + 1); ++i) hipEventDestroy(c->ev[i]);
+    free(c->ev);
+    c->ev = nullptr;
+    c->ev_calls = c->ev_used = 0;
+}
+
+inline int grid_for(int64_t work, int per, int cap) {
+    int64_t g = (work + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+#define LAUNCH_CHECK()                                   \
+    do {                                                 \
+        if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP; \
+    } while (0)
+
+edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
+    Grid& g = c->g;
+    const int mb = g.max_blocks;
+    const int tg = grid_for(mb, 256, 4096);
+    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 1,
+                       g.list_yi, (int)C_NYI);
+    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 2,
+                       g.list_zi, (int)C_NZI);
+    mark(c, 3, st);
+    hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
+                       (const int32_t*)nullptr, 0);
+    mark(c, 4, st);
+    hipLaunchKernelGGL(k_pass_y, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
+                       (const int32_t*)g.list_yi, (int)C_NYI, 0u, c->cap);
+    mark(c, 5, st);
+    hipLaunchKernelGGL(k_pass_z, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
+                       (const int32_t*)g.list_zi, (int)C_NZI, 0u, c->cap);
+    mark(c, 6, st);
+    if (c->ev && c->ev_used < c->ev_calls) c->ev_used++;
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status dilate_region(edt_ctx* c, hipStream_t st) {
+    Grid& g = c->g;
+    const int tg = grid_for((int64_t)g.max_blocks * 2 * g.R, 256, 4096);
+    for (int axis = 0; axis < 3; ++axis) {
+        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP);
+        hipLaunchKernelGGL(k_dilate_axis, dim3(tg), dim3(256), 0, st, g, axis);
+    }
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* edt_status_str(int s) {
+    switch (s) {
+        case EDT_OK: return "EDT_OK";
+        case EDT_ERR_ARG: return "EDT_ERR_ARG";
+        case EDT_ERR_RANGE: return "EDT_ERR_RANGE";
+        case EDT_ERR_CAPACITY: return "EDT_ERR_CAPACITY";
+        case EDT_ERR_HIP: return "EDT_ERR_HIP";
+        case EDT_ERR_STATE: return "EDT_ERR_STATE";
+        default: return "EDT_UNKNOWN";
+    }
+}
+
+int64_t edt_workspace_bytes(const edt_config* cfg) {
+    Layout L;
+    if (!layout_of(cfg, &L)) return EDT_ERR_ARG;
+    return L.total;
+}
+
+edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void* stream,
+                      edt_ctx** out) {
+    if (!out) return EDT_ERR_ARG;
+    *out = nullptr;
+    Layout L;
+    if (!layout_of(cfg, &L) || !d_ws) return EDT_ERR_ARG;
+    if (((uintptr_t)d_ws & 255) != 0) return EDT_ERR_ARG;
+    if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
+    edt_ctx* c = (edt_ctx*)calloc(1, sizeof(edt_ctx));
+    if (!c) return EDT_ERR_CAPACITY;
+    c->cfg = *cfg;
+    c->hcap = L.hcap;
+    c->ucap = L.ucap;
+    char* b = (char*)d_ws;
+    Grid& g = c->g;
+    g.nx = cfg->nx; g.ny = cfg->ny; g.nz = cfg->nz;
+    g.nbx = (cfg->nx + 7) / 8; g.nby = (cfg->ny + 7) / 8; g.nbz = (cfg->nz + 7) / 8;
+    g.dmax = cfg->d_max;
+    g.D = cfg->d_max * cfg->d_max;
+    g.R = (cfg->d_max + 7) / 8;
+    g.max_blocks = (int)L.max_blocks;
+    g.hmask = (uint32_t)(L.hcap - 1);
+    g.umask = (uint32_t)(L.ucap - 1);
+    g.max_changes = (int)L.max_changes;
+    g.hkeys = (unsigned long long*)(b + L.off[O_HKEYS]);
+    g.hvals = (int32_t*)(b + L.off[O_HVALS]);
+    g.bkey = (unsigned long long*)(b + L.off[O_BKEY]);
+    g.occ = (uint32_t*)(b + L.off[O_OCC]);
+    g.dist = (uint8_t*)(b + L.off[O_DIST]);
+    g.g2 = (uint16_t*)(b + L.off[O_G2]);
+    g.s = (int32_t*)(b + L.off[O_S]);
+    g.bmax = (int32_t*)(b + L.off[O_BMAX]);
+    g.flags = (uint32_t*)(b + L.off[O_FLAGS]);
+    g.cnt = (int32_t*)(b + L.off[O_CNT]);
+    g.list_yi = (int32_t*)(b + L.off[O_YI]);
+    g.list_zi = (int32_t*)(b + L.off[O_ZI]);
+    g.list_seed = (int32_t*)(b + L.off[O_SEED]);
+    g.list_dirty = (int32_t*)(b + L.off[O_DIRTY]);
+    g.list_xs = (int32_t*)(b + L.off[O_XS]);
+    g.list_ys = (int32_t*)(b + L.off[O_YS]);
+    g.list_newdil = (int32_t*)(b + L.off[O_NEWDIL]);
+    g.chg_add = (uint32_t*)(b + L.off[O_CHGA]);
+    g.chg_rem = (uint32_t*)(b + L.off[O_CHGR]);
+    g.seed_box = (int32_t*)(b + L.off[O_SEEDBOX]);
+    g.ukeys = (unsigned long long*)(b + L.off[O_UKEYS]);
+    g.uvals = (int32_t*)(b + L.off[O_UVALS]);
+    g.upos = (int32_t*)(b + L.off[O_UPOS]);
+    c->cap = 2 * g.dmax + 10;
+    c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
+    // the envelope ring must fit the device's LDS per workgroup
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+        free(c);
+        return EDT_ERR_HIP;
+    }
+    if ((int64_t)c->env_lds > lds_max) {
+        free(c);
+        return EDT_ERR_ARG;
+    }
+    if (c->env_lds > 65536) {
+        if (hipFuncSetAttribute((const void*)k_pass_y, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)c->env_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_pass_z, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)c->env_lds) != hipSuccess) {
+            free(c);
+            return EDT_ERR_HIP;
+        }
+    }
+
+    hipStream_t st = S(stream);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.hcap, 256, 4096)), dim3(256), 0, st, g.hkeys,
+                       L.hcap, KEY_EMPTY);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.ukeys,
+                       L.ucap, KEY_EMPTY);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
+                       L.ucap, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt, (int64_t)64, 0);
+    if (hipGetLastError() != hipSuccess) {
+        free(c);
+        return EDT_ERR_HIP;
+    }
+    *out = c;
+    return EDT_OK;
+}
+
+edt_status edt_destroy(edt_ctx* ctx) {
+    if (!ctx) return EDT_ERR_ARG;
+    free_events(ctx);
+    free(ctx);
+    return EDT_OK;
+}
+
+edt_status edt_timing_begin(edt_ctx* c, int32_t n_calls) {
+    if (!c || n_calls < 0 || n_calls > 100000) return EDT_ERR_ARG;
+    free_events(c);
+    if (n_calls == 0) return EDT_OK;
+    const int ne = n_calls * (NPHASE + 1);
+    c->ev = (hipEvent_t*)calloc((size_t)ne, sizeof(hipEvent_t));
+    if (!c->ev) return EDT_ERR_CAPACITY;
+    for (int i = 0; i < ne; ++i) {
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) hipEventDestroy(c->ev[j]);
+            free(c->ev);
+            c->ev = nullptr;
+            return EDT_ERR_HIP;
+        }
+    }
+    c->ev_calls = n_calls;
+    c->ev_used = 0;
+    return EDT_OK;
+}
+
+edt_status edt_timing_read(edt_ctx* c, float* ms, int32_t* n_recorded) {
+    if (!c || !ms || !n_recorded) return EDT_ERR_ARG;
+    for (int k = 0; k < NPHASE; ++k) ms[k] = 0.0f;
+    *n_recorded = c->ev_used;
+    for (int i = 0; i < c->ev_used; ++i) {
+        hipEvent_t* e = c->ev + i * (NPHASE + 1);
+        if (hipEventSynchronize(e[NPHASE]) != hipSuccess) return EDT_ERR_HIP;
+        for (int k = 0; k < NPHASE; ++k) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess) return EDT_ERR_HIP;
+            ms[k] += t / (float)c->ev_used;
+        }
+    }
+    return EDT_OK;
+}
+
+edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
+    if (!c || !map) return EDT_ERR_ARG;
+    Grid& g = c->g;
+    hipStream_t st = S(stream);
+    if (map->kind == EDT_MAP_DENSE) {
+        if (!map->d_occ) return EDT_ERR_ARG;
+    } else if (map->kind == EDT_MAP_BLOCKS) {
+        if (map->n_blocks < 0) return EDT_ERR_ARG;
+        if (map->n_blocks > 0 && (!map->d_block_xyz || !map->d_block_occ)) return EDT_ERR_ARG;
+    } else {
+        return EDT_ERR_ARG;
+    }
+    mark(c, 0, st);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c->hcap, 256, 4096)), dim3(256), 0, st, g.hkeys,
+                       c->hcap, KEY_EMPTY);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, g);
+    if (map->kind == EDT_MAP_DENSE) {
+        hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
+                           map->d_occ);
+        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
+        mark(c, 1, st);
+        edt_status r = dilate_region(c, st);
+        if (r) return r;
+        hipLaunchKernelGGL(k_zero_occ, dim3(grid_for((int64_t)g.max_blocks * 16, 256, 4096)),
+                           dim3(256), 0, st, g, (int)C_SNAP2);
+        mark(c, 2, st);
+    } else {
+        const int64_t n = map->n_blocks;
+        if (n > 0)
+            hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st,
+                               g, map->d_block_xyz, map->d_block_occ, n);
+        mark(c, 1, st);
+        edt_status r = dilate_region(c, st);
+        if (r) return r;
+        hipLaunchKernelGGL(k_zero_occ, dim3(grid_for((int64_t)g.max_blocks * 16, 256, 4096)),
+                           dim3(256), 0, st, g, -1);
+        if (n > 0)
+            hipLaunchKernelGGL(k_ingest_blocks_write, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st,
+                               g, map->d_block_xyz, map->d_block_occ, n);
+        mark(c, 2, st);
+    }
+    LAUNCH_CHECK();
+    return run_passes_global(c, st);
+}
+
+edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, int64_t n,
+                      void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (n == 0) return EDT_OK;
+    if (!d_xyz || !d_state) return EDT_ERR_ARG;
+    if (n > c->g.max_changes) return EDT_ERR_CAPACITY;
+    Grid& g = c->g;
+    hipStream_t st = S(stream);
+    const int mb = g.max_blocks;
+    const int tn = grid_for(n, 256, 4096);
+    const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
+    hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n);
+    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
+    hipLaunchKernelGGL(k_init_new, dim3(2048), dim3(64), 0, st, g, (int)C_SNAP);
+    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
+    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
+    hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_init_new, dim3(2048), dim3(64), 0, st, g, (int)C_SNAP2);
+    hipLaunchKernelGGL(k_seed_box, dim3(grid_for(n, 1, 4096)), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_upd_mark, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 8192)), dim3(64), 0, st, g,
+                       (const int32_t*)g.list_xs, (int)C_NXS);
+    const int tg = grid_for(mb, 256, 4096);
+    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_ys,
+                       (int)C_NYS, (uint32_t)F_YS, 1, g.list_yi, (int)C_NYI);
+    hipLaunchKernelGGL(k_pass_y, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
+                       (const int32_t*)g.list_yi, (int)C_NYI, (uint32_t)F_YS, c->cap);
+    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_dirty,
+                       (int)C_NDIRTY, (uint32_t)F_DIRTY, 2, g.list_zi, (int)C_NZI);
+    hipLaunchKernelGGL(k_pass_z, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
+                       (const int32_t*)g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY, c->cap);
+    hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,
+                       g, n);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_query(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_t* d_out, void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (n == 0) return EDT_OK;
+    if (!d_xyz || !d_out) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_query, dim3(grid_for(n, 256, 8192)), dim3(256), 0, S(stream), c->g, d_xyz,
+                       n, d_out);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_read_dense(edt_ctx* c, int32_t* d_out, void* stream) {
+    if (!c || !d_out) return EDT_ERR_ARG;
+    const Grid& g = c->g;
+    hipLaunchKernelGGL(k_read_dense, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_out);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_read_occupancy(edt_ctx* c, uint8_t* d_occ, void* stream) {
+    if (!c || !d_occ) return EDT_ERR_ARG;
+    const Grid& g = c->g;
+    hipLaunchKernelGGL(k_read_occ, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_occ);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_get_stats(edt_ctx* c, edt_stats* o, void* stream) {
+    if (!c || !o) return EDT_ERR_ARG;
+    int32_t h[C_N];
+    hipStream_t st = S(stream);
+    if (hipMemcpyAsync(h, c->g.cnt, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return EDT_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return EDT_ERR_HIP;
+    memset(o, 0, sizeof(*o));
+    o->blocks = h[C_NBLK] < c->g.max_blocks ? h[C_NBLK] : c->g.max_blocks;
+    o->obstacle_blocks = h[C_NDIL];
+    o->added = h[C_NADD];
+    o->removed = h[C_NREM];
+    o->changed = (int64_t)h[C_NADD] + h[C_NREM];
+    o->seed_blocks = h[C_NSEED];
+    o->raise_blocks = h[C_NRAISE];
+    o->lower_blocks = h[C_NLOWER];
+    o->dirty_blocks = h[C_NDIRTY];
+    o->error = h[C_ERR];
+    o->d_max = c->g.dmax;
+    return EDT_OK;
+}
+
+edt_status edt_get_error(edt_ctx* c, void* stream) {
+    if (!c) return EDT_ERR_ARG;
+    int32_t e = 0;
+    hipStream_t st = S(stream);
+    if (hipMemcpyAsync(&e, c->g.cnt + C_ERR, sizeof(e), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return EDT_ERR_HIP;
+    hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(1), 0, st, c->g);
+    if (hipStreamSynchronize(st) != hipSuccess) return EDT_ERR_HIP;
+    return (edt_status)e;
+}
+
+}  // extern "C"

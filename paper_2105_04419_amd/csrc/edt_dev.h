@@ -1,0 +1,168 @@
+// edt_dev.h -- device-side data structures of libedt (gfx950).
+//
+// Storage: a pool of 8x8x8 leaf blocks addressed through an open-addressing
+// hash table keyed by block coordinates.  This replaces the paper's VDB
+// B+-tree (section IV-A): both give O(1) access to sparse leaves and treat
+// every absent leaf as the background value D (Algorithm 1, Initialize).
+//
+// Per pool slot (one leaf block):
+//   occ    512 occupancy bits, 16 x uint32; byte (y + 8z) holds row (y,z),
+//          bit x = voxel x of that row.
+//   dist   uint8 per voxel, layout x + 8z + 64y: distance along x to the
+//          nearest obstacle of the same row, min(.,255); values >= d_max mean
+//          "none within the transform radius".
+//   g2     uint16 per voxel, layout x + 8y + 64z: min over dy of
+//          dist(x, y+dy, z)^2 + dy^2, clamped to D.
+//   s      int32 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
+//   bmax   int32: max of s over the block (pruning bound for updates).
+//   flags  uint32: state bits (F_*).
+// Blocks exist exactly where s can differ from D: blocks that held an
+// obstacle at some point and all blocks within R = ceil(d_max/8) blocks of
+// them (Chebyshev).  A voxel outside that region has no obstacle within
+// distance 8R >= d_max along at least one axis, so its value is D.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace edt {
+
+constexpr unsigned long long KEY_EMPTY = ~0ull;
+constexpr int LRUN = 16;        // max output blocks per y / z work item
+constexpr int32_t FINF = 1 << 28;
+
+enum : uint32_t {
+    F_DILATED = 1u,  // block's R-neighbourhood is in the pool
+    F_SEED = 2u,     // block holds a changed voxel in the current update
+    F_DIRTY = 4u,    // block's values are recomputed in the current update
+    F_XS = 8u,       // dist recomputed in the current update
+    F_YS = 16u,      // g2 recomputed in the current update
+    F_RAISE = 32u,   // marked by the raise front
+    F_LOWER = 64u,   // marked by the lower front
+};
+
+// device counters (int32 slots of the counter array)
+enum {
+    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_SNAP, C_SNAP2,
+    C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
+    C_NXS, C_NYS, C_NNEWDIL, C_N
+};
+
+struct Grid {
+    int nx, ny, nz;          // extent (voxels)
+    int nbx, nby, nbz;       // extent (blocks)
+    int dmax, D, R;          // radius, D = dmax^2, R = ceil(dmax / 8)
+    int max_blocks;
+    uint32_t hmask;          // hash capacity - 1
+    uint32_t umask;          // update-dedupe hash capacity - 1
+    int max_changes;
+    unsigned long long* hkeys;
+    int32_t* hvals;
+    unsigned long long* bkey;
+    uint32_t* occ;
+    uint8_t* dist;
+    uint16_t* g2;
+    int32_t* s;
+    int32_t* bmax;
+    uint32_t* flags;
+    int32_t* cnt;
+    int32_t* list_yi;        // y work items (start slots)
+    int32_t* list_zi;        // z work items
+    int32_t* list_seed;      // update: seed blocks
+    int32_t* list_dirty;     // update: dirty blocks
+    int32_t* list_xs;        // update: blocks whose dist is recomputed
+    int32_t* list_ys;        // update: blocks whose g2 is recomputed
+    int32_t* list_newdil;    // update: blocks that became obstacle blocks
+    uint32_t* chg_add;       // [slot][16] voxels added in this update
+    uint32_t* chg_rem;       // [slot][16] voxels removed in this update
+    int32_t* seed_box;       // [seed][2] packed bounding boxes (add, rem)
+    unsigned long long* ukeys;
+    int32_t* uvals;
+    int32_t* upos;
+};
+
+__host__ __device__ inline unsigned long long pack_key(int bx, int by, int bz) {
+    return (unsigned long long)(uint32_t)bx | ((unsigned long long)(uint32_t)by << 21) |
+           ((unsigned long long)(uint32_t)bz << 42);
+}
+__device__ inline void unpack_key(unsigned long long k, int& bx, int& by, int& bz) {
+    bx = (int)(k & 0x1fffff);
+    by = (int)((k >> 21) & 0x1fffff);
+    bz = (int)((k >> 42) & 0x1fffff);
+}
+
+__device__ inline uint32_t hash_of(unsigned long long k, uint32_t mask) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return (uint32_t)k & mask;
+}
+
+// Slot of block key `key`, or -1.  Probes are bounded by the capacity.
+__device__ inline int32_t hfind(const unsigned long long* keys, const int32_t* vals,
+                                uint32_t mask, unsigned long long key) {
+    uint32_t h = hash_of(key, mask);
+    for (uint32_t i = 0; i <= mask; ++i) {
+        unsigned long long k = keys[h];
+        if (k == key) return vals[h];
+        if (k == KEY_EMPTY) return -1;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+__device__ inline int32_t find_block(const Grid& g, int bx, int by, int bz) {
+    if (bx < 0 || by < 0 || bz < 0 || bx >= g.nbx || by >= g.nby || bz >= g.nbz) return -1;
+    return hfind(g.hkeys, g.hvals, g.hmask, pack_key(bx, by, bz));
+}
+
+// Find-or-insert: returns the table position, or -1 when the table is full.
+// *created is true for the one thread whose CAS placed the key.
+__device__ inline int32_t hinsert(unsigned long long* keys, uint32_t mask,
+                                  unsigned long long key, bool* created) {
+    uint32_t h = hash_of(key, mask);
+    for (uint32_t i = 0; i <= mask; ++i) {
+        unsigned long long k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) { *created = false; return (int32_t)h; }
+        if (k == KEY_EMPTY) {
+            unsigned long long old = atomicCAS(&keys[h], KEY_EMPTY, key);
+            if (old == KEY_EMPTY) { *created = true; return (int32_t)h; }
+            if (old == key) { *created = false; return (int32_t)h; }
+        }
+        h = (h + 1) & mask;
+    }
+    *created = false;
+    return -1;
+}
+
+__device__ inline void set_error(const Grid& g, int code) {
+    atomicCAS(&g.cnt[C_ERR], 0, code);
+}
+
+// Wave-aggregated append of `pred` lanes to list[] (ballot + mbcnt + one
+// atomicAdd per wave).  Returns the lane's index or -1.
+__device__ inline int wave_append(bool pred, int32_t* counter) {
+    unsigned long long m = __ballot(pred);
+    if (m == 0) return -1;
+    int lane = __lane_id();
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    unsigned int lo = __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0);
+    unsigned int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), lo);
+    return pred ? base + (int)rank : -1;
+}
+
+__device__ inline int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+}  // namespace edt

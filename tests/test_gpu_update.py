@@ -1,0 +1,198 @@
+"""Incremental transform on the GPU: after every update the field equals the
+oracle of the new occupancy and a fresh GPU global transform, bit for bit
+(Algorithm 1's SetObstacle / RemoveObstacle semantics: absolute target
+states, re-setting or re-clearing is a no-op, the last entry of a voxel
+wins)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from workloads.scans import ScanSim, ellipse_path, tunnel_path
+from paper_2105_04419_amd import EdtError, Field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    oracle.build(force=False)
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def apply_cpu(occ, xyz, state):
+    occ = occ.copy()
+    for (x, y, z), s in zip(xyz, state):     # in order: last entry wins
+        occ[z, y, x] = 1 if s else 0
+    return occ
+
+
+def check(f, occ, dmax, what):
+    got = f.dense().cpu().numpy()
+    ref = oracle.edt_separable(occ, dmax)
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        z, y, x = bad[0]
+        raise AssertionError(f"{what}: {len(bad)} mismatches, first at ({x},{y},{z}) "
+                             f"gpu={got[z, y, x]} oracle={ref[z, y, x]}")
+    assert np.array_equal(f.occupancy().cpu().numpy(), (occ != 0).astype(np.uint8)), what
+
+
+def random_batch(rng, occ, n, p_add=0.5):
+    nz, ny, nx = occ.shape
+    occupied = np.argwhere(occ)
+    k_rem = int(n * (1 - p_add))
+    picks = []
+    if len(occupied) and k_rem:
+        sel = occupied[rng.integers(0, len(occupied), k_rem)][:, ::-1]
+        picks.append(np.concatenate([sel, np.zeros((k_rem, 1), int)], 1))
+    k_add = n - k_rem
+    addp = np.stack([rng.integers(0, nx, k_add), rng.integers(0, ny, k_add),
+                     rng.integers(0, nz, k_add), np.ones(k_add, int)], 1)
+    picks.append(addp)
+    b = np.concatenate(picks)
+    rng.shuffle(b)
+    return b[:, :3].astype(np.int32), b[:, 3].astype(np.uint8)
+
+
+@pytest.mark.parametrize("shape,p,dmax", [
+    ((29, 37, 50), 0.002, 5), ((24, 40, 48), 0.001, 12), ((32, 32, 32), 0.0005, 20),
+    ((16, 24, 96), 0.003, 32),
+])
+def test_random_update_sequences(shape, p, dmax):
+    rng = np.random.default_rng(abs(hash((shape, dmax))) % (1 << 32))
+    occ = (rng.random(shape) < p).astype(np.uint8)
+    nz, ny, nx = shape
+    f = Field((nx, ny, nz), dmax)
+    f.global_(cu(occ))
+    for step in range(12):
+        n = int(rng.choice([1, 3, 17, 200, 1500]))
+        xyz, st = random_batch(rng, occ, n, p_add=float(rng.choice([0.0, 0.3, 0.7, 1.0])))
+        # duplicates with conflicting states: the last one must win
+        if n > 3:
+            xyz = np.concatenate([xyz, xyz[:3]])
+            st = np.concatenate([st, 1 - st[:3]]).astype(np.uint8)
+        occ = apply_cpu(occ, xyz, st)
+        f.update(cu(xyz), cu(st))
+        check(f, occ, dmax, f"{shape} d={dmax} step {step} n={len(xyz)}")
+        assert f.error() == 0
+    g = Field((nx, ny, nz), dmax)
+    g.global_(cu(occ))
+    assert np.array_equal(g.dense().cpu().numpy(), f.dense().cpu().numpy())
+
+
+def test_noop_and_idempotence():
+    occ = workloads.random_grid(1, (32, 40, 48), 0.002)
+    f = Field((48, 40, 32), 10)
+    f.global_(cu(occ))
+    before = f.dense().cpu().numpy()
+    occupied = np.argwhere(occ)[:50][:, ::-1].astype(np.int32)
+    f.update(cu(occupied), cu(np.ones(len(occupied), np.uint8)))     # already set
+    st = f.stats()
+    assert st["changed"] == 0 and st["dirty_blocks"] == 0
+    assert np.array_equal(f.dense().cpu().numpy(), before)
+    xyz = np.array([[5, 6, 7], [40, 30, 20]], np.int32)
+    f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
+    a = f.dense().cpu().numpy()
+    f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
+    assert f.stats()["changed"] == 0
+    assert np.array_equal(f.dense().cpu().numpy(), a)
+
+
+def test_add_then_remove_round_trip():
+    occ = workloads.random_grid(2, (24, 48, 40), 0.001)
+    f = Field((40, 48, 24), 16)
+    f.global_(cu(occ))
+    before = f.dense().cpu().numpy()
+    rng = np.random.default_rng(3)
+    free = np.argwhere(occ == 0)
+    xyz = free[rng.choice(len(free), 300, replace=False)][:, ::-1].astype(np.int32)
+    f.update(cu(xyz), cu(np.ones(300, np.uint8)))
+    f.update(cu(xyz), cu(np.zeros(300, np.uint8)))
+    assert np.array_equal(f.dense().cpu().numpy(), before)
+
+
+def test_split_batch_equals_whole():
+    occ = workloads.random_grid(4, (32, 32, 40), 0.002)
+    rng = np.random.default_rng(5)
+    xyz, st = random_batch(rng, occ, 600)
+    a = Field((40, 32, 32), 14)
+    a.global_(cu(occ))
+    a.update(cu(xyz), cu(st))
+    b = Field((40, 32, 32), 14)
+    b.global_(cu(occ))
+    b.update(cu(xyz[:250]), cu(st[:250]))
+    b.update(cu(xyz[250:]), cu(st[250:]))
+    assert np.array_equal(a.dense().cpu().numpy(), b.dense().cpu().numpy())
+
+
+def test_far_additions_grow_region_and_remove_all():
+    nx, ny, nz = 96, 80, 40
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    f = Field((nx, ny, nz), 9)
+    f.global_(cu(occ))
+    xyz = np.array([[0, 0, 0], [95, 79, 39], [50, 40, 20], [50, 41, 20]], np.int32)
+    f.update(cu(xyz), cu(np.ones(4, np.uint8)))
+    occ = apply_cpu(occ, xyz, np.ones(4))
+    check(f, occ, 9, "far adds")
+    f.update(cu(xyz), cu(np.zeros(4, np.uint8)))
+    assert (f.dense().cpu().numpy() == 81).all()
+
+
+def test_out_of_range_entry_cancels_call():
+    occ = workloads.random_grid(6, (16, 16, 16), 0.01)
+    f = Field((16, 16, 16), 6)
+    f.global_(cu(occ))
+    before = f.dense().cpu().numpy()
+    xyz = np.array([[1, 1, 1], [16, 0, 0]], np.int32)
+    f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
+    assert f.error() == -2
+    assert np.array_equal(f.dense().cpu().numpy(), before)
+    xyz = np.array([[1, 1, 1], [0, -1, 0]], np.int32)
+    f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
+    assert f.error() == -2
+    assert np.array_equal(f.dense().cpu().numpy(), before)
+
+
+def test_change_capacity_is_checked_on_host():
+    f = Field((16, 16, 16), 6, max_changes=8)
+    f.global_(cu(np.zeros((16, 16, 16), np.uint8)))
+    with pytest.raises(EdtError):
+        f.update(cu(np.zeros((9, 3), np.int32)), cu(np.ones(9, np.uint8)))
+
+
+def test_scans_on_dense_boxes_map():
+    """Range scans along a loop through the 64x64x32 boxes map (d_max 20)."""
+    occ = workloads.dense_boxes(0)
+    sim = ScanSim(occ, ellipse_path(64, 64, 32), seed=0)
+    f = Field((64, 64, 32), 20)
+    f.global_(cu(occ))
+    for t in range(30):
+        xyz, st, _ = sim.step()
+        f.update(cu(xyz), cu(st))
+        check(f, sim.map, 20, f"scan {t}")
+
+
+def test_scans_on_tunnel_map():
+    """Range scans along the tunnel centerlines (1024x1024x128, d_max 32):
+    incremental == global == oracle at several scans."""
+    occ = workloads.tunnels(0)
+    sim = ScanSim(occ, tunnel_path(0), seed=0)
+    xyz0, data0 = workloads.dense_to_blocks(occ)
+    f = Field((1024, 1024, 128), 32)
+    f.global_blocks(cu(xyz0), cu(data0))
+    g = Field((1024, 1024, 128), 32)
+    for t in range(12):
+        xyz, st, _ = sim.step()
+        f.update(cu(xyz), cu(st))
+        if t in (0, 1, 5, 11):
+            g.global_(cu(sim.map))
+            a = f.dense().cpu().numpy()
+            assert np.array_equal(a, g.dense().cpu().numpy()), f"scan {t}: incremental != global"
+            assert np.array_equal(a, oracle.edt_separable(sim.map, 32)), f"scan {t}"
+    assert f.error() == 0
