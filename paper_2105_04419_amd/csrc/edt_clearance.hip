@@ -35,9 +35,10 @@ __device__ inline Tri trilinear(const int32_t* __restrict__ s, int nx, int ny, i
                                 float px, float py, float pz) {
     int ix, iy, iz;
     float tx, ty, tz, lx, ly, lz;
-    axis_cell(px / h, nx, ix, tx, lx);
-    axis_cell(py / h, ny, iy, ty, ly);
-    axis_cell(pz / h, nz, iz, tz, lz);
+    // correctly rounded fp32 quotients: the cell index is decided in fp32
+    axis_cell(__fdiv_rn(px, h), nx, ix, tx, lx);
+    axis_cell(__fdiv_rn(py, h), ny, iy, ty, ly);
+    axis_cell(__fdiv_rn(pz, h), nz, iz, tz, lz);
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t b = ix + sy * iy + sz * iz;
     const float c000 = metric(s, b, h), c001 = metric(s, b + 1, h);
