@@ -49,7 +49,7 @@ struct Layout {
 enum {
     O_HKEYS, O_HVALS, O_BKEY, O_OCC, O_DIST, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -78,7 +78,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         L->hcap * 8, L->hcap * 4, mb * 8, mb * 64, mb * 512, mb * 1024, mb * 2048, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
-        L->ucap * 8, L->ucap * 4, mc * 4};
+        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -93,12 +93,12 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 // Event k of the current timed call (no-op unless timing is armed).
 inline void mark(edt_ctx* c, int k, hipStream_t st) {
     if (c->ev && c->ev_used < c->ev_calls)
-        hipEventRecord(c->ev[c->ev_used * (NPHASE + 1) + k], st);
+        (void)hipEventRecord(c->ev[c->ev_used * (NPHASE + 1) + k], st);
 }
 
 void free_events(edt_ctx* c) {
     if (!c->ev) return;
-    for (int i = 0; i < c->ev_calls * (NPHASE + 1); ++i) hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < c->ev_calls * (NPHASE + 1); ++i) (void)hipEventDestroy(c->ev[i]);
     free(c->ev);
     c->ev = nullptr;
     c->ev_calls = c->ev_used = 0;
@@ -120,10 +120,7 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
     const int mb = g.max_blocks;
     const int tg = grid_for(mb, 256, 4096);
-    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 1,
-                       g.list_yi, (int)C_NYI);
-    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 2,
-                       g.list_zi, (int)C_NZI);
+    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 3);
     mark(c, 3, st);
     hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
                        (const int32_t*)nullptr, 0);
@@ -141,11 +138,11 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
 
 edt_status dilate_region(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
-    const int tg = grid_for((int64_t)g.max_blocks * 2 * g.R, 256, 4096);
-    for (int axis = 0; axis < 3; ++axis) {
-        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP);
+    // few workgroups: each kernel's last workgroup leaves the final block
+    // count in C_SNAP (one counter atomic per workgroup)
+    const int tg = grid_for((int64_t)g.max_blocks * 2 * g.R, 256, 512);
+    for (int axis = 0; axis < 3; ++axis)
         hipLaunchKernelGGL(k_dilate_axis, dim3(tg), dim3(256), 0, st, g, axis);
-    }
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -219,7 +216,8 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.ukeys = (unsigned long long*)(b + L.off[O_UKEYS]);
     g.uvals = (int32_t*)(b + L.off[O_UVALS]);
     g.upos = (int32_t*)(b + L.off[O_UPOS]);
-    c->cap = 2 * g.dmax + 10;
+    g.dummy = (uint32_t*)(b + L.off[O_DUMMY]);
+    c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
     int dev = 0, lds_max = 0;
@@ -275,7 +273,7 @@ edt_status edt_timing_begin(edt_ctx* c, int32_t n_calls) {
     if (!c->ev) return EDT_ERR_CAPACITY;
     for (int i = 0; i < ne; ++i) {
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
-            for (int j = 0; j < i; ++j) hipEventDestroy(c->ev[j]);
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
             free(c->ev);
             c->ev = nullptr;
             return EDT_ERR_HIP;
@@ -315,12 +313,12 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         return EDT_ERR_ARG;
     }
     mark(c, 0, st);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c->hcap, 256, 4096)), dim3(256), 0, st, g.hkeys,
-                       c->hcap, KEY_EMPTY);
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->hcap, 256, 4096)), dim3(256), 0, st, g,
+                       c->hcap);
     if (map->kind == EDT_MAP_DENSE) {
         hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
                            map->d_occ);
+        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP);
         hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
@@ -330,9 +328,9 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         mark(c, 2, st);
     } else {
         const int64_t n = map->n_blocks;
-        if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st,
-                               g, map->d_block_xyz, map->d_block_occ, n);
+        // runs even for n == 0: its exit records the block count for the region growth
+        hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 64, 4096)), dim3(64), 0, st, g,
+                           map->d_block_xyz, map->d_block_occ, n);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;
@@ -372,11 +370,11 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
                        (const int32_t*)g.list_xs, (int)C_NXS);
     const int tg = grid_for(mb, 256, 4096);
     hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_ys,
-                       (int)C_NYS, (uint32_t)F_YS, 1, g.list_yi, (int)C_NYI);
+                       (int)C_NYS, (uint32_t)F_YS, 1);
     hipLaunchKernelGGL(k_pass_y, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
                        (const int32_t*)g.list_yi, (int)C_NYI, (uint32_t)F_YS, c->cap);
     hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_dirty,
-                       (int)C_NDIRTY, (uint32_t)F_DIRTY, 2, g.list_zi, (int)C_NZI);
+                       (int)C_NDIRTY, (uint32_t)F_DIRTY, 2);
     hipLaunchKernelGGL(k_pass_z, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
                        (const int32_t*)g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY, c->cap);
     hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,

@@ -8,11 +8,12 @@
 // Per pool slot (one leaf block):
 //   occ    512 occupancy bits, 16 x uint32; byte (y + 8z) holds row (y,z),
 //          bit x = voxel x of that row.
-//   dist   uint8 per voxel, layout x + 8z + 64y: distance along x to the
-//          nearest obstacle of the same row, min(.,255); values >= d_max mean
-//          "none within the transform radius".
-//   g2     uint16 per voxel, layout x + 8y + 64z: min over dy of
-//          dist(x, y+dy, z)^2 + dy^2, clamped to D.
+//   dist   uint8 per voxel, layout (x + 8z) * 8 + y: distance along x to
+//          the nearest obstacle of the same row, min(.,255); values >= d_max
+//          mean "none within the transform radius".  The 8 values of one
+//          y-column are contiguous (one load per block in pass y).
+//   g2     uint16 per voxel, layout (x + 8y) * 8 + z: min over dy of
+//          dist(x, y+dy, z)^2 + dy^2, clamped to D (contiguous z-columns).
 //   s      int32 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
 //   bmax   int32: max of s over the block (pruning bound for updates).
 //   flags  uint32: state bits (F_*).
@@ -44,7 +45,7 @@ enum : uint32_t {
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_SNAP, C_SNAP2,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
-    C_NXS, C_NYS, C_NNEWDIL, C_N
+    C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_N
 };
 
 struct Grid {
@@ -78,6 +79,7 @@ struct Grid {
     unsigned long long* ukeys;
     int32_t* uvals;
     int32_t* upos;
+    uint32_t* dummy;         // 256 x 64 words of write-only scratch rows
 };
 
 __host__ __device__ inline unsigned long long pack_key(int bx, int by, int bz) {

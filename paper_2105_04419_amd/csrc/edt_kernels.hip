@@ -38,28 +38,51 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
         p[i] = v;
 }
 
-// counters: reset all but the error word (global transform start)
-__global__ void k_reset_counters(Grid g) {
-    int i = threadIdx.x;
-    if (i < C_N && i != C_ERR) g.cnt[i] = 0;
+// Global transform start: empty block table, counters reset (the error word
+// is kept until it is read).
+__global__ void k_begin_global(Grid g, int64_t hcap) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = tid; i < hcap; i += (int64_t)gridDim.x * blockDim.x) g.hkeys[i] = KEY_EMPTY;
+    if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
 }
 
 __global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
 
-// Allocate a pool slot for a key just placed at table position h.
-__device__ inline int32_t claim_slot(const Grid& g, int32_t h, unsigned long long key,
-                                     uint32_t flags) {
-    int32_t slot = atomicAdd(&g.cnt[C_NBLK], 1);
-    if (slot >= g.max_blocks) {
+__device__ inline int32_t load_count(const Grid& g, int idx) {
+    return __hip_atomic_load(&g.cnt[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by every workgroup at its end: the last one to finish records the
+// final block count in cnt[dst] (the range the next kernel works on).
+__device__ inline void snapshot_at_exit(const Grid& g, int dst, int dst2 = -1) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&g.cnt[C_DONE], 1) == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
+            const int32_t n = load_count(g, C_NBLK);
+            g.cnt[dst] = n;
+            if (dst2 >= 0) g.cnt[dst2] = n;
+            g.cnt[C_DONE] = 0;
+        }
+    }
+}
+
+// Pool slots for the lanes that just placed a key at table position h: one
+// counter atomic per wave.  Returns the slot, or -1 (not created / pool full).
+__device__ inline int32_t claim_slots(const Grid& g, bool created, int32_t h,
+                                      unsigned long long key, uint32_t flags) {
+    const int idx = wave_append(created, &g.cnt[C_NBLK]);
+    if (!created) return -1;
+    if (idx >= g.max_blocks) {
         g.hvals[h] = -1;
         set_error(g, -3 /* EDT_ERR_CAPACITY */);
         g.cnt[C_ABORT] = 1;
         return -1;
     }
-    g.bkey[slot] = key;
-    g.flags[slot] = flags;
-    g.hvals[h] = slot;
-    return slot;
+    g.bkey[idx] = key;
+    g.flags[idx] = flags;
+    g.hvals[h] = idx;
+    return idx;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,27 +128,28 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
             bytes[j] = b;
         }
     }
+    // lane j (< 8) learns whether block bx0 + j holds an obstacle
+    bool mine = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool any = __ballot(bytes[j] != 0) != 0;
+        if (lane == j) mine = any && (bx0 + j < g.nbx);
+    }
+    int32_t h = -1;
+    bool created = false;
+    const unsigned long long key = pack_key(bx0 + lane, by, bz);
+    if (mine) {
+        h = hinsert(g.hkeys, g.hmask, key, &created);
+        if (h < 0) set_error(g, -3);
+    }
+    const int32_t slot = claim_slots(g, created, h, key, F_DILATED);
+    const int ndil = __popcll(__ballot(slot >= 0));
+    if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     uint8_t* occ8 = (uint8_t*)g.occ;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int bx = bx0 + j;
-        if (bx >= g.nbx) break;
-        unsigned long long m = __ballot(bytes[j] != 0);
-        if (m == 0) continue;
-        int32_t slot = -1;
-        if (lane == 0) {
-            unsigned long long key = pack_key(bx, by, bz);
-            bool created;
-            int32_t h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) {
-                set_error(g, -3);
-            } else if (created) {
-                slot = claim_slot(g, h, key, F_DILATED);
-                if (slot >= 0) atomicAdd(&g.cnt[C_NDIL], 1);
-            }
-        }
-        slot = __shfl(slot, 0);
-        if (slot >= 0) occ8[(int64_t)slot * 64 + lane] = (uint8_t)bytes[j];
+        const int32_t sj = __shfl(slot, j);
+        if (sj >= 0) occ8[(int64_t)sj * 64 + lane] = (uint8_t)bytes[j];
     }
 }
 
@@ -153,29 +177,39 @@ __device__ inline uint32_t block_row_bits(const Grid& g, const int32_t* xyz,
     return b;
 }
 
+// Each wave takes 64 consecutive input blocks: the wave reads them one by one
+// (coalesced 512 B), lane k keeps the verdict for block k, then the lanes
+// insert their blocks in parallel with one slot-counter atomic per wave.
 __global__ void __launch_bounds__(64) k_ingest_blocks_insert(Grid g, const int32_t* xyz,
                                                              const uint8_t* data, int64_t n) {
     const int lane = threadIdx.x;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        int bx, by, bz;
-        bool ok;
-        uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
-        if (!ok) {
-            if (lane == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
-            continue;
-        }
-        if (__ballot(b != 0) == 0) continue;
-        if (lane == 0) {
-            unsigned long long key = pack_key(bx, by, bz);
-            bool created;
-            int32_t h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) {
-                set_error(g, -3);
-            } else if (created) {
-                if (claim_slot(g, h, key, F_DILATED) >= 0) atomicAdd(&g.cnt[C_NDIL], 1);
+    for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
+        bool mine = false;
+        const int cnt = (int)min((int64_t)64, n - i0);
+        for (int k = 0; k < cnt; ++k) {
+            int bx, by, bz;
+            bool ok;
+            const uint32_t b = block_row_bits(g, xyz, data, i0 + k, lane, bx, by, bz, ok);
+            const bool any = __ballot(b != 0) != 0;
+            if (lane == k) {
+                if (!ok) set_error(g, -2 /* EDT_ERR_RANGE */);
+                mine = ok && any;
             }
         }
+        int32_t h = -1;
+        bool created = false;
+        unsigned long long key = 0;
+        if (mine) {
+            const int64_t i = i0 + lane;
+            key = pack_key(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+            h = hinsert(g.hkeys, g.hmask, key, &created);
+            if (h < 0) set_error(g, -3);
+        }
+        const int32_t slot = claim_slots(g, created, h, key, F_DILATED);
+        const int ndil = __popcll(__ballot(slot >= 0));
+        if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     }
+    snapshot_at_exit(g, C_SNAP);
 }
 
 // phase 2 (after zeroing the occupancy of the new slots): OR the bits in.
@@ -224,16 +258,16 @@ __global__ void k_dilate_axis(Grid g, int axis) {
         unpack_key(g.bkey[slot], c[0], c[1], c[2]);
         c[axis] += off;
         const int lim = axis == 0 ? g.nbx : (axis == 1 ? g.nby : g.nbz);
-        if (c[axis] < 0 || c[axis] >= lim) continue;
-        unsigned long long key = pack_key(c[0], c[1], c[2]);
-        bool created;
-        int32_t h = hinsert(g.hkeys, g.hmask, key, &created);
-        if (h < 0) {
-            set_error(g, -3);
-            continue;
+        const unsigned long long key = pack_key(c[0], c[1], c[2]);
+        bool created = false;
+        int32_t h = -1;
+        if (c[axis] >= 0 && c[axis] < lim) {
+            h = hinsert(g.hkeys, g.hmask, key, &created);
+            if (h < 0) set_error(g, -3);
         }
-        if (created) claim_slot(g, h, key, 0u);
+        claim_slots(g, created, h, key, 0u);
     }
+    snapshot_at_exit(g, C_SNAP);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,22 +277,36 @@ __device__ inline bool run_member(const Grid& g, int32_t slot, uint32_t runflag)
     return slot >= 0 && (runflag == 0u || (g.flags[slot] & runflag));
 }
 
+// A block starts a work item along `axis` when it is the first member of a
+// run (the previous block is absent or not a member) or sits on an LRUN
+// boundary.  axes: 1 = y only, 2 = z only, 3 = both (global transform).
+__device__ inline bool run_start(const Grid& g, int bx, int by, int bz, int axis,
+                                 uint32_t runflag) {
+    const int c = axis == 1 ? by : bz;
+    if (c % LRUN == 0) return true;
+    return !run_member(g, axis == 1 ? find_block(g, bx, by - 1, bz) : find_block(g, bx, by, bz - 1),
+                       runflag);
+}
+
 __global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t runflag,
-                        int axis, int32_t* out, int out_counter) {
+                        int axes) {
     const int64_t n = src ? g.cnt[src_counter] : g.cnt[C_NBLK];
     const int64_t lim = n < g.max_blocks ? n : g.max_blocks;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < lim;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t slot = src ? src[i] : (int32_t)i;
-        int c[3];
-        unpack_key(g.bkey[slot], c[0], c[1], c[2]);
-        bool start = (c[axis] % LRUN) == 0;
-        if (!start) {
-            c[axis] -= 1;
-            start = !run_member(g, find_block(g, c[0], c[1], c[2]), runflag);
+        int bx, by, bz;
+        unpack_key(g.bkey[slot], bx, by, bz);
+        if (axes & 1) {
+            const bool st = run_start(g, bx, by, bz, 1, runflag);
+            const int idx = wave_append(st, &g.cnt[C_NYI]);
+            if (st) g.list_yi[idx] = slot;
         }
-        int idx = wave_append(start, &g.cnt[out_counter]);
-        if (start) out[idx] = slot;
+        if (axes & 2) {
+            const bool st = run_start(g, bx, by, bz, 2, runflag);
+            const int idx = wave_append(st, &g.cnt[C_NZI]);
+            if (st) g.list_zi[idx] = slot;
+        }
     }
 }
 
@@ -282,17 +330,34 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
         __syncthreads();
         const uint32_t c = occ8[(int64_t)slot * 64 + lane];
         int prev = -100000, next = 100000;
-        for (int k = 1; k <= R; ++k) {
-            const int32_t s2 = nb[R - k];
-            if (s2 < 0) continue;
-            const uint32_t b = occ8[(int64_t)s2 * 64 + lane];
-            if (b) { prev = -8 * k + (31 - __clz(b)); break; }
-        }
-        for (int k = 1; k <= R; ++k) {
-            const int32_t s2 = nb[R + k];
-            if (s2 < 0) continue;
-            const uint32_t b = occ8[(int64_t)s2 * 64 + lane];
-            if (b) { next = 8 * k + (__ffs(b) - 1); break; }
+        if (R <= 8) {
+            // issue all neighbour loads at once, then scan in registers
+            uint32_t lb[8], rb[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t sl = k < R ? nb[R - 1 - k] : -1;
+                const int32_t sr = k < R ? nb[R + 1 + k] : -1;
+                lb[k] = sl >= 0 ? (uint32_t)occ8[(int64_t)sl * 64 + lane] : 0u;
+                rb[k] = sr >= 0 ? (uint32_t)occ8[(int64_t)sr * 64 + lane] : 0u;
+            }
+#pragma unroll
+            for (int k = 7; k >= 0; --k) {
+                if (lb[k]) prev = -8 * (k + 1) + (31 - __clz(lb[k]));
+                if (rb[k]) next = 8 * (k + 1) + (__ffs(rb[k]) - 1);
+            }
+        } else {
+            for (int k = 1; k <= R; ++k) {
+                const int32_t s2 = nb[R - k];
+                if (s2 < 0) continue;
+                const uint32_t b = occ8[(int64_t)s2 * 64 + lane];
+                if (b) { prev = -8 * k + (31 - __clz(b)); break; }
+            }
+            for (int k = 1; k <= R; ++k) {
+                const int32_t s2 = nb[R + k];
+                if (s2 < 0) continue;
+                const uint32_t b = occ8[(int64_t)s2 * 64 + lane];
+                if (b) { next = 8 * k + (__ffs(b) - 1); break; }
+            }
         }
         int dl[8];
         int p = prev;
@@ -301,16 +366,14 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
             if ((c >> x) & 1u) p = x;
             dl[x] = x - p;
         }
-        unsigned long long packed = 0;
         int q = next;
+        const int y = lane & 7, z = lane >> 3;
+        uint8_t* dst = g.dist + (int64_t)slot * 512 + 64 * z + y;
 #pragma unroll
         for (int x = 7; x >= 0; --x) {
             if ((c >> x) & 1u) q = x;
-            int d = min(min(dl[x], q - x), 255);
-            packed |= (unsigned long long)d << (8 * x);
+            dst[8 * x] = (uint8_t)min(min(dl[x], q - x), 255);
         }
-        const int y = lane & 7, z = lane >> 3;
-        *(unsigned long long*)(g.dist + (int64_t)slot * 512 + 8 * z + 64 * y) = packed;
         __syncthreads();
     }
 }
@@ -321,74 +384,82 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
 // Sites are pushed in increasing position q with value f < D; outputs are
 // evaluated at i = q - dmax once every site that can reach i is in.  The
 // envelope is kept only on [next output, inf): the bottom site is removed
-// when the new site is no worse at the next output; sites more than dmax left
-// of the output give values > D and are dropped.  The live sites then lie in
-// a window of 2*dmax + 2 positions, which bounds the ring.
+// when the new site is no worse at the next output, and sites more than dmax
+// left of the output (values > D) are dropped.  The live sites then lie in a
+// window of 2*dmax + 2 positions, which bounds the ring.  The two sites at
+// each end of the envelope are mirrored in registers, so LDS is read only
+// when a site is popped from the top or passed at the bottom.
 struct Envelope {
-    uint32_t* ring;   // LDS, element e of this lane at ring[e * 64 + lane]
+    uint32_t* ring;   // LDS, entry e of this lane at ring[e * 64 + lane]
     int cap;          // ring capacity (entries)
     int lane;
     int n;            // live entries
     int bp, tp;       // physical bottom / top index
-    int pt, kt;       // top site position and key f + p^2
+    uint32_t t0, t1;  // top, below top      (entry = position << 16 | value)
+    uint32_t b0, b1;  // bottom, above bottom
 
     __device__ void init(uint32_t* r, int c, int l) {
-        ring = r; cap = c; lane = l; n = 0; bp = 0; tp = c - 1; pt = 0; kt = 0;
+        ring = r; cap = c; lane = l; n = 0; bp = 0; tp = c - 1; t0 = t1 = b0 = b1 = 0u;
     }
+    __device__ int inc(int p) const { return p + 1 == cap ? 0 : p + 1; }
+    __device__ int dec(int p) const { return p == 0 ? cap - 1 : p - 1; }
     __device__ uint32_t at(int phys) const { return ring[phys * 64 + lane]; }
+    static __device__ int pos(uint32_t e) { return (int)(e >> 16); }
+    static __device__ int val(uint32_t e) { return (int)(e & 0xffffu); }
 
     __device__ void push(int q, int f, int inext) {
         const int kq = f + q * q;
         while (n > 0) {
+            const int pt = pos(t0);
+            const int kt = val(t0) + pt * pt;
             if (n == 1) {
-                // bottom: the new site is no worse on [inext, inf)
+                // the only site: drop it if the new one is no worse on [inext, inf)
                 if (kq - kt <= 2 * inext * (q - pt)) {
                     n = 0;
-                    tp = bp == 0 ? cap - 1 : bp - 1;
+                    tp = dec(bp);
                 }
                 break;
             }
-            const int below = tp == 0 ? cap - 1 : tp - 1;
-            const uint32_t e = at(below);
-            const int p0 = (int)(e >> 16), f0 = (int)(e & 0xffffu);
-            const int k0 = f0 + p0 * p0;
-            // top is hidden when the new site meets `below` no later than top does
+            const int p0 = pos(t1);
+            const int k0 = val(t1) + p0 * p0;
+            // top is hidden when the new site meets t1 no later than top does
             if ((kq - k0) * (pt - p0) <= (kt - k0) * (q - p0)) {
+                tp = dec(tp);
                 --n;
-                tp = below;
-                pt = p0;
-                kt = k0;
+                t0 = t1;
+                if (n >= 2) t1 = at(dec(tp));
             } else {
                 break;
             }
         }
-        tp = tp + 1 == cap ? 0 : tp + 1;
-        ring[tp * 64 + lane] = ((uint32_t)q << 16) | (uint32_t)f;
+        tp = inc(tp);
+        const uint32_t e = ((uint32_t)q << 16) | (uint32_t)f;
+        ring[tp * 64 + lane] = e;
         ++n;
-        pt = q;
-        kt = kq;
+        t1 = t0;
+        t0 = e;
+        if (n == 1) b0 = e;
+        else if (n == 2) b1 = e;
+    }
+
+    __device__ void advance() {
+        bp = inc(bp);
+        --n;
+        if (n >= 1) b0 = b1;
+        if (n >= 2) b1 = at(inc(bp));
     }
 
     // min over live sites of f + (i - p)^2, clamped to D
     __device__ int eval(int i, int dmax, int D) {
-        while (n > 0) {
-            const uint32_t e = at(bp);
-            if ((int)(e >> 16) >= i - dmax) break;
-            bp = bp + 1 == cap ? 0 : bp + 1;
-            --n;
-        }
+        while (n > 0 && pos(b0) < i - dmax) advance();
         if (n == 0) return D;
-        uint32_t e = at(bp);
-        int pb = (int)(e >> 16);
-        int vb = (int)(e & 0xffffu) + (i - pb) * (i - pb);
-        while (n > 1) {
-            const int nx = bp + 1 == cap ? 0 : bp + 1;
-            const uint32_t e1 = at(nx);
-            const int p1 = (int)(e1 >> 16);
-            const int v1 = (int)(e1 & 0xffffu) + (i - p1) * (i - p1);
+        int d0 = i - pos(b0);
+        int vb = val(b0) + d0 * d0;
+        while (n >= 2) {
+            const int d1 = i - pos(b1);
+            const int v1 = val(b1) + d1 * d1;
             if (v1 > vb) break;
-            bp = nx;
-            --n;
+            advance();
             vb = v1;
         }
         return vb < D ? vb : D;
@@ -420,8 +491,48 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
     while (ha < R && sl[R + len + ha] >= 0) ++ha;
 }
 
-// pass Y: lane = (x, z) with lane = x + 8z; reads dist (layout x+8z+64y),
-// writes g2 (layout x+8y+64z).
+// The envelope passes walk the blocks of a work item two at a time with two
+// explicit input buffers (no register copies), and every step issues exactly
+// one global store (halo steps store to a per-wave scratch row), so the
+// memory operations form a fixed sequence and a step never waits for the
+// stores of the steps before it.
+//
+// pass Y: lane = x + 8z.  Reads dist (layout (x + 8z) * 8 + y: one 8-byte
+// load per block and lane), writes g2 (layout (x + 8y) * 8 + z).
+struct PassYItem {
+    const Grid& g;
+    const int32_t* sl;
+    Envelope& env;
+    int base, nb, o0, o1, qa, qb, dmax, D, lane, out_lane;
+    uint16_t* dummy;
+
+    __device__ unsigned long long load(int j) const {
+        const int jj = j < nb ? j : nb - 1;
+        return ((const unsigned long long*)g.dist)[(int64_t)sl[base + jj] * 64 + lane];
+    }
+    __device__ void block(unsigned long long cur, int j) {
+        const int jo = (j * 8 - dmax) >> 3;
+        const int32_t slo = (jo >= 0 && jo < nb) ? sl[base + jo] : -1;
+        const int32_t shi = (jo + 1 >= 0 && jo + 1 < nb) ? sl[base + jo + 1] : -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * j + k;
+            if (q >= qa && q < qb) {
+                const int d = (int)((cur >> (8 * k)) & 0xffu);
+                if (d < dmax) env.push(q, d * d, max(o0, q - dmax));
+            }
+            const int i = q - dmax;
+            const bool out = i >= o0 && i < o1;
+            int v = 0;
+            if (out) v = env.eval(i, dmax, D);
+            const int32_t slot = ((i >> 3) == jo) ? slo : shi;
+            uint16_t* dst = out ? g.g2 + (int64_t)slot * 512 + out_lane + 64 * (i & 7)
+                                : dummy + lane;
+            *dst = (uint16_t)v;
+        }
+    }
+};
+
 __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int item_counter,
                                                uint32_t runflag, int cap) {
     extern __shared__ uint32_t smem[];
@@ -430,37 +541,77 @@ __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int
     uint32_t* ring = smem + 96 + 24;
     const int lane = threadIdx.x;
     const int64_t nit = g.cnt[item_counter];
-    const int dmax = g.dmax, D = g.D, R = g.R;
-    const int x = lane & 7, z = lane >> 3;
+    const int R = g.R;
+    uint16_t* dummy = (uint16_t*)(g.dummy + (blockIdx.x & 255) * 64);
     for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
         const int32_t s0 = items[it];
         int bx, by, bz;
         unpack_key(g.bkey[s0], bx, by, bz);
         int hb, len, ha;
         resolve_run(g, sl, mem, bx, by, bz, 1, runflag, hb, len, ha);
-        const int base = R - hb;
-        const int o0 = 8 * hb, o1 = 8 * (hb + len), nq = 8 * (hb + len + ha);
-        const int qa = max(0, o0 - dmax), qb = min(nq, o1 + dmax);
         Envelope env;
         env.init(ring, cap, lane);
-        for (int q = qa; q < o1 + dmax; ++q) {
-            if (q < qb) {
-                const int32_t slot = sl[base + (q >> 3)];
-                const int d = g.dist[(int64_t)slot * 512 + lane + 64 * (q & 7)];
-                if (d < dmax) env.push(q, d * d, max(o0, q - dmax));
-            }
-            const int i = q - dmax;
-            if (i >= o0) {
-                const int v = env.eval(i, dmax, D);
-                const int32_t slot = sl[base + (i >> 3)];
-                g.g2[(int64_t)slot * 512 + x + 8 * (i & 7) + 64 * z] = (uint16_t)v;
-            }
+        const int nb = hb + len + ha;
+        const int o0 = 8 * hb, o1 = 8 * (hb + len);
+        PassYItem P{g, sl, env, R - hb, nb, o0, o1, max(0, o0 - g.dmax), min(8 * nb, o1 + g.dmax),
+                    g.dmax, g.D, lane, (lane & 7) * 8 + (lane >> 3), dummy};
+        const int jlo = P.qa >> 3, jhi = (o1 + g.dmax - 1) >> 3;
+        unsigned long long A = P.load(jlo), B = P.load(jlo + 1);
+        for (int j = jlo; j <= jhi; j += 2) {
+            P.block(A, j);
+            A = P.load(j + 2);
+            if (j + 1 > jhi) break;
+            P.block(B, j + 1);
+            B = P.load(j + 3);
         }
         __syncthreads();
     }
 }
 
-// pass Z: lane = (x, y) with lane = x + 8y; reads g2, writes s and bmax.
+// pass Z: lane = x + 8y.  Reads g2 (one 16-byte load per block and lane),
+// writes s (layout x + 8y + 64z) and the per-block maximum.
+struct PassZItem {
+    const Grid& g;
+    const int32_t* sl;
+    Envelope& env;
+    int base, nb, o0, o1, qa, qb, dmax, D, lane;
+    int32_t* dummy;
+    int bm;
+
+    __device__ uint4 load(int j) const {
+        const int jj = j < nb ? j : nb - 1;
+        return ((const uint4*)g.g2)[(int64_t)sl[base + jj] * 64 + lane];
+    }
+    __device__ void block(uint4 cur, int j) {
+        const int jo = (j * 8 - dmax) >> 3;
+        const int32_t slo = (jo >= 0 && jo < nb) ? sl[base + jo] : -1;
+        const int32_t shi = (jo + 1 >= 0 && jo + 1 < nb) ? sl[base + jo + 1] : -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = 8 * j + k;
+            if (q >= qa && q < qb) {
+                const uint32_t wk = k < 2 ? cur.x : (k < 4 ? cur.y : (k < 6 ? cur.z : cur.w));
+                const int f = (int)((wk >> (16 * (k & 1))) & 0xffffu);
+                if (f < D) env.push(q, f, max(o0, q - dmax));
+            }
+            const int i = q - dmax;
+            const bool out = i >= o0 && i < o1;
+            int v = 0;
+            if (out) v = env.eval(i, dmax, D);
+            const int32_t slot = ((i >> 3) == jo) ? slo : shi;
+            int32_t* dst = out ? g.s + (int64_t)slot * 512 + lane + 64 * (i & 7) : dummy + lane;
+            *dst = v;
+            bm = max(bm, v);
+            if (((k - dmax) & 7) == 7) {          // the step that ends an output block
+                const int m = wave_max(bm);
+                int32_t* bd = out ? g.bmax + slot : dummy + 64 + lane;
+                *bd = m;
+                bm = 0;
+            }
+        }
+    }
+};
+
 __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int item_counter,
                                                uint32_t runflag, int cap) {
     extern __shared__ uint32_t smem[];
@@ -469,37 +620,28 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
     uint32_t* ring = smem + 96 + 24;
     const int lane = threadIdx.x;
     const int64_t nit = g.cnt[item_counter];
-    const int dmax = g.dmax, D = g.D, R = g.R;
+    const int R = g.R;
+    int32_t* dummy = (int32_t*)(g.dummy + (blockIdx.x & 255) * 64);
     for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
         const int32_t s0 = items[it];
         int bx, by, bz;
         unpack_key(g.bkey[s0], bx, by, bz);
         int hb, len, ha;
         resolve_run(g, sl, mem, bx, by, bz, 2, runflag, hb, len, ha);
-        const int base = R - hb;
-        const int o0 = 8 * hb, o1 = 8 * (hb + len), nq = 8 * (hb + len + ha);
-        const int qa = max(0, o0 - dmax), qb = min(nq, o1 + dmax);
         Envelope env;
         env.init(ring, cap, lane);
-        int bm = 0;
-        for (int q = qa; q < o1 + dmax; ++q) {
-            if (q < qb) {
-                const int32_t slot = sl[base + (q >> 3)];
-                const int f = g.g2[(int64_t)slot * 512 + lane + 64 * (q & 7)];
-                if (f < D) env.push(q, f, max(o0, q - dmax));
-            }
-            const int i = q - dmax;
-            if (i >= o0) {
-                const int v = env.eval(i, dmax, D);
-                const int32_t slot = sl[base + (i >> 3)];
-                g.s[(int64_t)slot * 512 + lane + 64 * (i & 7)] = v;
-                bm = max(bm, v);
-                if ((i & 7) == 7) {
-                    const int m = wave_max(bm);
-                    if (lane == 0) g.bmax[slot] = m;
-                    bm = 0;
-                }
-            }
+        const int nb = hb + len + ha;
+        const int o0 = 8 * hb, o1 = 8 * (hb + len);
+        PassZItem P{g, sl, env, R - hb, nb, o0, o1, max(0, o0 - g.dmax), min(8 * nb, o1 + g.dmax),
+                    g.dmax, g.D, lane, dummy, 0};
+        const int jlo = P.qa >> 3, jhi = (o1 + g.dmax - 1) >> 3;
+        uint4 A = P.load(jlo), B = P.load(jlo + 1);
+        for (int j = jlo; j <= jhi; j += 2) {
+            P.block(A, j);
+            A = P.load(j + 2);
+            if (j + 1 > jhi) break;
+            P.block(B, j + 1);
+            B = P.load(j + 3);
         }
         __syncthreads();
     }
@@ -595,17 +737,18 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
     if (g.cnt[C_ABORT]) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (!state[i] || !upd_winner(g, i)) continue;
-        const int bx = xyz[3 * i] >> 3, by = xyz[3 * i + 1] >> 3, bz = xyz[3 * i + 2] >> 3;
-        const unsigned long long key = pack_key(bx, by, bz);
-        bool created;
-        const int32_t h = hinsert(g.hkeys, g.hmask, key, &created);
-        if (h < 0) {
-            set_error(g, -3);
-            g.cnt[C_ABORT] = 1;
-        } else if (created) {
-            claim_slot(g, h, key, 0u);
+        bool created = false;
+        int32_t h = -1;
+        unsigned long long key = 0;
+        if (state[i] && upd_winner(g, i)) {
+            key = pack_key(xyz[3 * i] >> 3, xyz[3 * i + 1] >> 3, xyz[3 * i + 2] >> 3);
+            h = hinsert(g.hkeys, g.hmask, key, &created);
+            if (h < 0) {
+                set_error(g, -3);
+                g.cnt[C_ABORT] = 1;
+            }
         }
+        claim_slots(g, created, h, key, 0u);
     }
 }
 
@@ -693,15 +836,14 @@ __global__ void k_upd_dilate(Grid g) {
         bx += o % w - R;
         by += (o / w) % w - R;
         bz += o / (w * w) - R;
-        if (bx < 0 || by < 0 || bz < 0 || bx >= g.nbx || by >= g.nby || bz >= g.nbz) continue;
+        bool created = false;
+        int32_t h = -1;
         const unsigned long long key = pack_key(bx, by, bz);
-        bool created;
-        const int32_t h = hinsert(g.hkeys, g.hmask, key, &created);
-        if (h < 0) {
-            set_error(g, -3);
-        } else if (created) {
-            claim_slot(g, h, key, 0u);
+        if (bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz) {
+            h = hinsert(g.hkeys, g.hmask, key, &created);
+            if (h < 0) set_error(g, -3);
         }
+        claim_slots(g, created, h, key, 0u);
     }
 }
 
