@@ -175,17 +175,18 @@ edt_status edt_timing_read(edt_ctx* ctx, float* ms, int32_t* n_recorded);
  *   h          voxel edge in metres; voxel center (i,j,k) sits at (i,j,k)*h.
  *   d(p)       trilinear interpolation of h*sqrt(s) at p (metres), with the
  *              cell index clamped to [0, n-2] and the cell coordinate to
- *              [0, 1] per axis.
+ *              [0, 1] per axis; u = p/h, the cell and its coordinate are
+ *              computed in double precision, everything else in float.
  *   d_wp       float[T][W][3] waypoints (x, y, z) in metres.
  *   d_cost     float[T]: sum over the W waypoints of c(p), accumulated in
  *              fp32 in a fixed order (deterministic).
  * edt_clearance_bwd writes d_gwp (float[T][W][3]) = d_gcost[t] * dc/dp,
  * zero on axes whose cell coordinate was clamped and where d >= margin.    */
 edt_status edt_clearance_fwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz,
-                             float h, float margin, const float* d_wp,
+                             double h, float margin, const float* d_wp,
                              int64_t T, int32_t W, float* d_cost, void* stream);
 edt_status edt_clearance_bwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz,
-                             float h, float margin, const float* d_wp,
+                             double h, float margin, const float* d_wp,
                              int64_t T, int32_t W, const float* d_gcost,
                              float* d_gwp, void* stream);
 

@@ -13,11 +13,7 @@ edge in metres).  Voxel center i sits at metric position i * h.
 Per axis with grid size n and u = p / h:
     i0 = clamp(floor(u), 0, n - 2),   t = clamp(u - i0, 0, 1);
 an axis whose t was clamped contributes no gradient (the interpolant is
-constant there).  The cell index i0 and the clamp test are integer decisions
-taken from floating point; at a cell face the one-sided gradients differ, so
-for fp32 waypoints (``decide_fp32=True``) both decisions are taken from the
-fp32 quotient fl32(p) / fl32(h), the precision of the GPU kernel (the paper
-fixes none).  Everything else is float64; fp32 inputs are widened exactly.
+constant there).  Everything is float64; fp32 inputs are widened exactly.
 """
 from __future__ import annotations
 
@@ -29,31 +25,25 @@ def metric_field(s: np.ndarray, h: float) -> np.ndarray:
     return float(h) * np.sqrt(np.asarray(s, dtype=np.float64))
 
 
-def _axis(u: np.ndarray, n: int, u_decide: np.ndarray):
-    """Cell index, cell coordinate and 'not clamped' flag along one axis;
-    i0 and the flag come from u_decide, t from u."""
-    i0 = np.clip(np.floor(u_decide), 0, n - 2).astype(np.int64)
-    td = u_decide - i0.astype(u_decide.dtype)
-    live = (td >= 0) & (td <= 1)
-    t = np.clip(u - i0, 0.0, 1.0)
+def _axis(u: np.ndarray, n: int):
+    """Cell index, cell coordinate and 'not clamped' flag along one axis."""
+    i0 = np.clip(np.floor(u), 0, n - 2).astype(np.int64)
+    t_raw = u - i0
+    t = np.clip(t_raw, 0.0, 1.0)
+    live = (t_raw >= 0.0) & (t_raw <= 1.0)
     return i0, t, live
 
 
-def trilinear(field: np.ndarray, p: np.ndarray, h: float, decide_fp32: bool = False):
+def trilinear(field: np.ndarray, p: np.ndarray, h: float):
     """Value and gradient (d/dp, metres) of the trilinear interpolant of a
     (nz, ny, nx) float64 field at points p[..., 3] = (x, y, z) metres."""
     field = np.asarray(field, dtype=np.float64)
     nz, ny, nx = field.shape
-    p32 = np.asarray(p)
-    p = p32.astype(np.float64)
+    p = np.asarray(p, dtype=np.float64)
     u = p / float(h)
-    if decide_fp32:
-        ud = p32.astype(np.float32) / np.float32(h)
-    else:
-        ud = u
-    ix, tx, lx = _axis(u[..., 0], nx, ud[..., 0])
-    iy, ty, ly = _axis(u[..., 1], ny, ud[..., 1])
-    iz, tz, lz = _axis(u[..., 2], nz, ud[..., 2])
+    ix, tx, lx = _axis(u[..., 0], nx)
+    iy, ty, ly = _axis(u[..., 1], ny)
+    iz, tz, lz = _axis(u[..., 2], nz)
 
     def f(dz, dy, dx):
         return field[iz + dz, iy + dy, ix + dx]
@@ -73,17 +63,17 @@ def trilinear(field: np.ndarray, p: np.ndarray, h: float, decide_fp32: bool = Fa
     return val, grad
 
 
-def cost(s: np.ndarray, wp: np.ndarray, h: float, margin: float, decide_fp32: bool = False):
+def cost(s: np.ndarray, wp: np.ndarray, h: float, margin: float):
     """Per-trajectory cost C_t (float64 [T]) for waypoints wp[T, W, 3]."""
-    d, _ = trilinear(metric_field(s, h), wp, h, decide_fp32)
+    d, _ = trilinear(metric_field(s, h), wp, h)
     c = np.maximum(0.0, margin - d) ** 2
     return c.sum(axis=-1)
 
 
 def cost_grad(s: np.ndarray, wp: np.ndarray, h: float, margin: float,
-              gcost: np.ndarray | None = None, decide_fp32: bool = False):
+              gcost: np.ndarray | None = None):
     """Analytic dL/dwp for L = sum_t gcost[t] * C_t (gcost defaults to ones)."""
-    d, gd = trilinear(metric_field(s, h), wp, h, decide_fp32)
+    d, gd = trilinear(metric_field(s, h), wp, h)
     hinge = np.maximum(0.0, margin - d)
     g = -2.0 * hinge[..., None] * gd
     if gcost is not None:

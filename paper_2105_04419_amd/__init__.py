@@ -68,6 +68,7 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2105_04419_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+    f64 = ctypes.c_double
     sig = {
         "edt_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "edt_workspace_bytes": ([ctypes.POINTER(EdtConfig)], i64),
@@ -83,8 +84,8 @@ def lib():
         "edt_timing_begin": ([vp, i32], ctypes.c_int),
         "edt_timing_read": ([vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)],
                             ctypes.c_int),
-        "edt_clearance_fwd": ([vp, i32, i32, i32, f32, f32, vp, i64, i32, vp, vp], ctypes.c_int),
-        "edt_clearance_bwd": ([vp, i32, i32, i32, f32, f32, vp, i64, i32, vp, vp, vp],
+        "edt_clearance_fwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp], ctypes.c_int),
+        "edt_clearance_bwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp, vp],
                               ctypes.c_int),
     }
     for name, (args, res) in sig.items():

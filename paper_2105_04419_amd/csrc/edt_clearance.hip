@@ -6,8 +6,12 @@
 // point p (metres, voxel center i at i*h).  Per axis with n voxels and
 // u = p / h: i0 = clamp(floor(u), 0, n-2), t = clamp(u - i0, 0, 1); an axis
 // whose t was clamped has zero derivative.  The field stays exact integer
-// arithmetic upstream; only this query is floating point (fp32 throughout,
-// with a fixed-order per-trajectory reduction so results are deterministic).
+// arithmetic upstream; only this query is floating point.  The map from a
+// waypoint to its cell (u, i0, t) is taken in fp64: it decides an integer
+// (the cell, hence which one-sided gradient applies on a face), and in fp32
+// u = p/h would carry an absolute error of ~|u| * 6e-8 into t.  The
+// interpolation, the cost and its gradient are fp32, and each trajectory's
+// cost is reduced in a fixed order, so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include "edt.h"
@@ -18,27 +22,28 @@ struct Tri {
     float v, gx, gy, gz;   // value and d/du (per voxel unit)
 };
 
-__device__ inline void axis_cell(float u, int n, int& i0, float& t, float& live) {
-    float fl = floorf(u);
-    fl = fminf(fmaxf(fl, 0.0f), (float)(n - 2));
+__device__ inline void axis_cell(float p, double h, int n, int& i0, float& t, float& live) {
+    const double u = (double)p / h;
+    double fl = floor(u);
+    fl = fmin(fmax(fl, 0.0), (double)(n - 2));
     i0 = (int)fl;
-    const float tr = u - fl;
-    live = (tr >= 0.0f && tr <= 1.0f) ? 1.0f : 0.0f;
-    t = fminf(fmaxf(tr, 0.0f), 1.0f);
+    const double tr = u - fl;
+    live = (tr >= 0.0 && tr <= 1.0) ? 1.0f : 0.0f;
+    t = (float)fmin(fmax(tr, 0.0), 1.0);
 }
 
 __device__ inline float metric(const int32_t* __restrict__ s, int64_t idx, float h) {
     return h * sqrtf((float)__ldg(s + idx));
 }
 
-__device__ inline Tri trilinear(const int32_t* __restrict__ s, int nx, int ny, int nz, float h,
+__device__ inline Tri trilinear(const int32_t* __restrict__ s, int nx, int ny, int nz, double hd,
                                 float px, float py, float pz) {
     int ix, iy, iz;
     float tx, ty, tz, lx, ly, lz;
-    // correctly rounded fp32 quotients: the cell index is decided in fp32
-    axis_cell(__fdiv_rn(px, h), nx, ix, tx, lx);
-    axis_cell(__fdiv_rn(py, h), ny, iy, ty, ly);
-    axis_cell(__fdiv_rn(pz, h), nz, iz, tz, lz);
+    axis_cell(px, hd, nx, ix, tx, lx);
+    axis_cell(py, hd, ny, iy, ty, ly);
+    axis_cell(pz, hd, nz, iz, tz, lz);
+    const float h = (float)hd;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t b = ix + sy * iy + sz * iz;
     const float c000 = metric(s, b, h), c001 = metric(s, b + 1, h);
@@ -61,7 +66,7 @@ __device__ inline Tri trilinear(const int32_t* __restrict__ s, int nx, int ny, i
 // One wave per trajectory: lane w accumulates waypoints w, w+64, ... in order,
 // then a fixed butterfly reduction over the 64 lanes.
 __global__ void __launch_bounds__(256) k_clear_fwd(const int32_t* __restrict__ s, int nx, int ny,
-                                                   int nz, float h, float margin,
+                                                   int nz, double h, float margin,
                                                    const float* __restrict__ wp, int64_t T, int W,
                                                    float* __restrict__ cost) {
     const int lane = threadIdx.x & 63;
@@ -81,7 +86,7 @@ __global__ void __launch_bounds__(256) k_clear_fwd(const int32_t* __restrict__ s
 }
 
 __global__ void __launch_bounds__(256) k_clear_bwd(const int32_t* __restrict__ s, int nx, int ny,
-                                                   int nz, float h, float margin,
+                                                   int nz, double h, float margin,
                                                    const float* __restrict__ wp, int64_t T, int W,
                                                    const float* __restrict__ gcost,
                                                    float* __restrict__ gwp) {
@@ -91,15 +96,15 @@ __global__ void __launch_bounds__(256) k_clear_bwd(const int32_t* __restrict__ s
         const float* p = wp + i * 3;
         const Tri r = trilinear(s, nx, ny, nz, h, p[0], p[1], p[2]);
         const float hinge = fmaxf(0.0f, margin - r.v);
-        const float k = gcost[i / W] * (-2.0f * hinge) / h;
+        const float k = gcost[i / W] * (-2.0f * hinge) * (float)(1.0 / h);
         gwp[i * 3 + 0] = k * r.gx;
         gwp[i * 3 + 1] = k * r.gy;
         gwp[i * 3 + 2] = k * r.gz;
     }
 }
 
-bool bad_field(const int32_t* s, int nx, int ny, int nz, float h) {
-    return !s || nx < 2 || ny < 2 || nz < 2 || !(h > 0.0f);
+bool bad_field(const int32_t* s, int nx, int ny, int nz, double h) {
+    return !s || nx < 2 || ny < 2 || nz < 2 || !(h > 0.0);
 }
 
 int grid_for(int64_t work, int per, int cap) {
@@ -113,7 +118,7 @@ int grid_for(int64_t work, int per, int cap) {
 
 extern "C" {
 
-edt_status edt_clearance_fwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz, float h,
+edt_status edt_clearance_fwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz, double h,
                              float margin, const float* d_wp, int64_t T, int32_t W, float* d_cost,
                              void* stream) {
     if (bad_field(d_s, nx, ny, nz, h) || T < 0 || W < 0) return EDT_ERR_ARG;
@@ -124,7 +129,7 @@ edt_status edt_clearance_fwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t
     return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_HIP;
 }
 
-edt_status edt_clearance_bwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz, float h,
+edt_status edt_clearance_bwd(const int32_t* d_s, int32_t nx, int32_t ny, int32_t nz, double h,
                              float margin, const float* d_wp, int64_t T, int32_t W,
                              const float* d_gcost, float* d_gwp, void* stream) {
     if (bad_field(d_s, nx, ny, nz, h) || T < 0 || W < 0) return EDT_ERR_ARG;

@@ -69,8 +69,7 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu(L):
     assert L.edt_destroy(None) == -1
     assert L.edt_global(None, None, None) == -1
     assert L.edt_update(None, None, None, 0, None) == -1
-    assert L.edt_clearance_fwd(None, 4, 4, 4, ctypes.c_float(0.2), ctypes.c_float(1.0), None,
-                               1, 1, None, None) == -1
+    assert L.edt_clearance_fwd(None, 4, 4, 4, 0.2, 1.0, None, 1, 1, None, None) == -1
 
 
 def test_product_package_does_not_import_the_oracle():

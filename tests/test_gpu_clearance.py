@@ -34,7 +34,7 @@ def test_forward_matches_fp64(field):
     occ, s_gpu, s_ref = field
     wp = workloads.trajectories(0, occ, ntraj=512)
     c = ClearanceCost.apply(s_gpu, torch.from_numpy(wp).cuda(), H, MARGIN).cpu().numpy()
-    ref = cl.cost(s_ref, wp, H, MARGIN, decide_fp32=True)
+    ref = cl.cost(s_ref, wp, H, MARGIN)
     assert np.all(np.abs(c - ref) <= 1e-5 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()) + 1e-6)
 
 
@@ -46,8 +46,7 @@ def test_backward_matches_fp64_analytic(field):
     gc = torch.linspace(0.5, 2.0, c.numel(), device="cuda")
     (c * gc).sum().backward()
     g = x.grad.cpu().numpy().astype(np.float64)
-    gref = cl.cost_grad(s_ref, wp, H, MARGIN, gc.cpu().numpy().astype(np.float64),
-                        decide_fp32=True)
+    gref = cl.cost_grad(s_ref, wp, H, MARGIN, gc.cpu().numpy().astype(np.float64))
     ok = tol_ok(g, gref)
     assert ok.all(), f"{(~ok).sum()} components outside tolerance"
 

@@ -95,19 +95,3 @@ def test_upstream_gradient_scales():
     assert np.allclose(cl.cost_grad(s, wp, H, 1.0, gc),
                        cl.cost_grad(s, wp, H, 1.0) * gc[:, None, None])
 
-
-def test_fp32_cell_decision_only_changes_face_points():
-    """Taking the cell index from the fp32 quotient changes the gradient only
-    for points whose fp32 and fp64 quotients straddle a cell face."""
-    rng = np.random.default_rng(7)
-    s = rng.integers(0, 40, size=(8, 9, 10)).astype(np.int32)
-    wp = (rng.random((50, 20, 3)) * np.array([9, 8, 7]) * H).astype(np.float32)
-    wp[0, 0] = np.array([3, 4, 5], np.float32) * np.float32(H)     # on faces
-    g64 = cl.cost_grad(s, wp, H, 1.0)
-    g32 = cl.cost_grad(s, wp, H, 1.0, decide_fp32=True)
-    u64 = wp.astype(np.float64) / H
-    u32 = wp / np.float32(H)
-    same_cell = (np.floor(u64) == np.floor(u32))
-    assert np.array_equal(g64[same_cell], g32[same_cell])
-    assert np.allclose(cl.cost(s, wp, H, 1.0), cl.cost(s, wp, H, 1.0, decide_fp32=True),
-                       rtol=1e-6)
