@@ -91,14 +91,14 @@ def bench_global(args, torch, np):
 def roofline(g):
     """Dominant kernel of the global step and its algorithmic HBM bytes:
     pass_z reads g2 (2 B) and writes s (4 B) per voxel of the region, plus
-    one int32 block maximum per block; pass_y reads dist (1 B) and writes g2
-    (2 B); pass_x reads 64 B of bits and writes 512 B of dist per block."""
+    one int32 block maximum per block; pass_y reads g1 (2 B) and writes g2
+    (2 B); pass_x reads 64 B of bits and writes 1 KiB of g1 per block."""
     ph = g["phases"]
     nb = g["st"]["blocks"]
     per_launch = {
         "pass_z": nb * 512 * 6 + nb * 4,
-        "pass_y": nb * 512 * 3,
-        "pass_x": nb * (64 + 512),
+        "pass_y": nb * 512 * 4,
+        "pass_x": nb * (64 + 1024),
     }
     kern = max(per_launch, key=lambda k: ph[k])
     ms = ph[kern]

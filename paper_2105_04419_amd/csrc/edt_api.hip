@@ -47,9 +47,9 @@ struct Layout {
 };
 
 enum {
-    O_HKEYS, O_HVALS, O_BKEY, O_OCC, O_DIST, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
+    O_HKEYS, O_HVALS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -75,10 +75,10 @@ bool layout_of(const edt_config* c, Layout* L) {
     L->hcap = next_pow2(mb * 2 < 64 ? 64 : mb * 2);
     L->ucap = next_pow2(mc * 2 < 64 ? 64 : mc * 2);
     const int64_t sz[O_N] = {
-        L->hcap * 8, L->hcap * 4, mb * 8, mb * 64, mb * 512, mb * 1024, mb * 2048, mb * 4,
+        L->hcap * 8, L->hcap * 4, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
-        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024};
+        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024, 1024};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -116,6 +116,41 @@ inline int grid_for(int64_t work, int per, int cap) {
         if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP; \
     } while (0)
 
+// Pass along y (axis 1) or z (axis 2) over the item list of that axis.
+// d_max <= 64: windowed minimum (one instantiation per block radius);
+// larger radii: streaming lower envelope.
+template <int AXIS>
+void launch_win(const Grid& g, int grid, hipStream_t st, const int32_t* items, int counter,
+                uint32_t runflag) {
+    switch (g.R) {
+#define EDT_WIN_CASE(m)                                                                     \
+    case m:                                                                                \
+        hipLaunchKernelGGL((k_pass_win<m, AXIS>), dim3(grid), dim3(64), 0, st, g, items, counter, \
+                           runflag);                                                       \
+        break;
+        EDT_WIN_CASE(1) EDT_WIN_CASE(2) EDT_WIN_CASE(3) EDT_WIN_CASE(4)
+        EDT_WIN_CASE(5) EDT_WIN_CASE(6) EDT_WIN_CASE(7) EDT_WIN_CASE(8)
+#undef EDT_WIN_CASE
+        default: break;
+    }
+}
+
+void launch_pass(edt_ctx* c, int axis, hipStream_t st, const int32_t* items, int counter,
+                 uint32_t runflag) {
+    const Grid& g = c->g;
+    const int grid = grid_for(g.max_blocks, 1, 8192);
+    if (g.R <= 8) {
+        if (axis == 1) launch_win<1>(g, grid, st, items, counter, runflag);
+        else launch_win<2>(g, grid, st, items, counter, runflag);
+    } else if (axis == 1) {
+        hipLaunchKernelGGL(k_pass_y, dim3(grid), dim3(64), c->env_lds, st, g, items, counter,
+                           runflag, c->cap);
+    } else {
+        hipLaunchKernelGGL(k_pass_z, dim3(grid), dim3(64), c->env_lds, st, g, items, counter,
+                           runflag, c->cap);
+    }
+}
+
 edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
     const int mb = g.max_blocks;
@@ -125,11 +160,9 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
     hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
                        (const int32_t*)nullptr, 0);
     mark(c, 4, st);
-    hipLaunchKernelGGL(k_pass_y, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
-                       (const int32_t*)g.list_yi, (int)C_NYI, 0u, c->cap);
+    launch_pass(c, 1, st, g.list_yi, (int)C_NYI, 0u);
     mark(c, 5, st);
-    hipLaunchKernelGGL(k_pass_z, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
-                       (const int32_t*)g.list_zi, (int)C_NZI, 0u, c->cap);
+    launch_pass(c, 2, st, g.list_zi, (int)C_NZI, 0u);
     mark(c, 6, st);
     if (c->ev && c->ev_used < c->ev_calls) c->ev_used++;
     LAUNCH_CHECK();
@@ -197,7 +230,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.hvals = (int32_t*)(b + L.off[O_HVALS]);
     g.bkey = (unsigned long long*)(b + L.off[O_BKEY]);
     g.occ = (uint32_t*)(b + L.off[O_OCC]);
-    g.dist = (uint8_t*)(b + L.off[O_DIST]);
+    g.g1 = (uint16_t*)(b + L.off[O_G1]);
     g.g2 = (uint16_t*)(b + L.off[O_G2]);
     g.s = (int32_t*)(b + L.off[O_S]);
     g.bmax = (int32_t*)(b + L.off[O_BMAX]);
@@ -217,6 +250,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.uvals = (int32_t*)(b + L.off[O_UVALS]);
     g.upos = (int32_t*)(b + L.off[O_UPOS]);
     g.dummy = (uint32_t*)(b + L.off[O_DUMMY]);
+    g.dblock = (uint16_t*)(b + L.off[O_DBLOCK]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -249,6 +283,8 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
                        L.ucap, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt, (int64_t)64, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int32_t*)g.dblock, (int64_t)256,
+                       (int32_t)((uint32_t)g.D | ((uint32_t)g.D << 16)));
     if (hipGetLastError() != hipSuccess) {
         free(c);
         return EDT_ERR_HIP;
@@ -371,12 +407,10 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
     const int tg = grid_for(mb, 256, 4096);
     hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_ys,
                        (int)C_NYS, (uint32_t)F_YS, 1);
-    hipLaunchKernelGGL(k_pass_y, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
-                       (const int32_t*)g.list_yi, (int)C_NYI, (uint32_t)F_YS, c->cap);
+    launch_pass(c, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
     hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_dirty,
                        (int)C_NDIRTY, (uint32_t)F_DIRTY, 2);
-    hipLaunchKernelGGL(k_pass_z, dim3(grid_for(mb, 1, 8192)), dim3(64), c->env_lds, st, g,
-                       (const int32_t*)g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY, c->cap);
+    launch_pass(c, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
     hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,
                        g, n);
     LAUNCH_CHECK();

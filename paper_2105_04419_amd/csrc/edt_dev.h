@@ -8,12 +8,12 @@
 // Per pool slot (one leaf block):
 //   occ    512 occupancy bits, 16 x uint32; byte (y + 8z) holds row (y,z),
 //          bit x = voxel x of that row.
-//   dist   uint8 per voxel, layout (x + 8z) * 8 + y: distance along x to
-//          the nearest obstacle of the same row, min(.,255); values >= d_max
-//          mean "none within the transform radius".  The 8 values of one
-//          y-column are contiguous (one load per block in pass y).
+//   g1     uint16 per voxel, layout (x + 8z) * 8 + y: squared distance
+//          along x to the nearest obstacle of the same row, clamped to D.
+//          The 8 values of one y-column are contiguous (one 16-byte load per
+//          block and lane in pass y).
 //   g2     uint16 per voxel, layout (x + 8y) * 8 + z: min over dy of
-//          dist(x, y+dy, z)^2 + dy^2, clamped to D (contiguous z-columns).
+//          g1(x, y+dy, z) + dy^2, clamped to D (contiguous z-columns).
 //   s      int32 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
 //   bmax   int32: max of s over the block (pruning bound for updates).
 //   flags  uint32: state bits (F_*).
@@ -35,7 +35,7 @@ enum : uint32_t {
     F_DILATED = 1u,  // block's R-neighbourhood is in the pool
     F_SEED = 2u,     // block holds a changed voxel in the current update
     F_DIRTY = 4u,    // block's values are recomputed in the current update
-    F_XS = 8u,       // dist recomputed in the current update
+    F_XS = 8u,       // g1 recomputed in the current update
     F_YS = 16u,      // g2 recomputed in the current update
     F_RAISE = 32u,   // marked by the raise front
     F_LOWER = 64u,   // marked by the lower front
@@ -60,7 +60,7 @@ struct Grid {
     int32_t* hvals;
     unsigned long long* bkey;
     uint32_t* occ;
-    uint8_t* dist;
+    uint16_t* g1;
     uint16_t* g2;
     int32_t* s;
     int32_t* bmax;
@@ -70,7 +70,7 @@ struct Grid {
     int32_t* list_zi;        // z work items
     int32_t* list_seed;      // update: seed blocks
     int32_t* list_dirty;     // update: dirty blocks
-    int32_t* list_xs;        // update: blocks whose dist is recomputed
+    int32_t* list_xs;        // update: blocks whose g1 is recomputed
     int32_t* list_ys;        // update: blocks whose g2 is recomputed
     int32_t* list_newdil;    // update: blocks that became obstacle blocks
     uint32_t* chg_add;       // [slot][16] voxels added in this update
@@ -80,6 +80,7 @@ struct Grid {
     int32_t* uvals;
     int32_t* upos;
     uint32_t* dummy;         // 256 x 64 words of write-only scratch rows
+    uint16_t* dblock;        // one block of D values (stands for absent blocks)
 };
 
 __host__ __device__ inline unsigned long long pack_key(int bx, int by, int bz) {

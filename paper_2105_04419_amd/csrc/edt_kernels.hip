@@ -4,21 +4,23 @@
 //   ingest          dense grid or leaf-block list -> occupancy bits + hash
 //   dilate (x,y,z)  region = obstacle blocks grown by R blocks (separable)
 //   items (y,z)     runs of consecutive region blocks, at most LRUN long
-//   pass_x          1-D distance along x from the occupancy bits
-//   pass_y          g2(y) = min_j dist(y+j)^2 + j^2        (lower envelope)
-//   pass_z          s(z)  = min(D, min_k g2(z+k) + k^2)    (lower envelope)
+//   pass_x          g1 = squared distance along x, from the occupancy bits
+//   pass_y          g2(y) = min_j g1(y+j) + j^2
+//   pass_z          s(z)  = min(D, min_k g2(z+k) + k^2)
 // The squared Euclidean distance splits into per-axis terms, so the three
 // passes give exactly Eq. 1; terms with an axis offset beyond d_max exceed D
-// and never change the clamped result.  The envelope passes follow the lower
-// envelope of parabolas (Felzenszwalb & Huttenlocher, cited by the paper as
-// the global transform), streamed with one lane per row and a ring of the
-// envelope sites that can still reach the next outputs.
+// and never change the clamped result.  For d_max <= 64 the y and z passes
+// take the windowed minimum directly, branch-free on packed 16-bit pairs;
+// for larger radii they follow the lower envelope of parabolas (Felzenszwalb
+// & Huttenlocher, cited by the paper as the global transform), streamed with
+// one lane per row and a ring of the sites that can still reach the next
+// outputs.
 //
 // Incremental transform (Algorithm 1's raise and lower waves, at block
 // granularity): changed voxels are the wave centres; a block is on the lower
 // front if some added voxel is closer to the block than its largest value,
 // and on the raise front if some removed voxel is no farther than its largest
-// value (only such blocks can change); the dist/g2 intermediates are kept
+// value (only such blocks can change); the g1/g2 intermediates are kept
 // current for every block and the marked blocks are recomputed exactly.
 #include "edt_dev.h"
 
@@ -311,8 +313,8 @@ __global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t ru
 }
 
 // ---------------------------------------------------------------------------
-// pass X: 1-D distance along x from the bits.  One wave per block,
-// lane = row (y + 8z).
+// pass X: squared 1-D distance along x from the bits, clamped to D.  One wave
+// per block, lane = row (y + 8z).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int list_counter) {
     __shared__ int32_t nb[72];
@@ -368,11 +370,13 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
         }
         int q = next;
         const int y = lane & 7, z = lane >> 3;
-        uint8_t* dst = g.dist + (int64_t)slot * 512 + 64 * z + y;
+        const int dmax = g.dmax;
+        uint16_t* dst = g.g1 + (int64_t)slot * 512 + 64 * z + y;
 #pragma unroll
         for (int x = 7; x >= 0; --x) {
             if ((c >> x) & 1u) q = x;
-            dst[8 * x] = (uint8_t)min(min(dl[x], q - x), 255);
+            const int d = min(min(dl[x], q - x), dmax);
+            dst[8 * x] = (uint16_t)(d * d);
         }
         __syncthreads();
     }
@@ -497,7 +501,7 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
 // memory operations form a fixed sequence and a step never waits for the
 // stores of the steps before it.
 //
-// pass Y: lane = x + 8z.  Reads dist (layout (x + 8z) * 8 + y: one 8-byte
+// pass Y: lane = x + 8z.  Reads g1 (layout (x + 8z) * 8 + y: one 16-byte
 // load per block and lane), writes g2 (layout (x + 8y) * 8 + z).
 struct PassYItem {
     const Grid& g;
@@ -506,11 +510,11 @@ struct PassYItem {
     int base, nb, o0, o1, qa, qb, dmax, D, lane, out_lane;
     uint16_t* dummy;
 
-    __device__ unsigned long long load(int j) const {
+    __device__ uint4 load(int j) const {
         const int jj = j < nb ? j : nb - 1;
-        return ((const unsigned long long*)g.dist)[(int64_t)sl[base + jj] * 64 + lane];
+        return ((const uint4*)g.g1)[(int64_t)sl[base + jj] * 64 + lane];
     }
-    __device__ void block(unsigned long long cur, int j) {
+    __device__ void block(uint4 cur, int j) {
         const int jo = (j * 8 - dmax) >> 3;
         const int32_t slo = (jo >= 0 && jo < nb) ? sl[base + jo] : -1;
         const int32_t shi = (jo + 1 >= 0 && jo + 1 < nb) ? sl[base + jo + 1] : -1;
@@ -518,8 +522,9 @@ struct PassYItem {
         for (int k = 0; k < 8; ++k) {
             const int q = 8 * j + k;
             if (q >= qa && q < qb) {
-                const int d = (int)((cur >> (8 * k)) & 0xffu);
-                if (d < dmax) env.push(q, d * d, max(o0, q - dmax));
+                const uint32_t wk = k < 2 ? cur.x : (k < 4 ? cur.y : (k < 6 ? cur.z : cur.w));
+                const int f = (int)((wk >> (16 * (k & 1))) & 0xffffu);
+                if (f < D) env.push(q, f, max(o0, q - dmax));
             }
             const int i = q - dmax;
             const bool out = i >= o0 && i < o1;
@@ -556,7 +561,7 @@ __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int
         PassYItem P{g, sl, env, R - hb, nb, o0, o1, max(0, o0 - g.dmax), min(8 * nb, o1 + g.dmax),
                     g.dmax, g.D, lane, (lane & 7) * 8 + (lane >> 3), dummy};
         const int jlo = P.qa >> 3, jhi = (o1 + g.dmax - 1) >> 3;
-        unsigned long long A = P.load(jlo), B = P.load(jlo + 1);
+        uint4 A = P.load(jlo), B = P.load(jlo + 1);
         for (int j = jlo; j <= jhi; j += 2) {
             P.block(A, j);
             A = P.load(j + 2);
@@ -642,6 +647,127 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
             if (j + 1 > jhi) break;
             P.block(B, j + 1);
             B = P.load(j + 3);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// windowed minimum along y or z for d_max <= 64 (M = ceil(d_max / 8) blocks)
+// ---------------------------------------------------------------------------
+// out(i) = min over |k| <= 8M - 1 of in(i + k) + k^2 taken directly: offsets
+// beyond d_max - 1 give in + k^2 >= D and change nothing, so the window is
+// rounded up to whole blocks.  One lane per row; a wave produces two output
+// blocks at a time, with outputs i and i + 8 packed in one 32-bit register
+// (16-bit halves, values <= D + k^2 < 2^16 for d_max <= 64), so each
+// candidate costs one packed add and one packed min for two outputs.  The
+// 2M + 2 input blocks of the window stay in registers and slide by two blocks
+// per step; absent blocks read a block of D.  Loads and stores are
+// unconditional (halo outputs go to a scratch row) so the loop has a fixed
+// memory-op sequence.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline uint32_t word_of(const uint4& v, int w) {
+    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+template <int M, int AXIS>
+__global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, int item_counter,
+                                                 uint32_t runflag) {
+    constexpr int NW = 2 * M + 2;        // window blocks
+    constexpr int K = 8 * M - 1;         // largest offset
+    __shared__ int32_t sl[96];
+    __shared__ uint8_t mem[96];
+    const int lane = threadIdx.x;
+    const int64_t nit = g.cnt[item_counter];
+    const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
+    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 64;
+    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
+    const int out_lane = AXIS == 1 ? (lane & 7) * 8 + (lane >> 3) : lane;
+    for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
+        const int32_t s0 = items[it];
+        int bx, by, bz;
+        unpack_key(g.bkey[s0], bx, by, bz);
+        int hb, len, ha;
+        resolve_run(g, sl, mem, bx, by, bz, AXIS, runflag, hb, len, ha);
+        const int base = M - hb;          // sl index of item block 0
+        const int nb = hb + len + ha;
+        auto blk = [&](int b) -> const uint4* {
+            return (b >= 0 && b < nb) ? (const uint4*)src + (int64_t)sl[base + b] * 64 + lane
+                                      : (const uint4*)g.dblock + lane;
+        };
+        uint4 W[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) W[w] = *blk(hb - M + w);
+        for (int ob = hb; ob < hb + len; ob += 2) {
+            const uint4 N0 = *blk(ob + M + 2), N1 = *blk(ob + M + 3);
+            u16x2 acc[8];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
+#pragma unroll
+            for (int b = 0; b + 1 < NW; ++b) {
+#pragma unroll
+                for (int z = 0; z < 8; ++z) {
+                    // input pair (position p, position p + 8), p = 8 (b - M) + z
+                    const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
+                    const u16x2 P = as_u16x2(
+                        __builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
+                    const int p = 8 * (b - M) + z;
+                    // all sums first, then all minima: independent instructions
+                    // back to back instead of each min waiting on its add
+                    u16x2 t[8];
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) {
+                        const int k = p - o;
+                        const unsigned short kk = (unsigned short)(k * k);
+                        if (k >= -K && k <= K) t[o] = P + (u16x2){kk, kk};
+                    }
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) {
+                        const int k = p - o;
+                        if (k >= -K && k <= K) acc[o] = __builtin_elementwise_min(acc[o], t[o]);
+                    }
+                }
+            }
+            // outputs: block ob from the low halves, block ob + 1 from the high halves
+            const bool has1 = ob + 1 < hb + len;
+            const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[base + ob]);
+            const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
+            if (AXIS == 1) {
+                uint16_t* d0 = g.g2 + (int64_t)slot0 * 512;
+                uint16_t* d1 = has1 ? g.g2 + (int64_t)slot1 * 512 : (uint16_t*)dummy;
+                const int ol = has1 ? out_lane : lane;
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const uint32_t v = as_u32(acc[o]);
+                    d0[out_lane + 64 * o] = (uint16_t)(v & 0xffffu);
+                    d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
+                }
+            } else {
+                int32_t* d0 = g.s + (int64_t)slot0 * 512;
+                int32_t* d1 = has1 ? g.s + (int64_t)slot1 * 512 : (int32_t*)dummy;
+                int m0 = 0, m1 = 0;
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const uint32_t v = as_u32(acc[o]);
+                    const int v0 = (int)(v & 0xffffu), v1 = (int)(v >> 16);
+                    d0[lane + 64 * o] = v0;
+                    d1[(has1 ? 64 * o : 0) + lane] = v1;
+                    m0 = max(m0, v0);
+                    m1 = max(m1, v1);
+                }
+                m0 = wave_max(m0);
+                m1 = wave_max(m1);
+                g.bmax[slot0] = m0;
+                int32_t* b1 = has1 ? g.bmax + slot1 : (int32_t*)dummy + 64;
+                *b1 = m1;
+            }
+#pragma unroll
+            for (int w = 0; w + 2 < NW; ++w) W[w] = W[w + 2];
+            W[NW - 2] = N0;
+            W[NW - 1] = N1;
         }
         __syncthreads();
     }
@@ -764,9 +890,11 @@ __global__ void __launch_bounds__(64) k_init_new(Grid g, int first_counter) {
             g.chg_add[s * 16 + lane] = 0u;
             g.chg_rem[s * 16 + lane] = 0u;
         }
-        ((unsigned long long*)(g.dist + s * 512))[lane] = ~0ull;
         const uint32_t d2 = (uint32_t)g.D | ((uint32_t)g.D << 16);
-        for (int k = lane; k < 256; k += 64) ((uint32_t*)(g.g2 + s * 512))[k] = d2;
+        for (int k = lane; k < 256; k += 64) {
+            ((uint32_t*)(g.g1 + s * 512))[k] = d2;
+            ((uint32_t*)(g.g2 + s * 512))[k] = d2;
+        }
         for (int k = lane; k < 512; k += 64) g.s[s * 512 + k] = g.D;
         if (lane == 0) g.bmax[s] = g.D;
     }
@@ -892,10 +1020,10 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
            box_gap2(zmn, zmx, 8 * bz, 8 * bz + 7);
 }
 
-// Raise / lower fronts around every seed and the dist/g2 recompute sets.
+// Raise / lower fronts around every seed and the g1/g2 recompute sets.
 //   lower: some added voxel a has |box(B) - a|^2 < bmax(B)   (a value can drop)
 //   raise: some removed voxel r has |box(B) - r|^2 <= bmax(B) and < D
-//   xs:    blocks within R along x of a seed (their dist can change)
+//   xs:    blocks within R along x of a seed (their g1 can change)
 //   ys:    blocks within R in x and y of a seed (their g2 can change)
 __global__ void k_upd_mark(Grid g) {
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
