@@ -12,7 +12,11 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
   incremental    p50 / p99 latency of edt_update over simulated range scans
                  along the tunnels, plus an incremental == global check;
   clearance      clearance cost forward + backward on the 64x64x32 map field
-                 with 4096 x 64 waypoints, points per second.
+                 with 4096 x 64 waypoints, points per second;
+  batched        64 dense room maps (sides 32..256, d_max 24): autotuned
+                 fused persistent launch vs per-map launches;
+  dense_small    the 64x64x32 boxes map (d_max 20), microseconds per
+                 global transform.
 """
 from __future__ import annotations
 
@@ -219,6 +223,60 @@ def bench_clearance(args, torch, np):
     return {"points": n, "median_ms": round(med, 4), "pts_per_s": n / (med * 1e-3)}
 
 
+def bench_batch(args, torch, np):
+    import workloads
+    from paper_2105_04419_amd import FUSED, PER_MAP, DEFAULT_TUNE, Batch, autotune
+    maps = workloads.batch_maps(args.seed)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
+    occ = b.pack(maps)
+    out = torch.empty(b.total, dtype=torch.int32, device=b.device)
+    best, results = autotune.tune(b, occ, out, reps=3)
+    reps = 10
+    t_tuned = autotune.time_config(b, occ, out, best, reps)
+    t_default = autotune.time_config(b, occ, out, DEFAULT_TUNE, reps)
+    per_map_cfg = dict(DEFAULT_TUNE, lrun=best["lrun"])
+    t_per_map = autotune.time_config(b, occ, out, per_map_cfg, reps, mode=PER_MAP)
+    fused = b.run(occ, mode=FUSED, tune=best)
+    per_map = b.run(occ, mode=PER_MAP, tune=per_map_cfg)
+    nvox = b.total
+    return {
+        "maps": len(maps),
+        "voxels": nvox,
+        "d_max": 24,
+        "fused_ms": round(t_tuned, 4),
+        "fused_voxels_per_s": nvox / (t_tuned * 1e-3),
+        "fused_default_schedule_ms": round(t_default, 4),
+        "per_map_ms": round(t_per_map, 4),
+        "per_map_voxels_per_s": nvox / (t_per_map * 1e-3),
+        "speedup_fused_vs_per_map": round(t_per_map / t_tuned, 3),
+        "tuned_schedule": best,
+        "search_space": {k: v for k, v in autotune.SPACE.items()},
+        "trials": len(results),
+        "fused_equals_per_map": bool(torch.equal(fused, per_map)),
+    }
+
+
+def bench_dense_small(args, torch, np):
+    import workloads
+    from paper_2105_04419_amd import Field
+    occ = torch.from_numpy(workloads.dense_boxes(0)).cuda()
+    f = Field((64, 64, 32), 20)
+    for _ in range(5):
+        f.global_(occ)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = 50
+    e0.record()
+    for _ in range(n):
+        f.global_(occ)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    return {"workload": "dense 64x64x32 boxes map, d_max 20", "us_per_transform": round(ms * 1e3, 2),
+            "voxels_per_s": 64 * 64 * 32 / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +340,10 @@ def main():
         out["incremental"] = bench_incremental(g, args, torch, np)
         log("[bench] clearance 4096 x 64")
         out["clearance"] = bench_clearance(args, torch, np)
+        log("[bench] batched: 64 dense maps, autotuned fused launch vs per-map launches")
+        out["batched"] = bench_batch(args, torch, np)
+        log("[bench] dense 64x64x32 global transform")
+        out["dense_small"] = bench_dense_small(args, torch, np)
     print(json.dumps(out), flush=True)
 
 

@@ -168,6 +168,53 @@ edt_status edt_timing_begin(edt_ctx* ctx, int32_t n_calls);
 edt_status edt_timing_read(edt_ctx* ctx, float* ms, int32_t* n_recorded);
 
 /* ------------------------------------------------------------------------ */
+/* Batched global transform of many dense maps (same definition as edt_global
+ * per map), with 1 <= d_max <= 64.  Map i occupies bytes
+ * d_occ[occ_offset .. occ_offset + nx*ny*nz) (grid layout) and its field is
+ * written to d_out[out_offset .. out_offset + nx*ny*nz) (int32, grid layout);
+ * sides 1 .. 4096.  Callers own d_occ, d_out and the workspace. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;
+    int64_t occ_offset;
+    int64_t out_offset;
+} edt_batch_map;
+
+/* Schedule of a batched run (edt_batch_run; NULL = defaults {8, 8, 4, 0}):
+ *   lrun          blocks per work item along y and z (1 .. 64)
+ *   waves_per_cu  waves resident per compute unit (0 = default, <= 64)
+ *   chunk         work items taken per queue atomic (1 .. 1024)
+ *   schedule      0 = dynamic queue, 1 = static stride                      */
+typedef struct {
+    int32_t lrun;
+    int32_t waves_per_cu;
+    int32_t chunk;
+    int32_t schedule;
+} edt_tune;
+
+/* EDT_BATCH_FUSED: one persistent cooperative launch for all maps and
+ * passes, a grid-wide barrier between the x, y and z passes.
+ * EDT_BATCH_PER_MAP: three launches (x, y, z) per map. */
+typedef enum { EDT_BATCH_FUSED = 0, EDT_BATCH_PER_MAP = 1 } edt_batch_mode;
+
+typedef struct edt_batch edt_batch;
+
+/* Device workspace bytes for the maps, or a negative edt_status. */
+int64_t edt_batch_workspace_bytes(const edt_batch_map* maps, int32_t n_maps, int32_t d_max);
+
+/* Prepares a batch over the caller's workspace (256-byte aligned, at least
+ * edt_batch_workspace_bytes).  `maps` is a host array, copied; the call
+ * synchronises `stream` once. */
+edt_status edt_batch_create(const edt_batch_map* maps, int32_t n_maps, int32_t d_max,
+                            void* d_ws, int64_t ws_bytes, void* stream, edt_batch** out);
+
+/* Transforms every map of the batch (mode: edt_batch_mode). */
+edt_status edt_batch_run(edt_batch* batch, const uint8_t* d_occ, int32_t* d_out,
+                         int32_t mode, const edt_tune* tune, void* stream);
+
+edt_status edt_batch_destroy(edt_batch* batch);
+
+/* ------------------------------------------------------------------------ */
 /* Clearance cost on a dense field (paper section III, Eq. 2, clearance
  * term, in the squared-hinge form  c(p) = max(0, margin - d(p))^2).
  *   d_s        int32[nz][ny][nx] squared voxel distances (e.g. from

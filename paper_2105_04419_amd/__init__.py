@@ -20,7 +20,7 @@ import os
 import torch
 
 __all__ = ["Field", "ClearanceCost", "clearance_cost", "lib", "EdtError", "LIB_PATH",
-           "batch_global"]
+           "Batch", "batch_global", "FUSED", "PER_MAP"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libedt.so")
 
@@ -56,6 +56,17 @@ class EdtStats(ctypes.Structure):
                 ("d_max", ctypes.c_int32)]
 
 
+class EdtBatchMap(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("occ_offset", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64)]
+
+
+class EdtTune(ctypes.Structure):
+    _fields_ = [("lrun", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -84,6 +95,11 @@ def lib():
         "edt_timing_begin": ([vp, i32], ctypes.c_int),
         "edt_timing_read": ([vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)],
                             ctypes.c_int),
+        "edt_batch_workspace_bytes": ([ctypes.POINTER(EdtBatchMap), i32, i32], i64),
+        "edt_batch_create": ([ctypes.POINTER(EdtBatchMap), i32, i32, vp, i64, vp,
+                              ctypes.POINTER(vp)], ctypes.c_int),
+        "edt_batch_run": ([vp, vp, vp, i32, ctypes.POINTER(EdtTune), vp], ctypes.c_int),
+        "edt_batch_destroy": ([vp], ctypes.c_int),
         "edt_clearance_fwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp], ctypes.c_int),
         "edt_clearance_bwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp, vp],
                               ctypes.c_int),
@@ -283,5 +299,83 @@ def clearance_cost(s, wp, h: float = 0.2, margin: float = 1.0):
     return ClearanceCost.apply(s, wp, h, margin)
 
 
-def batch_global(*args, **kwargs):
-    raise NotImplementedError("batched transform is not built yet")
+# ---------------------------------------------------------------------------
+# batched dense maps
+# ---------------------------------------------------------------------------
+FUSED, PER_MAP = 0, 1
+DEFAULT_TUNE = {"lrun": 8, "waves_per_cu": 8, "chunk": 4, "schedule": 0}
+
+
+class Batch:
+    """Many dense maps transformed together.  Occupancy of all maps lives in
+    one flat uint8 tensor, the fields in one flat int32 tensor; map i uses
+    the slice [offsets[i], offsets[i] + nx*ny*nz) of both (grid layout, x
+    fastest)."""
+
+    def __init__(self, shapes, d_max: int, device=None, stream=None):
+        self.shapes = [tuple(int(v) for v in sh) for sh in shapes]   # (nx, ny, nz)
+        self.d_max = int(d_max)
+        self.offsets = []
+        off = 0
+        for nx, ny, nz in self.shapes:
+            self.offsets.append(off)
+            off += nx * ny * nz
+        self.total = off
+        n = len(self.shapes)
+        self._maps = (EdtBatchMap * n)(*[EdtBatchMap(nx, ny, nz, 0, o, o) for (nx, ny, nz), o
+                                         in zip(self.shapes, self.offsets)])
+        L = lib()
+        nbytes = L.edt_batch_workspace_bytes(self._maps, n, self.d_max)
+        if nbytes < 0:
+            raise EdtError("edt_batch_workspace_bytes", int(nbytes))
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check("edt_batch_create", L.edt_batch_create(self._maps, n, self.d_max, _ptr(self.workspace),
+                                                      int(nbytes), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().edt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, maps) -> torch.Tensor:
+        """Concatenate per-map (nz, ny, nx) uint8 arrays into the flat input."""
+        flat = torch.empty(self.total, dtype=torch.uint8, device=self.device)
+        for m, o, (nx, ny, nz) in zip(maps, self.offsets, self.shapes):
+            t = m if isinstance(m, torch.Tensor) else torch.from_numpy(m)
+            flat[o:o + nx * ny * nz] = t.reshape(-1).to(self.device)
+        return flat
+
+    def unpack(self, out: torch.Tensor):
+        return [out[o:o + nx * ny * nz].view(nz, ny, nx)
+                for o, (nx, ny, nz) in zip(self.offsets, self.shapes)]
+
+    def run(self, occ_flat: torch.Tensor, out: torch.Tensor | None = None, mode: int = FUSED,
+            tune: dict | None = None, stream=None) -> torch.Tensor:
+        occ_flat = _dev_tensor(occ_flat, torch.uint8, (self.total,))
+        if out is None:
+            out = torch.empty(self.total, dtype=torch.int32, device=self.device)
+        out = _dev_tensor(out, torch.int32, (self.total,))
+        t = dict(DEFAULT_TUNE)
+        if tune:
+            t.update(tune)
+        tt = EdtTune(t["lrun"], t["waves_per_cu"], t["chunk"], t["schedule"])
+        _check("edt_batch_run", lib().edt_batch_run(self._h, _ptr(occ_flat), _ptr(out), int(mode),
+                                                    ctypes.byref(tt), _stream(stream)))
+        return out
+
+
+def batch_global(maps, d_max: int, mode: int = FUSED, tune: dict | None = None):
+    """Transform a list of dense (nz, ny, nx) uint8 maps; returns int32 fields."""
+    shapes = [(m.shape[2], m.shape[1], m.shape[0]) for m in maps]
+    b = Batch(shapes, d_max)
+    out = b.run(b.pack(maps), mode=mode, tune=tune)
+    return b.unpack(out)

@@ -27,7 +27,7 @@ struct edt_ctx {
     int ev_used;        // calls recorded so far
     int cap;            // envelope ring capacity (entries per lane)
     size_t env_lds;     // dynamic LDS bytes of the envelope passes
-    int64_t hcap;       // block hash capacity
+    int64_t tcap;       // tile hash capacity
     int64_t ucap;       // update hash capacity
     int64_t stats_host[C_N];
 };
@@ -41,13 +41,13 @@ int64_t next_pow2(int64_t v) {
 }
 
 struct Layout {
-    int64_t max_blocks, max_changes, hcap, ucap;
+    int64_t max_blocks, max_changes, tcap, ucap;
     int64_t off[32];
     int64_t total;
 };
 
 enum {
-    O_HKEYS, O_HVALS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
+    O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
     O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_N
 };
@@ -72,10 +72,15 @@ bool layout_of(const edt_config* c, Layout* L) {
     if (mc > (1 << 28)) return false;
     L->max_blocks = mb;
     L->max_changes = mc;
-    L->hcap = next_pow2(mb * 2 < 64 ? 64 : mb * 2);
+    // tiles of 8x8x8 blocks: at most one per tile of the extent and one per block
+    const int64_t ntx = (nbx + 7) / 8, nty = (nby + 7) / 8, ntz = (nbz + 7) / 8;
+    int64_t tiles = ntx * nty * ntz;
+    if (tiles > mb) tiles = mb;
+    L->tcap = next_pow2(tiles * 2 < 64 ? 64 : tiles * 2);
+    if (L->tcap > (1 << 24)) return false;
     L->ucap = next_pow2(mc * 2 < 64 ? 64 : mc * 2);
     const int64_t sz[O_N] = {
-        L->hcap * 8, L->hcap * 4, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
+        L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024, 1024};
@@ -213,7 +218,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     edt_ctx* c = (edt_ctx*)calloc(1, sizeof(edt_ctx));
     if (!c) return EDT_ERR_CAPACITY;
     c->cfg = *cfg;
-    c->hcap = L.hcap;
+    c->tcap = L.tcap;
     c->ucap = L.ucap;
     char* b = (char*)d_ws;
     Grid& g = c->g;
@@ -223,11 +228,11 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.D = cfg->d_max * cfg->d_max;
     g.R = (cfg->d_max + 7) / 8;
     g.max_blocks = (int)L.max_blocks;
-    g.hmask = (uint32_t)(L.hcap - 1);
+    g.tmask = (uint32_t)(L.tcap - 1);
     g.umask = (uint32_t)(L.ucap - 1);
     g.max_changes = (int)L.max_changes;
-    g.hkeys = (unsigned long long*)(b + L.off[O_HKEYS]);
-    g.hvals = (int32_t*)(b + L.off[O_HVALS]);
+    g.tkeys = (unsigned long long*)(b + L.off[O_TKEYS]);
+    g.tslots = (int32_t*)(b + L.off[O_TSLOTS]);
     g.bkey = (unsigned long long*)(b + L.off[O_BKEY]);
     g.occ = (uint32_t*)(b + L.off[O_OCC]);
     g.g1 = (uint16_t*)(b + L.off[O_G1]);
@@ -276,8 +281,8 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     }
 
     hipStream_t st = S(stream);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.hcap, 256, 4096)), dim3(256), 0, st, g.hkeys,
-                       L.hcap, KEY_EMPTY);
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(L.tcap * 128, 256, 4096)), dim3(256), 0, st,
+                       g, L.tcap);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.ukeys,
                        L.ucap, KEY_EMPTY);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
@@ -349,8 +354,8 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         return EDT_ERR_ARG;
     }
     mark(c, 0, st);
-    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->hcap, 256, 4096)), dim3(256), 0, st, g,
-                       c->hcap);
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
+                       g, c->tcap);
     if (map->kind == EDT_MAP_DENSE) {
         hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
                            map->d_occ);

@@ -1,0 +1,477 @@
+// edt_batch.hip -- global transform of many dense maps in one launch.
+//
+// Every map goes through the same three separable passes as the single-map
+// transform (x from the occupancy bytes, then the windowed minimum along y
+// and z; d_max <= 64).  Maps are dense, so a block is addressed by its
+// position in the map's block grid and no region growth is needed.
+//
+// Work items (per map, in map order; maps are ordered largest first):
+//   phase 0 (x)  a strip of 8 blocks along x at (by, bz)
+//   phase 1 (y)  a run of up to `lrun` blocks along y at (bx, bz)
+//   phase 2 (z)  a run of up to `lrun` blocks along z at (bx, by)
+// FUSED runs all three phases of all maps in one cooperative persistent
+// launch: waves take items from a per-phase queue (chunks of `chunk` items
+// through one atomic, or a static stride), and a grid-wide barrier separates
+// the phases, so a map's y pass starts only after every x item is written.
+// PER_MAP launches the same phase code three times per map.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "edt.h"
+#include "edt_win.h"
+
+namespace {
+
+using namespace edt;
+
+struct MapDev {
+    int nx, ny, nz;
+    int nbx, nby, nbz;
+    int nxr;                 // strips of 8 blocks along x
+    int pad;
+    int64_t occ_off;         // bytes into the occupancy input
+    int64_t out_off;         // int32 elements into the output
+    int64_t blk_off;         // blocks into g1 / g2
+};
+
+struct BArgs {
+    const MapDev* maps;
+    const int32_t* pref;     // [3][n_maps + 1] item prefix sums (phase-major)
+    int32_t* queues;         // [3][n_maps + 1] grab counters
+    const uint8_t* occ;
+    int32_t* out;
+    uint16_t* g1;
+    uint16_t* g2;
+    const uint16_t* dblock;
+    uint32_t* dummy;
+    int n_maps;
+    int dmax, D;
+    int lrun, chunk, schedule;
+};
+
+// map whose item range holds global item index i (binary search)
+__device__ inline int map_of(const int32_t* pref, int n_maps, int i) {
+    int lo = 0, hi = n_maps;   // pref[lo] <= i < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int bx, int by, int bz,
+                                       const uint16_t* dblock, int lane) {
+    if (bx < 0 || by < 0 || bz < 0 || bx >= m.nbx || by >= m.nby || bz >= m.nbz)
+        return (const uint4*)dblock + lane;
+    const int64_t b = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx + bx;
+    return (const uint4*)arr + b * 64 + lane;
+}
+
+// phase 0: squared distance along x, from the occupancy bytes of one row
+// window per lane (lane = y + 8z), for a strip of 8 blocks.  The row window
+// (blocks bx0-M .. bx0+7+M) becomes a bit string; the nearest obstacle on
+// each side of a voxel is found with count-leading/trailing-zeros on the
+// 64-bit words around it (d_max <= 64, so two words per side suffice).
+template <int M>
+__device__ void item_x(const BArgs& a, const MapDev& m, int li) {
+    constexpr int NBITS = 64 + 16 * M;
+    constexpr int NW64 = (NBITS + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int bx0 = 8 * (li % m.nxr);
+    const int rest = li / m.nxr;
+    const int by = rest % m.nby, bz = rest / m.nby;
+    const int Y = 8 * by + (lane & 7), Z = 8 * bz + (lane >> 3);
+    const bool row_ok = Y < m.ny && Z < m.nz;
+    const int xs = 8 * (bx0 - M);
+    const uint8_t* row = a.occ + m.occ_off + ((int64_t)Z * m.ny + Y) * m.nx;
+    unsigned long long w[NW64 + 1];
+#pragma unroll
+    for (int k = 0; k <= NW64; ++k) w[k] = 0ull;
+#pragma unroll
+    for (int k = 0; k < NBITS; ++k) {
+        const int x = xs + k;
+        if (row_ok && x >= 0 && x < m.nx && row[x]) w[k >> 6] |= 1ull << (k & 63);
+    }
+    const int dmax = a.dmax;
+    const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int bx = bx0 + j;
+        uint16_t* dst = bx < m.nbx ? a.g1 + (brow + bx) * 512 + 64 * (lane >> 3) + (lane & 7)
+                                   : (uint16_t*)a.dummy + lane;
+        const int dstep = bx < m.nbx ? 8 : 0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const int k = 8 * M + 8 * j + x;            // bit of this voxel
+            const int q = k >> 6, r = k & 63;
+            // left: highest set bit <= k
+            const unsigned long long l0 = w[q] & (r == 63 ? ~0ull : ((1ull << (r + 1)) - 1ull));
+            int dl = 1000;
+            if (l0) dl = r - (63 - __clzll(l0));
+            else if (q >= 1 && w[q - 1]) dl = r + 1 + __clzll(w[q - 1]);
+            // right: lowest set bit >= k
+            const unsigned long long r0 = w[q] >> r;
+            int dr = 1000;
+            if (r0) dr = __ffsll(r0) - 1;
+            else if (q + 1 <= NW64 && w[q + 1]) dr = (64 - r) + __ffsll(w[q + 1]) - 1;
+            const int d = min(min(dl, dr), dmax);
+            dst[dstep * x] = (uint16_t)(d * d);
+        }
+    }
+}
+
+// phase 1: windowed minimum along y (lane = x + 8z), g1 -> g2
+template <int M>
+__device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
+    const int lane = threadIdx.x & 63;
+    const int nseg = (m.nby + a.lrun - 1) / a.lrun;
+    const int bx = li % m.nbx;
+    const int rest = li / m.nbx;
+    const int bz = rest % m.nbz, seg = rest / m.nbz;
+    (void)nseg;
+    const int by0 = seg * a.lrun;
+    const int len = min(a.lrun, m.nby - by0);
+    const int out_lane = (lane & 7) * 8 + (lane >> 3);
+    uint16_t* dummy = (uint16_t*)(a.dummy + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 255) * 64);
+    auto blk = [&](int b) -> uint4 { return *blk_ptr(a.g1, m, bx, b, bz, a.dblock, lane); };
+    auto emit = [&](int ob, const u16x2* acc, bool has1) {
+        const int64_t b0 = m.blk_off + ((int64_t)bz * m.nby + ob) * m.nbx + bx;
+        uint16_t* d0 = a.g2 + b0 * 512;
+        uint16_t* d1 = has1 ? a.g2 + (b0 + m.nbx) * 512 : dummy;
+        const int ol = has1 ? out_lane : lane;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t v = as_u32(acc[o]);
+            d0[out_lane + 64 * o] = (uint16_t)(v & 0xffffu);
+            d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
+        }
+    };
+    window_min<M>(by0, len, Dp, blk, emit);
+}
+
+// phase 2: windowed minimum along z (lane = x + 8y), g2 -> dense int32 field
+template <int M>
+__device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
+    const int lane = threadIdx.x & 63;
+    const int bx = li % m.nbx;
+    const int rest = li / m.nbx;
+    const int by = rest % m.nby, seg = rest / m.nby;
+    const int bz0 = seg * a.lrun;
+    const int len = min(a.lrun, m.nbz - bz0);
+    const int X = 8 * bx + (lane & 7), Y = 8 * by + (lane >> 3);
+    const bool col_ok = X < m.nx && Y < m.ny;
+    int32_t* dummy = (int32_t*)(a.dummy + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 255) * 64);
+    int32_t* col = a.out + m.out_off + (int64_t)Y * m.nx + X;
+    const int64_t zstride = (int64_t)m.nx * m.ny;
+    auto blk = [&](int b) -> uint4 { return *blk_ptr(a.g2, m, bx, by, b, a.dblock, lane); };
+    auto emit = [&](int ob, const u16x2* acc, bool has1) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t v = as_u32(acc[o]);
+            const int z0 = 8 * ob + o, z1 = 8 * ob + 8 + o;
+            int32_t* p0 = (col_ok && z0 < m.nz) ? col + z0 * zstride : dummy + lane;
+            int32_t* p1 = (col_ok && has1 && z1 < m.nz) ? col + z1 * zstride : dummy + lane;
+            *p0 = (int)(v & 0xffffu);
+            *p1 = (int)(v >> 16);
+        }
+    };
+    window_min<M>(bz0, len, Dp, blk, emit);
+}
+
+template <int M>
+__device__ inline void run_item(const BArgs& a, int phase, int gi, uint32_t Dp) {
+    const int* pref = a.pref + phase * (a.n_maps + 1);
+    const int mi = map_of(pref, a.n_maps, gi);
+    const MapDev m = a.maps[mi];
+    const int li = gi - pref[mi];
+    if (phase == 0) item_x<M>(a, m, li);
+    else if (phase == 1) item_y<M>(a, m, li, Dp);
+    else item_z<M>(a, m, li, Dp);
+}
+
+// Items [lo, hi) of `phase`; one wave per item.  Dynamic schedule: a wave
+// takes `chunk` items per atomic on the phase's counter (cidx); static: wave
+// w takes items lo + w, lo + w + nwaves, ...
+template <int M>
+__device__ void run_phase(const BArgs& a, int phase, int lo, int hi, int cidx) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int wid = blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * wpb;
+    const uint32_t Dp = (uint32_t)a.D | ((uint32_t)a.D << 16);
+    if (a.schedule == 0) {
+        for (;;) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&a.queues[cidx], a.chunk);
+            base = __shfl(base, 0) + lo;
+            if (base >= hi) break;
+            const int end = min(base + a.chunk, hi);
+            for (int i = base; i < end; ++i) run_item<M>(a, phase, i, Dp);
+        }
+    } else {
+        for (int i = lo + wid; i < hi; i += nwaves) run_item<M>(a, phase, i, Dp);
+    }
+}
+
+// FUSED: phases 0..2 of all maps, grid barrier between phases.
+template <int M>
+__global__ void __launch_bounds__(256) k_batch_fused(BArgs a) {
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    const int n = a.n_maps;
+    for (int phase = 0; phase < 3; ++phase) {
+        const int* pref = a.pref + phase * (n + 1);
+        run_phase<M>(a, phase, pref[0], pref[n], phase * (n + 1) + n);
+        if (phase < 2) grid.sync();
+    }
+}
+
+// PER_MAP: one phase of one map.
+template <int M>
+__global__ void __launch_bounds__(256) k_batch_phase(BArgs a, int phase, int map) {
+    const int* pref = a.pref + phase * (a.n_maps + 1);
+    run_phase<M>(a, phase, pref[map], pref[map + 1], phase * (a.n_maps + 1) + map);
+}
+
+__global__ void k_batch_prefix(const MapDev* maps, int n, int lrun, int32_t* pref, int32_t* queues) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int acc[3] = {0, 0, 0};
+        for (int i = 0; i <= n; ++i) {
+            for (int p = 0; p < 3; ++p) pref[p * (n + 1) + i] = acc[p];
+            if (i == n) break;
+            const MapDev m = maps[i];
+            acc[0] += m.nxr * m.nby * m.nbz;
+            acc[1] += m.nbx * m.nbz * ((m.nby + lrun - 1) / lrun);
+            acc[2] += m.nbx * m.nby * ((m.nbz + lrun - 1) / lrun);
+        }
+    }
+    for (int i = threadIdx.x; i < 3 * (n + 1); i += blockDim.x) queues[i] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+struct BLayout {
+    int64_t off_maps, off_pref, off_queues, off_g1, off_g2, off_dblock, off_dummy, total;
+    int64_t nblocks;
+};
+
+bool blayout(const edt_batch_map* maps, int n, int dmax, BLayout* L) {
+    if (!maps || n < 1 || n > (1 << 16) || dmax < 1 || dmax > 64) return false;
+    int64_t nb = 0;
+    for (int i = 0; i < n; ++i) {
+        const edt_batch_map& m = maps[i];
+        if (m.nx < 1 || m.ny < 1 || m.nz < 1 || m.nx > 4096 || m.ny > 4096 || m.nz > 4096)
+            return false;
+        if (m.occ_offset < 0 || m.out_offset < 0) return false;
+        nb += (int64_t)((m.nx + 7) / 8) * ((m.ny + 7) / 8) * ((m.nz + 7) / 8);
+    }
+    if (nb > (1ll << 26)) return false;
+    int64_t o = 0;
+    L->off_maps = o; o += align256((int64_t)n * sizeof(MapDev));
+    L->off_pref = o; o += align256((int64_t)3 * (n + 1) * 4);
+    L->off_queues = o; o += align256((int64_t)3 * (n + 1) * 4);
+    L->off_g1 = o; o += align256(nb * 1024);
+    L->off_g2 = o; o += align256(nb * 1024);
+    L->off_dblock = o; o += 1024;
+    L->off_dummy = o; o += align256(256 * 64 * 4 + 1024);
+    L->total = o;
+    L->nblocks = nb;
+    return true;
+}
+
+int grid_cap(int64_t work, int cap) {
+    int64_t g = work < 1 ? 1 : work;
+    return (int)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+struct edt_batch {
+    int n;
+    int dmax;
+    int M;
+    BLayout L;
+    char* ws;
+    MapDev* host_maps;       // in processing order
+    int64_t* map_items[3];   // per map item counts at the last lrun (host copy)
+    int last_lrun;
+    int cus;
+};
+
+namespace {
+
+template <int M>
+edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu,
+                        hipStream_t st) {
+    if (mode == EDT_BATCH_FUSED) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<M>, 256, 0) !=
+            hipSuccess)
+            return EDT_ERR_HIP;
+        const int wgs_per_cu = waves_per_cu > 0 ? (waves_per_cu + 3) / 4 : 2;
+        const int g = b->cus * (wgs_per_cu < per_cu ? wgs_per_cu : per_cu);
+        if (g < 1) return EDT_ERR_HIP;
+        void* args[] = {(void*)&a};
+        if (hipLaunchCooperativeKernel((const void*)k_batch_fused<M>, dim3(g), dim3(256), args, 0,
+                                       st) != hipSuccess)
+            return EDT_ERR_HIP;
+        return EDT_OK;
+    }
+    // PER_MAP: three launches per map, each sized to the map's items
+    for (int mi = 0; mi < b->n; ++mi) {
+        const MapDev& m = b->host_maps[mi];
+        const int64_t items[3] = {
+            (int64_t)m.nxr * m.nby * m.nbz,
+            (int64_t)m.nbx * m.nbz * ((m.nby + a.lrun - 1) / a.lrun),
+            (int64_t)m.nbx * m.nby * ((m.nbz + a.lrun - 1) / a.lrun)};
+        for (int phase = 0; phase < 3; ++phase) {
+            const int waves = grid_cap(items[phase], b->cus * (waves_per_cu > 0 ? waves_per_cu : 8));
+            hipLaunchKernelGGL(k_batch_phase<M>, dim3((waves + 3) / 4), dim3(256), 0, st, a, phase,
+                               mi);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t edt_batch_workspace_bytes(const edt_batch_map* maps, int32_t n_maps, int32_t d_max) {
+    BLayout L;
+    if (!blayout(maps, n_maps, d_max, &L)) return EDT_ERR_ARG;
+    return L.total;
+}
+
+edt_status edt_batch_create(const edt_batch_map* maps, int32_t n_maps, int32_t d_max, void* d_ws,
+                            int64_t ws_bytes, void* stream, edt_batch** out) {
+    if (!out) return EDT_ERR_ARG;
+    *out = nullptr;
+    BLayout L;
+    if (!blayout(maps, n_maps, d_max, &L) || !d_ws || ((uintptr_t)d_ws & 255)) return EDT_ERR_ARG;
+    if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
+    edt_batch* b = (edt_batch*)calloc(1, sizeof(edt_batch));
+    if (!b) return EDT_ERR_CAPACITY;
+    b->host_maps = (MapDev*)calloc((size_t)n_maps, sizeof(MapDev));
+    if (!b->host_maps) {
+        free(b);
+        return EDT_ERR_CAPACITY;
+    }
+    b->n = n_maps;
+    b->dmax = d_max;
+    b->M = (d_max + 7) / 8;
+    b->L = L;
+    b->ws = (char*)d_ws;
+    // processing order: largest map first (longest-processing-time first)
+    int* order = (int*)malloc(sizeof(int) * (size_t)n_maps);
+    for (int i = 0; i < n_maps; ++i) order[i] = i;
+    for (int i = 1; i < n_maps; ++i) {   // insertion sort by volume, descending
+        const int v = order[i];
+        const int64_t vol = (int64_t)maps[v].nx * maps[v].ny * maps[v].nz;
+        int j = i - 1;
+        while (j >= 0 && (int64_t)maps[order[j]].nx * maps[order[j]].ny * maps[order[j]].nz < vol) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = v;
+    }
+    int64_t blk = 0;
+    for (int k = 0; k < n_maps; ++k) {
+        const edt_batch_map& s = maps[order[k]];
+        MapDev& m = b->host_maps[k];
+        m.nx = s.nx; m.ny = s.ny; m.nz = s.nz;
+        m.nbx = (s.nx + 7) / 8; m.nby = (s.ny + 7) / 8; m.nbz = (s.nz + 7) / 8;
+        m.nxr = (m.nbx + 7) / 8;
+        m.occ_off = s.occ_offset;
+        m.out_off = s.out_offset;
+        m.blk_off = blk;
+        blk += (int64_t)m.nbx * m.nby * m.nbz;
+    }
+    free(order);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        free(b->host_maps);
+        free(b);
+        return EDT_ERR_HIP;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(b->ws + L.off_maps, b->host_maps, sizeof(MapDev) * (size_t)n_maps,
+                       hipMemcpyHostToDevice, st) != hipSuccess) {
+        free(b->host_maps);
+        free(b);
+        return EDT_ERR_HIP;
+    }
+    const uint32_t D = (uint32_t)(d_max * d_max);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (uint32_t*)(b->ws + L.off_dblock),
+                       (int64_t)256, D | (D << 16));
+    if (hipStreamSynchronize(st) != hipSuccess) {   // the host map table may go away now
+        free(b->host_maps);
+        free(b);
+        return EDT_ERR_HIP;
+    }
+    b->last_lrun = 0;
+    *out = b;
+    return EDT_OK;
+}
+
+edt_status edt_batch_destroy(edt_batch* b) {
+    if (!b) return EDT_ERR_ARG;
+    free(b->host_maps);
+    free(b);
+    return EDT_OK;
+}
+
+edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int32_t mode,
+                         const edt_tune* tune, void* stream) {
+    if (!b || !d_occ || !d_out) return EDT_ERR_ARG;
+    if (mode != EDT_BATCH_FUSED && mode != EDT_BATCH_PER_MAP) return EDT_ERR_ARG;
+    edt_tune t = {8, 8, 4, 0};
+    if (tune) t = *tune;
+    if (t.lrun < 1 || t.lrun > 64 || t.chunk < 1 || t.chunk > 1024 || t.waves_per_cu < 0 ||
+        t.waves_per_cu > 64 || (t.schedule != 0 && t.schedule != 1))
+        return EDT_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const BLayout& L = b->L;
+    BArgs a;
+    a.maps = (const MapDev*)(b->ws + L.off_maps);
+    a.pref = (const int32_t*)(b->ws + L.off_pref);
+    a.queues = (int32_t*)(b->ws + L.off_queues);
+    a.occ = d_occ;
+    a.out = d_out;
+    a.g1 = (uint16_t*)(b->ws + L.off_g1);
+    a.g2 = (uint16_t*)(b->ws + L.off_g2);
+    a.dblock = (const uint16_t*)(b->ws + L.off_dblock);
+    a.dummy = (uint32_t*)(b->ws + L.off_dummy);
+    a.n_maps = b->n;
+    a.dmax = b->dmax;
+    a.D = b->dmax * b->dmax;
+    a.lrun = t.lrun;
+    a.chunk = t.chunk;
+    a.schedule = t.schedule;
+    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(256), 0, st, a.maps, b->n, t.lrun,
+                       (int32_t*)a.pref, a.queues);
+    if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
+    switch (b->M) {
+        case 1: return launch_batch<1>(b, a, mode, t.waves_per_cu, st);
+        case 2: return launch_batch<2>(b, a, mode, t.waves_per_cu, st);
+        case 3: return launch_batch<3>(b, a, mode, t.waves_per_cu, st);
+        case 4: return launch_batch<4>(b, a, mode, t.waves_per_cu, st);
+        case 5: return launch_batch<5>(b, a, mode, t.waves_per_cu, st);
+        case 6: return launch_batch<6>(b, a, mode, t.waves_per_cu, st);
+        case 7: return launch_batch<7>(b, a, mode, t.waves_per_cu, st);
+        case 8: return launch_batch<8>(b, a, mode, t.waves_per_cu, st);
+        default: return EDT_ERR_ARG;
+    }
+}
+
+}  // extern "C"

@@ -1,9 +1,12 @@
 // edt_dev.h -- device-side data structures of libedt (gfx950).
 //
-// Storage: a pool of 8x8x8 leaf blocks addressed through an open-addressing
-// hash table keyed by block coordinates.  This replaces the paper's VDB
-// B+-tree (section IV-A): both give O(1) access to sparse leaves and treat
-// every absent leaf as the background value D (Algorithm 1, Initialize).
+// Storage: a pool of 8x8x8 leaf blocks under a two-level index, the GPU
+// counterpart of the paper's VDB tree (section IV-A): a device hash table
+// keyed by tile coordinates (a tile = 8x8x8 blocks = 64^3 voxels) whose
+// probe position is the tile's id, and per tile a dense table of 512 pool
+// slots (-1 = absent).  Both give O(1) access to sparse leaves and treat every
+// absent leaf as the background value D (Algorithm 1, Initialize); the tile
+// tables are small enough to stay in L2, so neighbour lookups are cheap.
 //
 // Per pool slot (one leaf block):
 //   occ    512 occupancy bits, 16 x uint32; byte (y + 8z) holds row (y,z),
@@ -53,11 +56,11 @@ struct Grid {
     int nbx, nby, nbz;       // extent (blocks)
     int dmax, D, R;          // radius, D = dmax^2, R = ceil(dmax / 8)
     int max_blocks;
-    uint32_t hmask;          // hash capacity - 1
+    uint32_t tmask;          // tile hash capacity - 1
     uint32_t umask;          // update-dedupe hash capacity - 1
     int max_changes;
-    unsigned long long* hkeys;
-    int32_t* hvals;
+    unsigned long long* tkeys;   // tile hash keys
+    int32_t* tslots;             // [tile position][512] pool slot of each block
     unsigned long long* bkey;
     uint32_t* occ;
     uint16_t* g1;
@@ -115,9 +118,27 @@ __device__ inline int32_t hfind(const unsigned long long* keys, const int32_t* v
     return -1;
 }
 
+// Table position of key, or -1 (read-only probe).
+__device__ inline int32_t hpos(const unsigned long long* keys, uint32_t mask,
+                               unsigned long long key) {
+    uint32_t h = hash_of(key, mask);
+    for (uint32_t i = 0; i <= mask; ++i) {
+        const unsigned long long k = keys[h];
+        if (k == key) return (int32_t)h;
+        if (k == KEY_EMPTY) return -1;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+__device__ inline int block_local(int bx, int by, int bz) {
+    return (bx & 7) + 8 * (by & 7) + 64 * (bz & 7);
+}
+
 __device__ inline int32_t find_block(const Grid& g, int bx, int by, int bz) {
     if (bx < 0 || by < 0 || bz < 0 || bx >= g.nbx || by >= g.nby || bz >= g.nbz) return -1;
-    return hfind(g.hkeys, g.hvals, g.hmask, pack_key(bx, by, bz));
+    const int32_t t = hpos(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3));
+    return t < 0 ? -1 : g.tslots[(int64_t)t * 512 + block_local(bx, by, bz)];
 }
 
 // Find-or-insert: returns the table position, or -1 when the table is full.
@@ -142,6 +163,23 @@ __device__ inline int32_t hinsert(unsigned long long* keys, uint32_t mask,
 
 __device__ inline void set_error(const Grid& g, int code) {
     atomicCAS(&g.cnt[C_ERR], 0, code);
+}
+
+constexpr int32_t SLOT_PENDING = -2;   // block claimed, pool slot not yet written
+
+// Find-or-insert of block (bx, by, bz) (inside the extent): returns its entry
+// in the tile tables, or -1 when the tile hash is full.  The one thread that
+// turns the entry from -1 into SLOT_PENDING gets *created = true and must
+// write the pool slot (claim_slots); others only learn that the block exists.
+__device__ inline int64_t insert_block(const Grid& g, int bx, int by, int bz, bool* created) {
+    bool tnew;
+    const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
+    *created = false;
+    if (t < 0) return -1;
+    const int64_t e = (int64_t)t * 512 + block_local(bx, by, bz);
+    if (__hip_atomic_load(&g.tslots[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) return e;
+    *created = atomicCAS(&g.tslots[e], -1, SLOT_PENDING) == -1;
+    return e;
 }
 
 // Wave-aggregated append of `pred` lanes to list[] (ballot + mbcnt + one

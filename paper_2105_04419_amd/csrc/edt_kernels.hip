@@ -23,6 +23,7 @@
 // value (only such blocks can change); the g1/g2 intermediates are kept
 // current for every block and the marked blocks are recomputed exactly.
 #include "edt_dev.h"
+#include "edt_win.h"
 
 namespace edt {
 
@@ -42,9 +43,12 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 // Global transform start: empty block table, counters reset (the error word
 // is kept until it is read).
-__global__ void k_begin_global(Grid g, int64_t hcap) {
+__global__ void k_begin_global(Grid g, int64_t tcap) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int64_t i = tid; i < hcap; i += (int64_t)gridDim.x * blockDim.x) g.hkeys[i] = KEY_EMPTY;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < tcap; i += stride) g.tkeys[i] = KEY_EMPTY;
+    int4* ts = (int4*)g.tslots;
+    for (int64_t i = tid; i < tcap * 128; i += stride) ts[i] = make_int4(-1, -1, -1, -1);
     if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
 }
 
@@ -69,21 +73,21 @@ __device__ inline void snapshot_at_exit(const Grid& g, int dst, int dst2 = -1) {
     }
 }
 
-// Pool slots for the lanes that just placed a key at table position h: one
+// Pool slots for the lanes that just created a block at tile entry e: one
 // counter atomic per wave.  Returns the slot, or -1 (not created / pool full).
-__device__ inline int32_t claim_slots(const Grid& g, bool created, int32_t h,
+__device__ inline int32_t claim_slots(const Grid& g, bool created, int64_t e,
                                       unsigned long long key, uint32_t flags) {
     const int idx = wave_append(created, &g.cnt[C_NBLK]);
     if (!created) return -1;
     if (idx >= g.max_blocks) {
-        g.hvals[h] = -1;
+        g.tslots[e] = -1;
         set_error(g, -3 /* EDT_ERR_CAPACITY */);
         g.cnt[C_ABORT] = 1;
         return -1;
     }
     g.bkey[idx] = key;
     g.flags[idx] = flags;
-    g.hvals[h] = idx;
+    g.tslots[e] = idx;
     return idx;
 }
 
@@ -137,14 +141,14 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
         const bool any = __ballot(bytes[j] != 0) != 0;
         if (lane == j) mine = any && (bx0 + j < g.nbx);
     }
-    int32_t h = -1;
+    int64_t e = -1;
     bool created = false;
     const unsigned long long key = pack_key(bx0 + lane, by, bz);
     if (mine) {
-        h = hinsert(g.hkeys, g.hmask, key, &created);
-        if (h < 0) set_error(g, -3);
+        e = insert_block(g, bx0 + lane, by, bz, &created);
+        if (e < 0) set_error(g, -3);
     }
-    const int32_t slot = claim_slots(g, created, h, key, F_DILATED);
+    const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
     const int ndil = __popcll(__ballot(slot >= 0));
     if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     uint8_t* occ8 = (uint8_t*)g.occ;
@@ -198,16 +202,16 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_insert(Grid g, const int32
                 mine = ok && any;
             }
         }
-        int32_t h = -1;
+        int64_t e = -1;
         bool created = false;
         unsigned long long key = 0;
         if (mine) {
             const int64_t i = i0 + lane;
             key = pack_key(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
-            h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) set_error(g, -3);
+            e = insert_block(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], &created);
+            if (e < 0) set_error(g, -3);
         }
-        const int32_t slot = claim_slots(g, created, h, key, F_DILATED);
+        const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
         const int ndil = __popcll(__ballot(slot >= 0));
         if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     }
@@ -262,12 +266,12 @@ __global__ void k_dilate_axis(Grid g, int axis) {
         const int lim = axis == 0 ? g.nbx : (axis == 1 ? g.nby : g.nbz);
         const unsigned long long key = pack_key(c[0], c[1], c[2]);
         bool created = false;
-        int32_t h = -1;
+        int64_t e = -1;
         if (c[axis] >= 0 && c[axis] < lim) {
-            h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) set_error(g, -3);
+            e = insert_block(g, c[0], c[1], c[2], &created);
+            if (e < 0) set_error(g, -3);
         }
-        claim_slots(g, created, h, key, 0u);
+        claim_slots(g, created, e, key, 0u);
     }
     snapshot_at_exit(g, C_SNAP);
 }
@@ -653,31 +657,11 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
 }
 
 // ---------------------------------------------------------------------------
-// windowed minimum along y or z for d_max <= 64 (M = ceil(d_max / 8) blocks)
+// windowed minimum along y or z for d_max <= 64 (core in edt_win.h)
 // ---------------------------------------------------------------------------
-// out(i) = min over |k| <= 8M - 1 of in(i + k) + k^2 taken directly: offsets
-// beyond d_max - 1 give in + k^2 >= D and change nothing, so the window is
-// rounded up to whole blocks.  One lane per row; a wave produces two output
-// blocks at a time, with outputs i and i + 8 packed in one 32-bit register
-// (16-bit halves, values <= D + k^2 < 2^16 for d_max <= 64), so each
-// candidate costs one packed add and one packed min for two outputs.  The
-// 2M + 2 input blocks of the window stay in registers and slide by two blocks
-// per step; absent blocks read a block of D.  Loads and stores are
-// unconditional (halo outputs go to a scratch row) so the loop has a fixed
-// memory-op sequence.
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
-__device__ inline uint32_t word_of(const uint4& v, int w) {
-    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
-}
-
 template <int M, int AXIS>
 __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, int item_counter,
                                                  uint32_t runflag) {
-    constexpr int NW = 2 * M + 2;        // window blocks
-    constexpr int K = 8 * M - 1;         // largest offset
     __shared__ int32_t sl[96];
     __shared__ uint8_t mem[96];
     const int lane = threadIdx.x;
@@ -694,45 +678,13 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
         resolve_run(g, sl, mem, bx, by, bz, AXIS, runflag, hb, len, ha);
         const int base = M - hb;          // sl index of item block 0
         const int nb = hb + len + ha;
-        auto blk = [&](int b) -> const uint4* {
-            return (b >= 0 && b < nb) ? (const uint4*)src + (int64_t)sl[base + b] * 64 + lane
-                                      : (const uint4*)g.dblock + lane;
+        auto blk = [&](int b) -> uint4 {
+            const uint4* p = (b >= 0 && b < nb)
+                                 ? (const uint4*)src + (int64_t)sl[base + b] * 64 + lane
+                                 : (const uint4*)g.dblock + lane;
+            return *p;
         };
-        uint4 W[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) W[w] = *blk(hb - M + w);
-        for (int ob = hb; ob < hb + len; ob += 2) {
-            const uint4 N0 = *blk(ob + M + 2), N1 = *blk(ob + M + 3);
-            u16x2 acc[8];
-#pragma unroll
-            for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
-#pragma unroll
-            for (int b = 0; b + 1 < NW; ++b) {
-#pragma unroll
-                for (int z = 0; z < 8; ++z) {
-                    // input pair (position p, position p + 8), p = 8 (b - M) + z
-                    const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
-                    const u16x2 P = as_u16x2(
-                        __builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
-                    const int p = 8 * (b - M) + z;
-                    // all sums first, then all minima: independent instructions
-                    // back to back instead of each min waiting on its add
-                    u16x2 t[8];
-#pragma unroll
-                    for (int o = 0; o < 8; ++o) {
-                        const int k = p - o;
-                        const unsigned short kk = (unsigned short)(k * k);
-                        if (k >= -K && k <= K) t[o] = P + (u16x2){kk, kk};
-                    }
-#pragma unroll
-                    for (int o = 0; o < 8; ++o) {
-                        const int k = p - o;
-                        if (k >= -K && k <= K) acc[o] = __builtin_elementwise_min(acc[o], t[o]);
-                    }
-                }
-            }
-            // outputs: block ob from the low halves, block ob + 1 from the high halves
-            const bool has1 = ob + 1 < hb + len;
+        auto emit = [&](int ob, const u16x2* acc, bool has1) {
             const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[base + ob]);
             const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
             if (AXIS == 1) {
@@ -764,11 +716,8 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
                 int32_t* b1 = has1 ? g.bmax + slot1 : (int32_t*)dummy + 64;
                 *b1 = m1;
             }
-#pragma unroll
-            for (int w = 0; w + 2 < NW; ++w) W[w] = W[w + 2];
-            W[NW - 2] = N0;
-            W[NW - 1] = N1;
-        }
+        };
+        window_min<M>(hb, len, Dp, blk, emit);
         __syncthreads();
     }
 }
@@ -864,17 +813,18 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         bool created = false;
-        int32_t h = -1;
+        int64_t e = -1;
         unsigned long long key = 0;
         if (state[i] && upd_winner(g, i)) {
-            key = pack_key(xyz[3 * i] >> 3, xyz[3 * i + 1] >> 3, xyz[3 * i + 2] >> 3);
-            h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) {
+            const int bx = xyz[3 * i] >> 3, by = xyz[3 * i + 1] >> 3, bz = xyz[3 * i + 2] >> 3;
+            key = pack_key(bx, by, bz);
+            e = insert_block(g, bx, by, bz, &created);
+            if (e < 0) {
                 set_error(g, -3);
                 g.cnt[C_ABORT] = 1;
             }
         }
-        claim_slots(g, created, h, key, 0u);
+        claim_slots(g, created, e, key, 0u);
     }
 }
 
@@ -965,13 +915,13 @@ __global__ void k_upd_dilate(Grid g) {
         by += (o / w) % w - R;
         bz += o / (w * w) - R;
         bool created = false;
-        int32_t h = -1;
+        int64_t e = -1;
         const unsigned long long key = pack_key(bx, by, bz);
         if (bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz) {
-            h = hinsert(g.hkeys, g.hmask, key, &created);
-            if (h < 0) set_error(g, -3);
+            e = insert_block(g, bx, by, bz, &created);
+            if (e < 0) set_error(g, -3);
         }
-        claim_slots(g, created, h, key, 0u);
+        claim_slots(g, created, e, key, 0u);
     }
 }
 

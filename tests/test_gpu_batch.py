@@ -1,0 +1,84 @@
+"""Batched transform of many dense maps: the fused persistent launch, the
+per-map launches and the CPU oracle agree bit for bit on every map, for
+every schedule the autotuner may pick."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_2105_04419_amd import FUSED, PER_MAP, Batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    assert torch.cuda.is_available()
+    oracle.build(force=False)
+
+
+def small_maps(seed, n, lo, hi):
+    rng = np.random.default_rng(seed)
+    maps = []
+    for _ in range(n):
+        nx, ny, nz = (int(v) for v in rng.integers(lo, hi + 1, 3))
+        occ = (rng.random((nz, ny, nx)) < rng.uniform(0.002, 0.05)).astype(np.uint8)
+        occ |= workloads.room_layout(rng, nx, ny, nz, min_room=8)
+        maps.append(occ)
+    return maps
+
+
+def check(b, maps, out, dmax, what):
+    for i, (m, got) in enumerate(zip(maps, b.unpack(out))):
+        ref = oracle.edt_separable(m, dmax)
+        g = got.cpu().numpy()
+        if not np.array_equal(g, ref):
+            bad = np.argwhere(g != ref)
+            raise AssertionError(f"{what}: map {i} shape {m.shape}: {len(bad)} mismatches, "
+                                 f"first {bad[0]}")
+
+
+@pytest.mark.parametrize("dmax", [1, 5, 8, 13, 24, 33, 64])
+def test_small_batch_all_modes(dmax):
+    maps = small_maps(dmax, 7, 3, 70)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], dmax)
+    occ = b.pack(maps)
+    f = b.run(occ, mode=FUSED)
+    check(b, maps, f, dmax, "fused")
+    p = b.run(occ, mode=PER_MAP)
+    assert torch.equal(f, p)
+
+
+@pytest.mark.parametrize("tune", [
+    {"lrun": 1, "chunk": 1, "schedule": 0, "waves_per_cu": 4},
+    {"lrun": 3, "chunk": 7, "schedule": 0, "waves_per_cu": 16},
+    {"lrun": 16, "chunk": 64, "schedule": 1, "waves_per_cu": 8},
+    {"lrun": 64, "chunk": 2, "schedule": 1, "waves_per_cu": 1},
+])
+def test_schedules_are_bit_identical(tune):
+    maps = small_maps(11, 9, 8, 90)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
+    occ = b.pack(maps)
+    ref = b.run(occ, mode=PER_MAP)
+    check(b, maps, ref, 24, "per_map")
+    assert torch.equal(b.run(occ, mode=FUSED, tune=tune), ref)
+    assert torch.equal(b.run(occ, mode=PER_MAP, tune=tune), ref)
+
+
+def test_full_batch_of_64_room_maps():
+    """64 maps with sides U{32..256}, density U(1%, 30%) plus room layouts,
+    d_max 24: fused == per-map == oracle for every map."""
+    maps = workloads.batch_maps(0)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
+    occ = b.pack(maps)
+    f = b.run(occ, mode=FUSED)
+    p = b.run(occ, mode=PER_MAP)
+    assert torch.equal(f, p)
+    check(b, maps, f, 24, "fused 64 maps")
+
+
+def test_rejects_large_radius():
+    from paper_2105_04419_amd import EdtError
+    with pytest.raises(EdtError):
+        Batch([(8, 8, 8)], 65)
