@@ -49,7 +49,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TFLAG, O_TLIST, O_OLIST, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -83,7 +83,8 @@ bool layout_of(const edt_config* c, Layout* L) {
         L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
-        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024, 1024};
+        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024, 1024,
+        L->tcap * 64, L->tcap * 4, L->tcap * 4, L->tcap * 4};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -176,11 +177,12 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
 
 edt_status dilate_region(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
-    // few workgroups: each kernel's last workgroup leaves the final block
-    // count in C_SNAP (one counter atomic per workgroup)
-    const int tg = grid_for((int64_t)g.max_blocks * 2 * g.R, 256, 512);
-    for (int axis = 0; axis < 3; ++axis)
-        hipLaunchKernelGGL(k_dilate_axis, dim3(tg), dim3(256), 0, st, g, axis);
+    const int TR = (g.R + 7) / 8, w = 2 * TR + 1;
+    hipLaunchKernelGGL(k_tile_neighbours, dim3(grid_for(c->tcap * w * w * w, 256, 1024)), dim3(256),
+                       0, st, g);
+    const int E = 8 + 2 * g.R;
+    const size_t lds = (size_t)w * w * w * 64 + E * E + E * 8 + 64;
+    hipLaunchKernelGGL(k_tile_dilate, dim3(grid_for(c->tcap, 1, 4096)), dim3(64), lds, st, g);
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -256,6 +258,10 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.upos = (int32_t*)(b + L.off[O_UPOS]);
     g.dummy = (uint32_t*)(b + L.off[O_DUMMY]);
     g.dblock = (uint16_t*)(b + L.off[O_DBLOCK]);
+    g.tobst = (uint32_t*)(b + L.off[O_TOBST]);
+    g.tflag = (int32_t*)(b + L.off[O_TFLAG]);
+    g.tlist = (int32_t*)(b + L.off[O_TLIST]);
+    g.olist = (int32_t*)(b + L.off[O_OLIST]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -359,7 +365,6 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
     if (map->kind == EDT_MAP_DENSE) {
         hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
                            map->d_occ);
-        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP);
         hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
@@ -369,9 +374,9 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         mark(c, 2, st);
     } else {
         const int64_t n = map->n_blocks;
-        // runs even for n == 0: its exit records the block count for the region growth
-        hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 64, 4096)), dim3(64), 0, st, g,
-                           map->d_block_xyz, map->d_block_occ, n);
+        if (n > 0)
+            hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 256, 4096)), dim3(256), 0,
+                               st, g, map->d_block_xyz, map->d_block_occ, n);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;

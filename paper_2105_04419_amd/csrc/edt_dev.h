@@ -48,7 +48,7 @@ enum : uint32_t {
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_SNAP, C_SNAP2,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
-    C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_N
+    C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_NOTILE, C_N
 };
 
 struct Grid {
@@ -61,6 +61,10 @@ struct Grid {
     int max_changes;
     unsigned long long* tkeys;   // tile hash keys
     int32_t* tslots;             // [tile position][512] pool slot of each block
+    uint32_t* tobst;             // [tile position][16] blocks holding an obstacle (global)
+    int32_t* tflag;              // [tile position] tile holds an obstacle block (global)
+    int32_t* tlist;              // tile positions in use (global transform)
+    int32_t* olist;              // tile positions holding obstacle blocks
     unsigned long long* bkey;
     uint32_t* occ;
     uint16_t* g1;
@@ -171,10 +175,12 @@ constexpr int32_t SLOT_PENDING = -2;   // block claimed, pool slot not yet writt
 // in the tile tables, or -1 when the tile hash is full.  The one thread that
 // turns the entry from -1 into SLOT_PENDING gets *created = true and must
 // write the pool slot (claim_slots); others only learn that the block exists.
-__device__ inline int64_t insert_block(const Grid& g, int bx, int by, int bz, bool* created) {
+__device__ inline int64_t insert_block(const Grid& g, int bx, int by, int bz, bool* created,
+                                      bool* tile_created = nullptr) {
     bool tnew;
     const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
     *created = false;
+    if (tile_created) *tile_created = t >= 0 && tnew;
     if (t < 0) return -1;
     const int64_t e = (int64_t)t * 512 + block_local(bx, by, bz);
     if (__hip_atomic_load(&g.tslots[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) return e;

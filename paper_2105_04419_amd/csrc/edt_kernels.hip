@@ -2,7 +2,7 @@
 //
 // Global transform (the field of Eq. 1, section III, limited to d_max):
 //   ingest          dense grid or leaf-block list -> occupancy bits + hash
-//   dilate (x,y,z)  region = obstacle blocks grown by R blocks (separable)
+//   tile dilation   region = obstacle blocks grown by R blocks (per tile)
 //   items (y,z)     runs of consecutive region blocks, at most LRUN long
 //   pass_x          g1 = squared distance along x, from the occupancy bits
 //   pass_y          g2(y) = min_j g1(y+j) + j^2
@@ -49,28 +49,31 @@ __global__ void k_begin_global(Grid g, int64_t tcap) {
     for (int64_t i = tid; i < tcap; i += stride) g.tkeys[i] = KEY_EMPTY;
     int4* ts = (int4*)g.tslots;
     for (int64_t i = tid; i < tcap * 128; i += stride) ts[i] = make_int4(-1, -1, -1, -1);
+    for (int64_t i = tid; i < tcap * 16; i += stride) g.tobst[i] = 0u;
+    for (int64_t i = tid; i < tcap; i += stride) g.tflag[i] = 0;
     if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
+}
+
+// Record a new tile (global transform) and, for obstacle blocks, the block in
+// its tile's obstacle mask (the tile goes to the obstacle-tile list once).
+__device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bool obstacle) {
+    const int t = e >= 0 ? (int)(e >> 9) : -1;
+    const int j = wave_append(tile_created, &g.cnt[C_NTILE]);
+    if (tile_created) g.tlist[j] = t;
+    bool first = false;
+    if (obstacle && e >= 0) {
+        const int local = (int)(e & 511);
+        atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
+        first = atomicOr(&g.tflag[t], 1) == 0;
+    }
+    const int k = wave_append(first, &g.cnt[C_NOTILE]);
+    if (first) g.olist[k] = t;
 }
 
 __global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
 
 __device__ inline int32_t load_count(const Grid& g, int idx) {
     return __hip_atomic_load(&g.cnt[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by every workgroup at its end: the last one to finish records the
-// final block count in cnt[dst] (the range the next kernel works on).
-__device__ inline void snapshot_at_exit(const Grid& g, int dst, int dst2 = -1) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&g.cnt[C_DONE], 1) == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
-            const int32_t n = load_count(g, C_NBLK);
-            g.cnt[dst] = n;
-            if (dst2 >= 0) g.cnt[dst2] = n;
-            g.cnt[C_DONE] = 0;
-        }
-    }
 }
 
 // Pool slots for the lanes that just created a block at tile entry e: one
@@ -142,12 +145,13 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
         if (lane == j) mine = any && (bx0 + j < g.nbx);
     }
     int64_t e = -1;
-    bool created = false;
+    bool created = false, tnew = false;
     const unsigned long long key = pack_key(bx0 + lane, by, bz);
     if (mine) {
-        e = insert_block(g, bx0 + lane, by, bz, &created);
+        e = insert_block(g, bx0 + lane, by, bz, &created, &tnew);
         if (e < 0) set_error(g, -3);
     }
+    note_tile(g, tnew, e, mine);
     const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
     const int ndil = __popcll(__ballot(slot >= 0));
     if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
@@ -183,39 +187,54 @@ __device__ inline uint32_t block_row_bits(const Grid& g, const int32_t* xyz,
     return b;
 }
 
-// Each wave takes 64 consecutive input blocks: the wave reads them one by one
-// (coalesced 512 B), lane k keeps the verdict for block k, then the lanes
-// insert their blocks in parallel with one slot-counter atomic per wave.
-__global__ void __launch_bounds__(64) k_ingest_blocks_insert(Grid g, const int32_t* xyz,
-                                                             const uint8_t* data, int64_t n) {
-    const int lane = threadIdx.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
+// One thread per input block: it reads the block's 512 bytes, decides whether
+// it holds an obstacle inside the extent, and inserts it (one slot-counter
+// atomic per wave).
+__global__ void __launch_bounds__(256) k_ingest_blocks_insert(Grid g, const int32_t* xyz,
+                                                              const uint8_t* data, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - threadIdx.x < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         bool mine = false;
-        const int cnt = (int)min((int64_t)64, n - i0);
-        for (int k = 0; k < cnt; ++k) {
-            int bx, by, bz;
-            bool ok;
-            const uint32_t b = block_row_bits(g, xyz, data, i0 + k, lane, bx, by, bz, ok);
-            const bool any = __ballot(b != 0) != 0;
-            if (lane == k) {
-                if (!ok) set_error(g, -2 /* EDT_ERR_RANGE */);
-                mine = ok && any;
+        int bx = 0, by = 0, bz = 0;
+        if (i < n) {
+            bx = xyz[3 * i];
+            by = xyz[3 * i + 1];
+            bz = xyz[3 * i + 2];
+            const bool ok = bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz;
+            if (!ok) set_error(g, -2 /* EDT_ERR_RANGE */);
+            if (ok) {
+                const int xr = g.nx - 8 * bx;
+                const unsigned long long xm =
+                    xr >= 8 ? ~0ull : 0x0101010101010101ull * ((1u << xr) - 1u);
+                const uint4* p = (const uint4*)(data + i * 512);
+                bool any = false;
+#pragma unroll 8
+                for (int r = 0; r < 32; ++r) {       // 16 bytes = rows 2r and 2r + 1
+                    const uint4 v = p[r];
+                    const int y0 = 8 * by + ((2 * r) & 7), z0 = 8 * bz + ((2 * r) >> 3);
+                    const int y1 = 8 * by + ((2 * r + 1) & 7);
+                    const unsigned long long lo = ((unsigned long long)v.y << 32) | v.x;
+                    const unsigned long long hi = ((unsigned long long)v.w << 32) | v.z;
+                    // a nonzero byte marks an occupied voxel; xm keeps the x < nx bytes
+                    const bool r0 = z0 < g.nz && y0 < g.ny && (lo & (xm * 0xffull)) != 0;
+                    const bool r1 = z0 < g.nz && y1 < g.ny && (hi & (xm * 0xffull)) != 0;
+                    any = any || r0 || r1;
+                }
+                mine = any;
             }
         }
         int64_t e = -1;
-        bool created = false;
-        unsigned long long key = 0;
+        bool created = false, tnew = false;
+        const unsigned long long key = pack_key(bx, by, bz);
         if (mine) {
-            const int64_t i = i0 + lane;
-            key = pack_key(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
-            e = insert_block(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], &created);
+            e = insert_block(g, bx, by, bz, &created, &tnew);
             if (e < 0) set_error(g, -3);
         }
+        note_tile(g, tnew, e, mine);
         const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
         const int ndil = __popcll(__ballot(slot >= 0));
-        if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
+        if (__lane_id() == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     }
-    snapshot_at_exit(g, C_SNAP);
 }
 
 // phase 2 (after zeroing the occupancy of the new slots): OR the bits in.
@@ -248,32 +267,121 @@ __global__ void k_zero_occ(Grid g, int first_counter) {
 }
 
 // ---------------------------------------------------------------------------
-// region growth: every slot < snapshot inserts its +-R neighbours on `axis`
+// region growth on tiles: every block within R blocks (Chebyshev) of an
+// obstacle block joins the pool.  TR = ceil(R / 8) tiles of neighbourhood.
 // ---------------------------------------------------------------------------
-__global__ void k_dilate_axis(Grid g, int axis) {
-    const int R = g.R;
-    const int64_t n0 = g.cnt[C_SNAP];
-    const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
-    const int64_t total = n * 2 * R;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+// Every tile within TR tiles of an obstacle tile must exist.
+__global__ void k_tile_neighbours(Grid g) {
+    const int TR = (g.R + 7) >> 3, w = 2 * TR + 1, w3 = w * w * w;
+    const int ntx = (g.nbx + 7) >> 3, nty = (g.nby + 7) >> 3, ntz = (g.nbz + 7) >> 3;
+    const int64_t total = (int64_t)g.cnt[C_NOTILE] * w3;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - threadIdx.x < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int slot = (int)(i / (2 * R));
-        const int k = (int)(i % (2 * R));
-        const int off = k < R ? -(k + 1) : (k - R + 1);
-        int c[3];
-        unpack_key(g.bkey[slot], c[0], c[1], c[2]);
-        c[axis] += off;
-        const int lim = axis == 0 ? g.nbx : (axis == 1 ? g.nby : g.nbz);
-        const unsigned long long key = pack_key(c[0], c[1], c[2]);
-        bool created = false;
-        int64_t e = -1;
-        if (c[axis] >= 0 && c[axis] < lim) {
-            e = insert_block(g, c[0], c[1], c[2], &created);
-            if (e < 0) set_error(g, -3);
+        bool tnew = false;
+        int32_t t = -1;
+        if (i < total) {
+            const int ot = g.olist[i / w3];
+            const int o = (int)(i % w3);
+            int tx, ty, tz;
+            unpack_key(g.tkeys[ot], tx, ty, tz);
+            tx += o % w - TR;
+            ty += (o / w) % w - TR;
+            tz += o / (w * w) - TR;
+            if (tx >= 0 && ty >= 0 && tz >= 0 && tx < ntx && ty < nty && tz < ntz) {
+                t = hinsert(g.tkeys, g.tmask, pack_key(tx, ty, tz), &tnew);
+                if (t < 0) set_error(g, -3);
+            }
         }
-        claim_slots(g, created, e, key, 0u);
+        const int j = wave_append(tnew, &g.cnt[C_NTILE]);
+        if (tnew) g.tlist[j] = t;
     }
-    snapshot_at_exit(g, C_SNAP);
+}
+
+// One workgroup per tile: OR the obstacle masks of the tile neighbourhood
+// shifted by -R..R along x, then y, then z (separable Chebyshev dilation on
+// bit rows in LDS) and create the missing blocks of the dilated mask.
+__global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
+    extern __shared__ uint32_t sm[];
+    const int R = g.R, TR = (R + 7) >> 3, w = 2 * TR + 1, NN = w * w * w;
+    const int E = 8 + 2 * R;                 // rows of the dilation window per axis
+    uint32_t* nmask = sm;                    // [NN][16] neighbour obstacle masks
+    uint8_t* s1 = (uint8_t*)(sm + NN * 16);  // [E][E]  x-dilated rows (y', z')
+    uint8_t* s2 = s1 + E * E;                // [E][8]  y-dilated rows (z', y)
+    uint8_t* dil = s2 + E * 8;               // [64]    result rows (y, z)
+    const int lane = threadIdx.x;
+    const int64_t ntiles = g.cnt[C_NTILE];
+    for (int64_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int t = g.tlist[it];
+        int tx, ty, tz;
+        unpack_key(g.tkeys[t], tx, ty, tz);
+        for (int n = lane; n < NN; n += 64) {
+            const int dx = n % w - TR, dy = (n / w) % w - TR, dz = n / (w * w) - TR;
+            const int nt = (tx + dx < 0 || ty + dy < 0 || tz + dz < 0)
+                               ? -1
+                               : hpos(g.tkeys, g.tmask, pack_key(tx + dx, ty + dy, tz + dz));
+            for (int k = 0; k < 16; ++k) nmask[n * 16 + k] = nt >= 0 ? g.tobst[(int64_t)nt * 16 + k] : 0u;
+        }
+        __syncthreads();
+        // obstacle bit of neighbourhood block (X, Y, Z), coordinates relative to
+        // the centre tile's origin, each in [-8 TR, 8 + 8 TR)
+        auto obst = [&](int X, int Y, int Z) -> uint32_t {
+            const int n = ((X >> 3) + TR) + w * (((Y >> 3) + TR) + w * ((Z >> 3) + TR));
+            const int l = (X & 7) + 8 * (Y & 7) + 64 * (Z & 7);
+            return (nmask[n * 16 + (l >> 5)] >> (l & 31)) & 1u;
+        };
+        for (int r = lane; r < E * E; r += 64) {            // x dilation
+            const int Y = r % E - R, Z = r / E - R;
+            // row bits X = -R .. 7 + R at positions 0 .. 7 + 2R (< 72): lo, hi words
+            unsigned long long lo = 0ull, hi = 0ull;
+            for (int X = -R; X < 8 + R; ++X) {
+                const int pos = X + R;
+                const unsigned long long b = obst(X, Y, Z);
+                if (pos < 64) lo |= b << pos;
+                else hi |= b << (pos - 64);
+            }
+            uint32_t d = 0u;
+            for (int x = 0; x < 8; ++x) {              // any bit in [x, x + 2R]
+                const int end = x + 2 * R;
+                const unsigned long long mlo =
+                    (end >= 63 ? ~0ull : ((1ull << (end + 1)) - 1ull)) & (~0ull << x);
+                bool any = (lo & mlo) != 0ull;
+                if (end >= 64) {
+                    const int he = end - 64;
+                    any = any || (hi & (he >= 63 ? ~0ull : ((1ull << (he + 1)) - 1ull))) != 0ull;
+                }
+                d |= (any ? 1u : 0u) << x;
+            }
+            s1[r] = (uint8_t)d;
+        }
+        __syncthreads();
+        for (int r = lane; r < E * 8; r += 64) {            // y dilation
+            const int y = r & 7, zp = r >> 3;
+            uint32_t d = 0u;
+            for (int dy = -R; dy <= R; ++dy) d |= s1[(y + dy + R) + E * zp];
+            s2[r] = (uint8_t)d;
+        }
+        __syncthreads();
+        {                                                   // z dilation, lane = y + 8z
+            const int y = lane & 7, z = lane >> 3;
+            uint32_t d = 0u;
+            for (int dz = -R; dz <= R; ++dz) d |= s2[y + 8 * (z + dz + R)];
+            dil[lane] = (uint8_t)d;
+        }
+        __syncthreads();
+        // create the dilated blocks that are missing; lane = row (y, z)
+        const int y = lane & 7, z = lane >> 3;
+        const int by = 8 * ty + y, bz = 8 * tz + z;
+        const uint32_t d = dil[lane];
+        for (int x = 0; x < 8; ++x) {
+            const int bx = 8 * tx + x;
+            const int64_t e = (int64_t)t * 512 + x + 8 * y + 64 * z;
+            const bool want = ((d >> x) & 1u) && bx < g.nbx && by < g.nby && bz < g.nbz &&
+                              g.tslots[e] == -1;
+            if (want) g.tslots[e] = SLOT_PENDING;
+            claim_slots(g, want, e, pack_key(bx, by, bz), 0u);
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
