@@ -22,7 +22,8 @@ import torch
 __all__ = ["Field", "ClearanceCost", "clearance_cost", "lib", "EdtError", "LIB_PATH",
            "Batch", "batch_global", "FUSED", "PER_MAP"]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libedt.so")
+LIB_PATH = os.environ.get("EDT_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                       "libedt.so")
 
 EDT_OK, EDT_ERR_ARG, EDT_ERR_RANGE, EDT_ERR_CAPACITY, EDT_ERR_HIP, EDT_ERR_STATE = 0, -1, -2, -3, -4, -5
 STATUS = {0: "EDT_OK", -1: "EDT_ERR_ARG", -2: "EDT_ERR_RANGE", -3: "EDT_ERR_CAPACITY",
