@@ -160,11 +160,22 @@ void launch_pass(edt_ctx* c, int axis, hipStream_t st, const int32_t* items, int
 edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
     const int mb = g.max_blocks;
-    const int tg = grid_for(mb, 256, 4096);
-    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)nullptr, 0, 0u, 3);
+    hipLaunchKernelGGL(k_items_tiles, dim3(grid_for(c->tcap, 1, 8192)), dim3(64), 0, st, g);
     mark(c, 3, st);
-    hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
-                       (const int32_t*)nullptr, 0);
+    if (g.R <= 8) {
+        const int grid = grid_for(c->tcap * 64, 1, 16384);
+        switch (g.R) {
+#define EDT_PX_CASE(m) \
+    case m: hipLaunchKernelGGL(k_pass_x_rows<m>, dim3(grid), dim3(64), 0, st, g); break;
+            EDT_PX_CASE(1) EDT_PX_CASE(2) EDT_PX_CASE(3) EDT_PX_CASE(4)
+            EDT_PX_CASE(5) EDT_PX_CASE(6) EDT_PX_CASE(7) EDT_PX_CASE(8)
+#undef EDT_PX_CASE
+            default: break;
+        }
+    } else {
+        hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
+                           (const int32_t*)nullptr, 0);
+    }
     mark(c, 4, st);
     launch_pass(c, 1, st, g.list_yi, (int)C_NYI, 0u);
     mark(c, 5, st);

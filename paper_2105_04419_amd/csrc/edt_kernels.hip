@@ -322,32 +322,32 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
             for (int k = 0; k < 16; ++k) nmask[n * 16 + k] = nt >= 0 ? g.tobst[(int64_t)nt * 16 + k] : 0u;
         }
         __syncthreads();
-        // obstacle bit of neighbourhood block (X, Y, Z), coordinates relative to
-        // the centre tile's origin, each in [-8 TR, 8 + 8 TR)
-        auto obst = [&](int X, int Y, int Z) -> uint32_t {
-            const int n = ((X >> 3) + TR) + w * (((Y >> 3) + TR) + w * ((Z >> 3) + TR));
-            const int l = (X & 7) + 8 * (Y & 7) + 64 * (Z & 7);
-            return (nmask[n * 16 + (l >> 5)] >> (l & 31)) & 1u;
-        };
         for (int r = lane; r < E * E; r += 64) {            // x dilation
             const int Y = r % E - R, Z = r / E - R;
-            // row bits X = -R .. 7 + R at positions 0 .. 7 + 2R (< 72): lo, hi words
+            // the row across the w tiles along x: one mask byte per tile, bit
+            // position X + 8 TR for X = -8 TR .. 8 + 8 TR - 1 (<= 72 bits)
+            const int ny = ((Y >> 3) + TR), nz = ((Z >> 3) + TR);
+            const int byte = (Y & 7) + 8 * (Z & 7);
             unsigned long long lo = 0ull, hi = 0ull;
-            for (int X = -R; X < 8 + R; ++X) {
-                const int pos = X + R;
-                const unsigned long long b = obst(X, Y, Z);
+            for (int tx2 = 0; tx2 < w; ++tx2) {
+                const int n = tx2 + w * (ny + w * nz);
+                const unsigned long long b =
+                    (nmask[n * 16 + (byte >> 2)] >> (8 * (byte & 3))) & 0xffu;
+                const int pos = 8 * tx2;
                 if (pos < 64) lo |= b << pos;
                 else hi |= b << (pos - 64);
             }
             uint32_t d = 0u;
-            for (int x = 0; x < 8; ++x) {              // any bit in [x, x + 2R]
-                const int end = x + 2 * R;
+            for (int x = 0; x < 8; ++x) {       // any bit in [x - R, x + R] + 8 TR
+                const int a0 = x - R + 8 * TR, end = x + R + 8 * TR;
                 const unsigned long long mlo =
-                    (end >= 63 ? ~0ull : ((1ull << (end + 1)) - 1ull)) & (~0ull << x);
-                bool any = (lo & mlo) != 0ull;
+                    (end >= 63 ? ~0ull : ((1ull << (end + 1)) - 1ull)) & (~0ull << a0);
+                bool any = a0 < 64 && (lo & mlo) != 0ull;
                 if (end >= 64) {
-                    const int he = end - 64;
-                    any = any || (hi & (he >= 63 ? ~0ull : ((1ull << (he + 1)) - 1ull))) != 0ull;
+                    const int hs = a0 > 64 ? a0 - 64 : 0, he = end - 64;
+                    const unsigned long long mhi =
+                        (he >= 63 ? ~0ull : ((1ull << (he + 1)) - 1ull)) & (~0ull << hs);
+                    any = any || (hi & mhi) != 0ull;
                 }
                 d |= (any ? 1u : 0u) << x;
             }
@@ -421,6 +421,147 @@ __global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t ru
             const int idx = wave_append(st, &g.cnt[C_NZI]);
             if (st) g.list_zi[idx] = slot;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-tile variants for the global transform
+// ---------------------------------------------------------------------------
+// Slot of the block at tile-relative position (x, y, z) (each coordinate in
+// [-8, 16)) of the tile at `tpos`, whose tile coordinates are (tx, ty, tz);
+// neighbouring tiles are looked up in the tile hash.
+__device__ inline int32_t tile_rel_slot(const Grid& g, int tpos, int tx, int ty, int tz, int x,
+                                        int y, int z) {
+    const int dx = x >> 3, dy = y >> 3, dz = z >> 3;
+    int t = tpos;
+    if (dx | dy | dz) {
+        const int ax = tx + dx, ay = ty + dy, az = tz + dz;
+        if (ax < 0 || ay < 0 || az < 0) return -1;
+        t = hpos(g.tkeys, g.tmask, pack_key(ax, ay, az));
+        if (t < 0) return -1;
+    }
+    return g.tslots[(int64_t)t * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+}
+
+// Work items of the global transform, one workgroup per tile: a block starts
+// a y (z) item when it sits on an LRUN boundary or the block before it along
+// y (z) is absent.
+__global__ void __launch_bounds__(64) k_items_tiles(Grid g) {
+    __shared__ int32_t own[512];
+    __shared__ int32_t below[64];     // (x, 7, z) of the tile at ty - 1
+    __shared__ int32_t behind[64];    // (x, y, 7) of the tile at tz - 1
+    const int lane = threadIdx.x;
+    const int64_t ntiles = g.cnt[C_NTILE];
+    for (int64_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int t = g.tlist[it];
+        int tx, ty, tz;
+        unpack_key(g.tkeys[t], tx, ty, tz);
+        for (int i = lane; i < 512; i += 64) own[i] = g.tslots[(int64_t)t * 512 + i];
+        below[lane] = tile_rel_slot(g, t, tx, ty, tz, lane & 7, -1, lane >> 3);
+        behind[lane] = tile_rel_slot(g, t, tx, ty, tz, lane & 7, lane >> 3, -1);
+        __syncthreads();
+        for (int i = lane; i < 512; i += 64) {
+            const int x = i & 7, y = (i >> 3) & 7, z = i >> 6;
+            const int32_t slot = own[i];
+            const int by = 8 * ty + y, bz = 8 * tz + z;
+            const bool ex = slot >= 0;
+            const int32_t py = y > 0 ? own[i - 8] : below[x + 8 * z];
+            const int32_t pz = z > 0 ? own[i - 64] : behind[x + 8 * y];
+            const bool sy = ex && ((by % LRUN) == 0 || py < 0);
+            const bool sz = ex && ((bz % LRUN) == 0 || pz < 0);
+            const int jy = wave_append(sy, &g.cnt[C_NYI]);
+            if (sy) g.list_yi[jy] = slot;
+            const int jz = wave_append(sz, &g.cnt[C_NZI]);
+            if (sz) g.list_zi[jz] = slot;
+        }
+        __syncthreads();
+    }
+}
+
+// pass X for the global transform: one wave per row of 8 blocks along x
+// inside a tile (64 per tile), lane = row (y + 8z) of the blocks.  Each lane
+// sweeps its row twice with a carried distance (left to right, then right to
+// left inside each block); a voxel's distance to the nearest obstacle along x
+// is the smaller of the two, capped at d_max (M = R <= 8 blocks of context on
+// each side cover d_max <= 64).  The squared values are transposed through
+// LDS so that every lane stores 16 contiguous bytes of the y-major g1 block.
+template <int M>
+__global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
+    constexpr int NB = 8 + 2 * M;
+    constexpr uint32_t FAR = 1u << 20;
+    __shared__ int32_t sl[NB];
+    __shared__ uint4 tr[2][72];       // row r at r + r / 8: conflict-free reads
+    const int lane = threadIdx.x;
+    const int64_t nrows = (int64_t)g.cnt[C_NTILE] * 64;
+    const uint8_t* occ8 = (const uint8_t*)g.occ;
+    const uint32_t dmax = (uint32_t)g.dmax;
+    for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+        const int t = g.tlist[it >> 6];
+        const int jy = (int)(it & 7), jz = (int)((it >> 3) & 7);
+        int tx, ty, tz;
+        unpack_key(g.tkeys[t], tx, ty, tz);
+        if (lane < NB) sl[lane] = tile_rel_slot(g, t, tx, ty, tz, lane - M, jy, jz);
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) any = any || sl[M + j] >= 0;
+        if (any) {
+            uint32_t b[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int32_t s2 = sl[k];
+                b[k] = s2 >= 0 ? (uint32_t)occ8[(int64_t)s2 * 64 + lane] : 0u;
+            }
+            // distance from the last voxel before the central blocks back to
+            // the nearest obstacle at or before it
+            uint32_t L = FAR;
+#pragma unroll
+            for (int k = 0; k < M; ++k) L = b[k] ? (uint32_t)__clz(b[k]) - 24u : L + 8u;
+            // rc[j]: distance from the first voxel after central block j to
+            // the nearest obstacle at or after it
+            uint32_t rc[8];
+            uint32_t R = FAR;
+#pragma unroll
+            for (int k = NB - 1; k >= M + 8; --k) R = b[k] ? (uint32_t)(__ffs(b[k]) - 1) : R + 8u;
+#pragma unroll
+            for (int j = 7; j >= 0; --j) {
+                rc[j] = R;
+                const uint32_t bj = b[M + j];
+                R = bj ? (uint32_t)(__ffs(bj) - 1) : R + 8u;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t bj = b[M + j];
+                uint32_t m[8], d[8];
+#pragma unroll
+                for (int x = 0; x < 8; ++x) m[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
+#pragma unroll
+                for (int x = 0; x < 8; ++x) { L = (L + 1u) & ~m[x]; d[x] = L; }
+                uint32_t r = rc[j];
+#pragma unroll
+                for (int x = 7; x >= 0; --x) {
+                    r = (r + 1u) & ~m[x];
+                    const uint32_t v = min(min(d[x], r), dmax);
+                    d[x] = v * v;
+                }
+                const int32_t slot = sl[M + j];
+                if (slot >= 0) {
+                    uint4* buf = tr[j & 1];
+                    buf[lane + (lane >> 3)] = make_uint4(d[0] | (d[1] << 16), d[2] | (d[3] << 16),
+                                                         d[4] | (d[5] << 16), d[6] | (d[7] << 16));
+                    __syncthreads();
+                    // lane = x + 8z gathers column x of rows y + 8z, y = 0..7
+                    const uint16_t* t16 = (const uint16_t*)buf + 72 * (lane >> 3) + (lane & 7);
+                    uint32_t w[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        w[q] = (uint32_t)t16[16 * q] | ((uint32_t)t16[16 * q + 8] << 16);
+                    *reinterpret_cast<uint4*>(g.g1 + (int64_t)slot * 512 + 8 * lane) =
+                        make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
