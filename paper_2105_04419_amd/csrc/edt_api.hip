@@ -83,7 +83,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
-        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 64 * 4 + 1024, 1024,
+        L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, L->tcap * 4, L->tcap * 4};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
@@ -157,30 +157,46 @@ void launch_pass(edt_ctx* c, int axis, hipStream_t st, const int32_t* items, int
     }
 }
 
+// Tile forms of the three passes for d_max <= 64 (block radius M = R <= 8).
+template <int M>
+void launch_tile_passes(edt_ctx* c, hipStream_t st) {
+    const Grid& g = c->g;
+    const int grid = grid_for(c->tcap * 64, 1, 16384);
+    hipLaunchKernelGGL(k_pass_x_rows<M>, dim3(grid), dim3(64), 0, st, g);
+    mark(c, 4, st);
+    hipLaunchKernelGGL((k_pass_win_tiles<M, 1>), dim3(grid), dim3(64), 0, st, g);
+    mark(c, 5, st);
+    hipLaunchKernelGGL((k_pass_win_tiles<M, 2>), dim3(grid), dim3(64), 0, st, g);
+    mark(c, 6, st);
+}
+
+// Passes of the global transform.  d_max <= 64 runs the tile forms (no
+// work-item lists); larger radii build the y/z item lists per tile and run
+// the list-driven passes.
 edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
     const int mb = g.max_blocks;
-    hipLaunchKernelGGL(k_items_tiles, dim3(grid_for(c->tcap, 1, 8192)), dim3(64), 0, st, g);
-    mark(c, 3, st);
     if (g.R <= 8) {
-        const int grid = grid_for(c->tcap * 64, 1, 16384);
+        mark(c, 3, st);
         switch (g.R) {
-#define EDT_PX_CASE(m) \
-    case m: hipLaunchKernelGGL(k_pass_x_rows<m>, dim3(grid), dim3(64), 0, st, g); break;
-            EDT_PX_CASE(1) EDT_PX_CASE(2) EDT_PX_CASE(3) EDT_PX_CASE(4)
-            EDT_PX_CASE(5) EDT_PX_CASE(6) EDT_PX_CASE(7) EDT_PX_CASE(8)
-#undef EDT_PX_CASE
+#define EDT_TP_CASE(m) \
+    case m: launch_tile_passes<m>(c, st); break;
+            EDT_TP_CASE(1) EDT_TP_CASE(2) EDT_TP_CASE(3) EDT_TP_CASE(4)
+            EDT_TP_CASE(5) EDT_TP_CASE(6) EDT_TP_CASE(7) EDT_TP_CASE(8)
+#undef EDT_TP_CASE
             default: break;
         }
     } else {
+        hipLaunchKernelGGL(k_items_tiles, dim3(grid_for(c->tcap, 1, 8192)), dim3(64), 0, st, g);
+        mark(c, 3, st);
         hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
                            (const int32_t*)nullptr, 0);
+        mark(c, 4, st);
+        launch_pass(c, 1, st, g.list_yi, (int)C_NYI, 0u);
+        mark(c, 5, st);
+        launch_pass(c, 2, st, g.list_zi, (int)C_NZI, 0u);
+        mark(c, 6, st);
     }
-    mark(c, 4, st);
-    launch_pass(c, 1, st, g.list_yi, (int)C_NYI, 0u);
-    mark(c, 5, st);
-    launch_pass(c, 2, st, g.list_zi, (int)C_NZI, 0u);
-    mark(c, 6, st);
     if (c->ev && c->ev_used < c->ev_calls) c->ev_used++;
     LAUNCH_CHECK();
     return EDT_OK;

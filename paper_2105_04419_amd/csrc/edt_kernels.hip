@@ -908,6 +908,49 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
 // ---------------------------------------------------------------------------
 // windowed minimum along y or z for d_max <= 64 (core in edt_win.h)
 // ---------------------------------------------------------------------------
+// Stores the results of one step of the windowed minimum: acc[o] holds output
+// row o of two consecutive blocks (low half: slot0, high half: slot1; a
+// negative slot sends its half to the wave's dummy buffer).  Pass Y writes g2
+// (z-major rows); pass Z writes s and the block maxima.
+template <int AXIS>
+__device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, const u16x2* acc,
+                                 int lane, uint32_t* dummy) {
+    if (AXIS == 1) {
+        const int out_lane = (lane & 7) * 8 + (lane >> 3);
+        uint16_t* d0 = slot0 >= 0 ? g.g2 + (int64_t)slot0 * 512 + out_lane : (uint16_t*)dummy + lane;
+        uint16_t* d1 = slot1 >= 0 ? g.g2 + (int64_t)slot1 * 512 + out_lane
+                                  : (uint16_t*)dummy + 64 + lane;
+        const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t v = as_u32(acc[o]);
+            d0[s0 * o] = (uint16_t)(v & 0xffffu);
+            d1[s1 * o] = (uint16_t)(v >> 16);
+        }
+    } else {
+        int32_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (int32_t*)dummy + lane;
+        int32_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (int32_t*)dummy + 64 + lane;
+        const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
+        int m0 = 0, m1 = 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t v = as_u32(acc[o]);
+            const int v0 = (int)(v & 0xffffu), v1 = (int)(v >> 16);
+            d0[s0 * o] = v0;
+            d1[s1 * o] = v1;
+            m0 = max(m0, v0);
+            m1 = max(m1, v1);
+        }
+        m0 = wave_max(m0);
+        m1 = wave_max(m1);
+        int32_t* b0 = slot0 >= 0 ? g.bmax + slot0 : (int32_t*)dummy + 128;
+        int32_t* b1 = slot1 >= 0 ? g.bmax + slot1 : (int32_t*)dummy + 129;
+        if (lane == 0) { *b0 = m0; *b1 = m1; }
+    }
+}
+
+// List-driven form: one wave per work item (a run of up to LRUN blocks,
+// extended by the halo of resolve_run).
 template <int M, int AXIS>
 __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, int item_counter,
                                                  uint32_t runflag) {
@@ -916,9 +959,8 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
     const int lane = threadIdx.x;
     const int64_t nit = g.cnt[item_counter];
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
-    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 64;
+    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
     const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
-    const int out_lane = AXIS == 1 ? (lane & 7) * 8 + (lane >> 3) : lane;
     for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
         const int32_t s0 = items[it];
         int bx, by, bz;
@@ -936,37 +978,53 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
         auto emit = [&](int ob, const u16x2* acc, bool has1) {
             const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[base + ob]);
             const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
-            if (AXIS == 1) {
-                uint16_t* d0 = g.g2 + (int64_t)slot0 * 512;
-                uint16_t* d1 = has1 ? g.g2 + (int64_t)slot1 * 512 : (uint16_t*)dummy;
-                const int ol = has1 ? out_lane : lane;
-#pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    const uint32_t v = as_u32(acc[o]);
-                    d0[out_lane + 64 * o] = (uint16_t)(v & 0xffffu);
-                    d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
-                }
-            } else {
-                int32_t* d0 = g.s + (int64_t)slot0 * 512;
-                int32_t* d1 = has1 ? g.s + (int64_t)slot1 * 512 : (int32_t*)dummy;
-                int m0 = 0, m1 = 0;
-#pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    const uint32_t v = as_u32(acc[o]);
-                    const int v0 = (int)(v & 0xffffu), v1 = (int)(v >> 16);
-                    d0[lane + 64 * o] = v0;
-                    d1[(has1 ? 64 * o : 0) + lane] = v1;
-                    m0 = max(m0, v0);
-                    m1 = max(m1, v1);
-                }
-                m0 = wave_max(m0);
-                m1 = wave_max(m1);
-                g.bmax[slot0] = m0;
-                int32_t* b1 = has1 ? g.bmax + slot1 : (int32_t*)dummy + 64;
-                *b1 = m1;
-            }
+            win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
         };
         window_min<M>(hb, len, Dp, blk, emit);
+        __syncthreads();
+    }
+}
+
+// Tile form for the global transform: one wave per column of 8 blocks along
+// the pass axis inside a tile (64 columns per tile), with M blocks of context
+// on each side taken from the neighbouring tiles.  Absent blocks hold no
+// obstacle within d_max, so they read as the constant D block.
+template <int M, int AXIS>
+__global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
+    constexpr int NB = 8 + 2 * M;
+    __shared__ int32_t sl[NB];
+    const int lane = threadIdx.x;
+    const int64_t ncol = (int64_t)g.cnt[C_NTILE] * 64;
+    const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
+    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
+    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
+    for (int64_t it = blockIdx.x; it < ncol; it += gridDim.x) {
+        const int t = g.tlist[it >> 6];
+        const int ca = (int)(it & 7), cb = (int)((it >> 3) & 7);
+        int tx, ty, tz;
+        unpack_key(g.tkeys[t], tx, ty, tz);
+        if (lane < NB)
+            sl[lane] = AXIS == 1 ? tile_rel_slot(g, t, tx, ty, tz, ca, lane - M, cb)
+                                 : tile_rel_slot(g, t, tx, ty, tz, ca, cb, lane - M);
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) any = any || sl[M + j] >= 0;
+        if (any) {
+            auto blk = [&](int b) -> uint4 {
+                const int32_t s2 = (b >= -M && b < 8 + M) ? sl[b + M] : -1;
+                const uint4* p = s2 >= 0 ? (const uint4*)src + (int64_t)s2 * 64 + lane
+                                         : (const uint4*)g.dblock + lane;
+                return *p;
+            };
+            auto emit = [&](int ob, const u16x2* acc, bool) {
+                const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[M + ob]);
+                const int32_t slot1 = __builtin_amdgcn_readfirstlane(sl[M + ob + 1]);
+                win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
+            };
+            auto need = [&](int ob) { return sl[M + ob] >= 0 || sl[M + ob + 1] >= 0; };
+            window_min<M>(0, 8, Dp, blk, emit, need);
+        }
         __syncthreads();
     }
 }

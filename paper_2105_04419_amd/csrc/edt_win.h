@@ -10,9 +10,10 @@
 // min, one packed add and one packed min for two outputs; offsets are taken
 // outward from 0, and the wave stops early once every output is already no
 // larger than the square of the next offset.  The 2M + 2 input blocks of the
-// window stay in registers and slide by two blocks per step.  Callers make every load and store unconditional (absent
-// blocks read a block of D values, halo outputs go to a scratch row) so the
-// loop issues a fixed sequence of memory operations.
+// window stay in registers and slide by two blocks per step.  Callers make
+// every load and store unconditional (absent blocks read a block of D values,
+// halo outputs go to a scratch row) so the loop issues a fixed sequence of
+// memory operations.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,8 +34,11 @@ __device__ inline uint32_t word_of(const uint4& v, int w) {
 // emit(ob, acc, has1): acc[o] holds out(8 ob + o) in the low half and
 // out(8 ob + 8 + o) in the high half; has1 tells whether block ob + 1 is an
 // output block.
-template <int M, class Blk, class Emit>
-__device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
+// need(ob): false when neither output block ob nor ob + 1 is wanted (must be
+// uniform across the wave); the window still slides over such a pair.
+template <int M, class Blk, class Emit, class Need>
+__device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit,
+                                  Need&& need) {
     constexpr int NW = 2 * M + 2;        // window blocks
     constexpr int K = 8 * M - 1;         // largest offset
     constexpr int NP = 8 * (NW - 1);     // input pairs: positions p = -8M .. 8M + 7
@@ -43,45 +47,52 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
     for (int w = 0; w < NW; ++w) W[w] = blk(first - M + w);
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
-        // P[q]: (in(p), in(p + 8)) for p = q - 8M, packed
-        u16x2 P[NP];
+        if (need(ob)) {
+            // P[q]: (in(p), in(p + 8)) for p = q - 8M, packed
+            u16x2 P[NP];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int b = q >> 3, z = q & 7;
-            const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
-            P[q] = as_u16x2(__builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
-        }
-        // k = 0, then offsets k = 1, 2, ... outward: the two candidates at +-k
-        // share k^2, so min(in(i - k), in(i + k)) + k^2 covers both
-        u16x2 acc[8];
-#pragma unroll
-        for (int o = 0; o < 8; ++o) acc[o] = P[o + 8 * M];
-#pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            const unsigned short kk = (unsigned short)(k * k);
-            u16x2 m[8];
-#pragma unroll
-            for (int o = 0; o < 8; ++o)
-                m[o] = __builtin_elementwise_min(P[o + 8 * M - k], P[o + 8 * M + k]) + (u16x2){kk, kk};
-#pragma unroll
-            for (int o = 0; o < 8; ++o) acc[o] = __builtin_elementwise_min(acc[o], m[o]);
-            // every 8 offsets: stop once no output of the wave can still drop,
-            // i.e. all are <= (k + 1)^2, the least any further candidate adds
-            if ((k & 7) == 7 && k < K) {
-                u16x2 mx = __builtin_elementwise_max(acc[0], acc[1]);
-#pragma unroll
-                for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
-                const int lim = (k + 1) * (k + 1);
-                const bool more = (int)mx.x > lim || (int)mx.y > lim;
-                if (!__any(more)) break;
+            for (int q = 0; q < NP; ++q) {
+                const int b = q >> 3, z = q & 7;
+                const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
+                P[q] = as_u16x2(__builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
             }
+            // k = 0, then offsets k = 1, 2, ... outward: the two candidates at +-k
+            // share k^2, so min(in(i - k), in(i + k)) + k^2 covers both
+            u16x2 acc[8];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) acc[o] = P[o + 8 * M];
+#pragma unroll
+            for (int k = 1; k <= K; ++k) {
+                const unsigned short kk = (unsigned short)(k * k);
+                u16x2 m[8];
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                    m[o] = __builtin_elementwise_min(P[o + 8 * M - k], P[o + 8 * M + k]) + (u16x2){kk, kk};
+#pragma unroll
+                for (int o = 0; o < 8; ++o) acc[o] = __builtin_elementwise_min(acc[o], m[o]);
+                // every 8 offsets: stop once no output of the wave can still drop,
+                // i.e. all are <= (k + 1)^2, the least any further candidate adds
+                if ((k & 7) == 7 && k < K) {
+                    u16x2 mx = __builtin_elementwise_max(acc[0], acc[1]);
+#pragma unroll
+                    for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
+                    const int lim = (k + 1) * (k + 1);
+                    const bool more = (int)mx.x > lim || (int)mx.y > lim;
+                    if (!__any(more)) break;
+                }
+            }
+            emit(ob, acc, ob + 1 < first + count);
         }
-        emit(ob, acc, ob + 1 < first + count);
 #pragma unroll
         for (int w = 0; w + 2 < NW; ++w) W[w] = W[w + 2];
         W[NW - 2] = N0;
         W[NW - 1] = N1;
     }
+}
+
+template <int M, class Blk, class Emit>
+__device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
+    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; });
 }
 
 }  // namespace edt
