@@ -86,7 +86,9 @@ struct Grid {
     unsigned long long* ukeys;
     int32_t* uvals;
     int32_t* upos;
-    uint32_t* dummy;         // 256 x 64 words of write-only scratch rows
+    uint8_t* alld1;          // [slot] g1 of the block is D everywhere (global transform)
+    uint8_t* alld2;          // [slot] g2 of the block is D everywhere (global transform)
+    uint32_t* dummy;         // 256 x 256 words of write-only scratch rows
     uint16_t* dblock;        // one block of D values (stands for absent blocks)
 };
 

@@ -532,6 +532,10 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint32_t bj = b[M + j];
+                // the block's g1 is D everywhere iff no lane has an obstacle in
+                // the block and both carries already reach d_max
+                const bool far = bj == 0u && L + 1u >= dmax && rc[j] + 1u >= dmax;
+                const bool alld = __ballot(!far) == 0ull;
                 uint32_t m[8], d[8];
 #pragma unroll
                 for (int x = 0; x < 8; ++x) m[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
@@ -546,6 +550,7 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                 }
                 const int32_t slot = sl[M + j];
                 if (slot >= 0) {
+                    if (lane == 0) g.alld1[slot] = alld ? 1 : 0;
                     uint4* buf = tr[j & 1];
                     buf[lane + (lane >> 3)] = make_uint4(d[0] | (d[1] << 16), d[2] | (d[3] << 16),
                                                          d[4] | (d[5] << 16), d[6] | (d[7] << 16));
@@ -921,12 +926,20 @@ __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, co
         uint16_t* d1 = slot1 >= 0 ? g.g2 + (int64_t)slot1 * 512 + out_lane
                                   : (uint16_t*)dummy + 64 + lane;
         const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
+        u16x2 mn = acc[0];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const uint32_t v = as_u32(acc[o]);
             d0[s0 * o] = (uint16_t)(v & 0xffffu);
             d1[s1 * o] = (uint16_t)(v >> 16);
+            mn = __builtin_elementwise_min(mn, acc[o]);
         }
+        // block flags for pass Z: output D everywhere
+        const bool a0 = __ballot((int)mn.x < g.D) == 0ull;
+        const bool a1 = __ballot((int)mn.y < g.D) == 0ull;
+        uint8_t* f0 = slot0 >= 0 ? g.alld2 + slot0 : (uint8_t*)(dummy + 130);
+        uint8_t* f1 = slot1 >= 0 ? g.alld2 + slot1 : (uint8_t*)(dummy + 131);
+        if (lane == 0) { *f0 = a0 ? 1 : 0; *f1 = a1 ? 1 : 0; }
     } else {
         int32_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (int32_t*)dummy + lane;
         int32_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (int32_t*)dummy + 64 + lane;
@@ -1011,6 +1024,15 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) any = any || sl[M + j] >= 0;
         if (any) {
+            // bit j: block j - M is absent or its input is D everywhere
+            // (positions past the context read the D block)
+            const uint8_t* alld = AXIS == 1 ? g.alld1 : g.alld2;
+            bool flat = true;
+            if (lane < NB) {
+                const int32_t s2 = sl[lane];
+                flat = s2 < 0 || alld[s2] != 0;
+            }
+            const uint64_t F = __ballot(flat);
             auto blk = [&](int b) -> uint4 {
                 const int32_t s2 = (b >= -M && b < 8 + M) ? sl[b + M] : -1;
                 const uint4* p = s2 >= 0 ? (const uint4*)src + (int64_t)s2 * 64 + lane
@@ -1023,7 +1045,7 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                 win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
             };
             auto need = [&](int ob) { return sl[M + ob] >= 0 || sl[M + ob + 1] >= 0; };
-            window_min<M>(0, 8, Dp, blk, emit, need);
+            window_min<M>(0, 8, Dp, blk, emit, need, F);
         }
         __syncthreads();
     }

@@ -36,9 +36,13 @@ __device__ inline uint32_t word_of(const uint4& v, int w) {
 // output block.
 // need(ob): false when neither output block ob nor ob + 1 is wanted (must be
 // uniform across the wave); the window still slides over such a pair.
+// F (uniform): bit j set when block first - M + j holds D everywhere (or is
+// absent).  Such a block only offers candidates D + k^2 > D >= acc, so a group
+// of 8 offsets whose candidates all come from flagged blocks is skipped, and
+// a pair whose whole window is flagged is D without any arithmetic.
 template <int M, class Blk, class Emit, class Need>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit,
-                                  Need&& need) {
+                                  Need&& need, uint64_t F) {
     constexpr int NW = 2 * M + 2;        // window blocks
     constexpr int K = 8 * M - 1;         // largest offset
     constexpr int NP = 8 * (NW - 1);     // input pairs: positions p = -8M .. 8M + 7
@@ -48,37 +52,54 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
         if (need(ob)) {
-            // P[q]: (in(p), in(p + 8)) for p = q - 8M, packed
-            u16x2 P[NP];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const int b = q >> 3, z = q & 7;
-                const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
-                P[q] = as_u16x2(__builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
-            }
-            // k = 0, then offsets k = 1, 2, ... outward: the two candidates at +-k
-            // share k^2, so min(in(i - k), in(i + k)) + k^2 covers both
+            // bit j of FF: block ob - M + j
+            const uint64_t FF = F >> (ob - first);
+            constexpr uint64_t ALL = (1ull << NW) - 1ull;
             u16x2 acc[8];
+            if ((FF & ALL) == ALL) {
 #pragma unroll
-            for (int o = 0; o < 8; ++o) acc[o] = P[o + 8 * M];
+                for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
+            } else {
+                // P[q]: (in(p), in(p + 8)) for p = q - 8M, packed
+                u16x2 P[NP];
 #pragma unroll
-            for (int k = 1; k <= K; ++k) {
-                const unsigned short kk = (unsigned short)(k * k);
-                u16x2 m[8];
+                for (int q = 0; q < NP; ++q) {
+                    const int b = q >> 3, z = q & 7;
+                    const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
+                    P[q] = as_u16x2(
+                        __builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
+                }
 #pragma unroll
-                for (int o = 0; o < 8; ++o)
-                    m[o] = __builtin_elementwise_min(P[o + 8 * M - k], P[o + 8 * M + k]) + (u16x2){kk, kk};
+                for (int o = 0; o < 8; ++o) acc[o] = P[o + 8 * M];
+                // offsets outward in groups of 8: group G (k = 8G .. 8G + 7,
+                // k >= 1) reads blocks ob - G - 1 .. ob - G + 1 and
+                // ob + G .. ob + G + 2; the two candidates at +-k share k^2,
+                // so min(in(i - k), in(i + k)) + k^2 covers both
 #pragma unroll
-                for (int o = 0; o < 8; ++o) acc[o] = __builtin_elementwise_min(acc[o], m[o]);
-                // every 8 offsets: stop once no output of the wave can still drop,
-                // i.e. all are <= (k + 1)^2, the least any further candidate adds
-                if ((k & 7) == 7 && k < K) {
-                    u16x2 mx = __builtin_elementwise_max(acc[0], acc[1]);
+                for (int G = 0; G < M; ++G) {
+                    const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
+                    if ((FF & CG) == CG) continue;
 #pragma unroll
-                    for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
-                    const int lim = (k + 1) * (k + 1);
-                    const bool more = (int)mx.x > lim || (int)mx.y > lim;
-                    if (!__any(more)) break;
+                    for (int k = (G == 0 ? 1 : 8 * G); k <= 8 * G + 7; ++k) {
+                        const unsigned short kk = (unsigned short)(k * k);
+                        u16x2 m[8];
+#pragma unroll
+                        for (int o = 0; o < 8; ++o)
+                            m[o] = __builtin_elementwise_min(P[o + 8 * M - k], P[o + 8 * M + k]) +
+                                   (u16x2){kk, kk};
+#pragma unroll
+                        for (int o = 0; o < 8; ++o) acc[o] = __builtin_elementwise_min(acc[o], m[o]);
+                    }
+                    // stop once no output of the wave can still drop, i.e. all
+                    // are <= (8G + 8)^2, the least any further candidate adds
+                    if (G + 1 < M) {
+                        u16x2 mx = __builtin_elementwise_max(acc[0], acc[1]);
+#pragma unroll
+                        for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
+                        const int lim = (8 * G + 8) * (8 * G + 8);
+                        const bool more = (int)mx.x > lim || (int)mx.y > lim;
+                        if (!__any(more)) break;
+                    }
                 }
             }
             emit(ob, acc, ob + 1 < first + count);
@@ -92,7 +113,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
 
 template <int M, class Blk, class Emit>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
-    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; });
+    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; }, 0ull);
 }
 
 }  // namespace edt
