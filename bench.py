@@ -92,24 +92,32 @@ def bench_global(args, torch, np):
                 n_obst_blocks=len(bxyz), xyz_d=xyz_d, occ_d=occ_d)
 
 
-def roofline(g):
-    """Dominant kernel of the global step and its algorithmic HBM bytes:
-    pass_z reads g2 (2 B) and writes s (4 B) per voxel of the region, plus
-    one int32 block maximum per block; pass_y reads g1 (2 B) and writes g2
-    (2 B); pass_x reads 64 B of bits and writes 1 KiB of g1 per block."""
+def roofline(g, dmax):
+    """Dominant kernel of the global step and its algorithmic HBM bytes per
+    launch, nb region blocks of 512 voxels:
+      pass_x  reads 64 B of occupancy bits, writes 1 KiB of g1 (uint16) and a
+              2 B block minimum per block;
+      pass_y  reads g1 and a block minimum, writes g2 and its minimum
+              (2 + 2 B per voxel, 4 B per block);
+      pass_z  reads g2 and its minimum, writes s (uint16) and the int32 block
+              maximum (2 + 2 B per voxel, 6 B per block)."""
     ph = g["phases"]
     nb = g["st"]["blocks"]
     per_launch = {
-        "pass_z": nb * 512 * 6 + nb * 4,
-        "pass_y": nb * 512 * 4,
-        "pass_x": nb * (64 + 1024),
+        "pass_x": nb * (64 + 1024 + 2),
+        "pass_y": nb * (512 * 4 + 4),
+        "pass_z": nb * (512 * 4 + 6),
     }
+    R = (dmax + 7) // 8
+    names = ({"pass_x": f"k_pass_x_rows<{R}>", "pass_y": f"k_pass_win_tiles<{R},1>",
+              "pass_z": f"k_pass_win_tiles<{R},2>"} if R <= 8 else
+             {"pass_x": "k_pass_x", "pass_y": "k_pass_y", "pass_z": "k_pass_z"})
     kern = max(per_launch, key=lambda k: ph[k])
     ms = ph[kern]
     achieved = per_launch[kern] / (ms * 1e-3) / 1e9
     tr = traffic_record(kern)
     return {
-        "kernel": f"k_{kern}",
+        "kernel": names[kern],
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -303,7 +311,7 @@ def main():
 
     log(f"[bench] global transform, tunnel map seed {args.seed}, d_max {args.dmax}")
     g = bench_global(args, torch, np)
-    rl = roofline(g)
+    rl = roofline(g, args.dmax)
     out = {
         "metric": METRIC,
         "value": g["n_ext"] / (g["ms"] * 1e-3),
@@ -315,7 +323,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "u16",
         "data": "synthetic",
         "config": {
             "workload": "sparse tunnel map 1024x1024x128, 12 tubes, 8^3 leaf blocks, "

@@ -14,7 +14,8 @@
  *
  * 0 on obstacles, D where no obstacle lies within d_max.  Results are exact
  * int32; a global transform and any sequence of incremental updates give the
- * same bits.
+ * same bits.  Inside the workspace s is held as 16-bit values (D <= 255^2 <
+ * 2^16), widened on readback.
  *
  * Conventions
  *  - Every pointer named d_* is a device pointer (HIP global memory); the

@@ -49,7 +49,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TFLAG, O_TLIST, O_OLIST, O_ALLD, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TFLAG, O_TLIST, O_OLIST, O_BMIN, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -80,11 +80,11 @@ bool layout_of(const edt_config* c, Layout* L) {
     if (L->tcap > (1 << 24)) return false;
     L->ucap = next_pow2(mc * 2 < 64 ? 64 : mc * 2);
     const int64_t sz[O_N] = {
-        L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 2048, mb * 4,
+        L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 1024, mb * 4,
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
-        L->tcap * 64, L->tcap * 4, L->tcap * 4, L->tcap * 4, mb * 2};
+        L->tcap * 64, L->tcap * 4, L->tcap * 4, L->tcap * 4, mb * 4};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -266,7 +266,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.occ = (uint32_t*)(b + L.off[O_OCC]);
     g.g1 = (uint16_t*)(b + L.off[O_G1]);
     g.g2 = (uint16_t*)(b + L.off[O_G2]);
-    g.s = (int32_t*)(b + L.off[O_S]);
+    g.s = (uint16_t*)(b + L.off[O_S]);
     g.bmax = (int32_t*)(b + L.off[O_BMAX]);
     g.flags = (uint32_t*)(b + L.off[O_FLAGS]);
     g.cnt = (int32_t*)(b + L.off[O_CNT]);
@@ -289,8 +289,8 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.tflag = (int32_t*)(b + L.off[O_TFLAG]);
     g.tlist = (int32_t*)(b + L.off[O_TLIST]);
     g.olist = (int32_t*)(b + L.off[O_OLIST]);
-    g.alld1 = (uint8_t*)(b + L.off[O_ALLD]);
-    g.alld2 = g.alld1 + L.max_blocks;
+    g.bmin1 = (uint16_t*)(b + L.off[O_BMIN]);
+    g.bmin2 = g.bmin1 + L.max_blocks;
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup

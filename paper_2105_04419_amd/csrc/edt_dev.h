@@ -69,7 +69,7 @@ struct Grid {
     uint32_t* occ;
     uint16_t* g1;
     uint16_t* g2;
-    int32_t* s;
+    uint16_t* s;             // [slot][512] squared distance, layout x + 8y + 64z (D <= 255^2)
     int32_t* bmax;
     uint32_t* flags;
     int32_t* cnt;
@@ -86,8 +86,8 @@ struct Grid {
     unsigned long long* ukeys;
     int32_t* uvals;
     int32_t* upos;
-    uint8_t* alld1;          // [slot] g1 of the block is D everywhere (global transform)
-    uint8_t* alld2;          // [slot] g2 of the block is D everywhere (global transform)
+    uint16_t* bmin1;         // [slot] least g1 value of the block (global transform)
+    uint16_t* bmin2;         // [slot] least g2 value of the block (global transform)
     uint32_t* dummy;         // 256 x 256 words of write-only scratch rows
     uint16_t* dblock;        // one block of D values (stands for absent blocks)
 };

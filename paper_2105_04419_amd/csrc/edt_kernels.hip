@@ -532,10 +532,11 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint32_t bj = b[M + j];
-                // the block's g1 is D everywhere iff no lane has an obstacle in
-                // the block and both carries already reach d_max
-                const bool far = bj == 0u && L + 1u >= dmax && rc[j] + 1u >= dmax;
-                const bool alld = __ballot(!far) == 0ull;
+                // least g1 of the block: 0 on a row holding an obstacle, else
+                // set by the end voxels (voxel 0 is nearest the left obstacle,
+                // voxel 7 the right one)
+                const uint32_t near = bj ? 0u : min(min(L + 1u, rc[j] + 1u), dmax);
+                const int bmin = wave_min((int)(near * near));
                 uint32_t m[8], d[8];
 #pragma unroll
                 for (int x = 0; x < 8; ++x) m[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
@@ -550,7 +551,7 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                 }
                 const int32_t slot = sl[M + j];
                 if (slot >= 0) {
-                    if (lane == 0) g.alld1[slot] = alld ? 1 : 0;
+                    if (lane == 0) g.bmin1[slot] = (uint16_t)bmin;
                     uint4* buf = tr[j & 1];
                     buf[lane + (lane >> 3)] = make_uint4(d[0] | (d[1] << 16), d[2] | (d[3] << 16),
                                                          d[4] | (d[5] << 16), d[6] | (d[7] << 16));
@@ -832,7 +833,7 @@ __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int
 }
 
 // pass Z: lane = x + 8y.  Reads g2 (one 16-byte load per block and lane),
-// writes s (layout x + 8y + 64z) and the per-block maximum.
+// writes s (uint16, layout x + 8y + 64z) and the per-block maximum.
 struct PassZItem {
     const Grid& g;
     const int32_t* sl;
@@ -862,8 +863,9 @@ struct PassZItem {
             int v = 0;
             if (out) v = env.eval(i, dmax, D);
             const int32_t slot = ((i >> 3) == jo) ? slo : shi;
-            int32_t* dst = out ? g.s + (int64_t)slot * 512 + lane + 64 * (i & 7) : dummy + lane;
-            *dst = v;
+            uint16_t* dst =
+                out ? g.s + (int64_t)slot * 512 + lane + 64 * (i & 7) : (uint16_t*)dummy + lane;
+            *dst = (uint16_t)v;
             bm = max(bm, v);
             if (((k - dmax) & 7) == 7) {          // the step that ends an output block
                 const int m = wave_max(bm);
@@ -934,23 +936,24 @@ __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, co
             d1[s1 * o] = (uint16_t)(v >> 16);
             mn = __builtin_elementwise_min(mn, acc[o]);
         }
-        // block flags for pass Z: output D everywhere
-        const bool a0 = __ballot((int)mn.x < g.D) == 0ull;
-        const bool a1 = __ballot((int)mn.y < g.D) == 0ull;
-        uint8_t* f0 = slot0 >= 0 ? g.alld2 + slot0 : (uint8_t*)(dummy + 130);
-        uint8_t* f1 = slot1 >= 0 ? g.alld2 + slot1 : (uint8_t*)(dummy + 131);
-        if (lane == 0) { *f0 = a0 ? 1 : 0; *f1 = a1 ? 1 : 0; }
+        // least output of each block, for the skip bounds of pass Z
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            mn = __builtin_elementwise_min(mn, as_u16x2((uint32_t)__shfl_xor((int)as_u32(mn), o)));
+        uint16_t* f0 = slot0 >= 0 ? g.bmin2 + slot0 : (uint16_t*)(dummy + 130);
+        uint16_t* f1 = slot1 >= 0 ? g.bmin2 + slot1 : (uint16_t*)(dummy + 131);
+        if (lane == 0) { *f0 = mn.x; *f1 = mn.y; }
     } else {
-        int32_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (int32_t*)dummy + lane;
-        int32_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (int32_t*)dummy + 64 + lane;
+        uint16_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (uint16_t*)dummy + lane;
+        uint16_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (uint16_t*)dummy + 64 + lane;
         const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
         int m0 = 0, m1 = 0;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const uint32_t v = as_u32(acc[o]);
             const int v0 = (int)(v & 0xffffu), v1 = (int)(v >> 16);
-            d0[s0 * o] = v0;
-            d1[s1 * o] = v1;
+            d0[s0 * o] = (uint16_t)v0;
+            d1[s1 * o] = (uint16_t)v1;
             m0 = max(m0, v0);
             m1 = max(m1, v1);
         }
@@ -1024,17 +1027,26 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) any = any || sl[M + j] >= 0;
         if (any) {
-            // bit j: block j - M is absent or its input is D everywhere
-            // (positions past the context read the D block)
-            const uint8_t* alld = AXIS == 1 ? g.alld1 : g.alld2;
-            bool flat = true;
+            // skip masks over window positions j (block j - M): least input
+            // of the block, D for absent blocks and past the context
+            const uint16_t* bmin = AXIS == 1 ? g.bmin1 : g.bmin2;
+            int bm = g.D;
             if (lane < NB) {
                 const int32_t s2 = sl[lane];
-                flat = s2 < 0 || alld[s2] != 0;
+                if (s2 >= 0) bm = bmin[s2];
             }
-            const uint64_t F = __ballot(flat);
+            WinSkip sk;
+            sk.d = __ballot(bm >= g.D);
+#pragma unroll
+            for (int G = 0; G < M; ++G) {
+                const int kg = G == 0 ? 1 : 8 * G;
+                sk.g[G] = __ballot(bm + kg * kg >= g.D);
+            }
+            // a block that is D everywhere reads the shared D block (cache
+            // resident) instead of its own copy
             auto blk = [&](int b) -> uint4 {
-                const int32_t s2 = (b >= -M && b < 8 + M) ? sl[b + M] : -1;
+                const int j = b + M;
+                const int32_t s2 = (j < NB && !((sk.d >> j) & 1ull)) ? sl[j] : -1;
                 const uint4* p = s2 >= 0 ? (const uint4*)src + (int64_t)s2 * 64 + lane
                                          : (const uint4*)g.dblock + lane;
                 return *p;
@@ -1045,7 +1057,7 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                 win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
             };
             auto need = [&](int ob) { return sl[M + ob] >= 0 || sl[M + ob + 1] >= 0; };
-            window_min<M>(0, 8, Dp, blk, emit, need, F);
+            window_min<M>(0, 8, Dp, blk, emit, need, sk);
         }
         __syncthreads();
     }
@@ -1066,7 +1078,7 @@ __global__ void __launch_bounds__(64) k_read_dense(Grid g, int32_t* __restrict__
         for (int k = 0; k < nxr; ++k) row[k] = g.D;
         return;
     }
-    const int32_t* src = g.s + (int64_t)slot * 512 + 8 * lane;
+    const uint16_t* src = g.s + (int64_t)slot * 512 + 8 * lane;
     for (int k = 0; k < nxr; ++k) row[k] = src[k];
 }
 
@@ -1174,7 +1186,7 @@ __global__ void __launch_bounds__(64) k_init_new(Grid g, int first_counter) {
             ((uint32_t*)(g.g1 + s * 512))[k] = d2;
             ((uint32_t*)(g.g2 + s * 512))[k] = d2;
         }
-        for (int k = lane; k < 512; k += 64) g.s[s * 512 + k] = g.D;
+        for (int k = lane; k < 256; k += 64) ((uint32_t*)(g.s + s * 512))[k] = d2;
         if (lane == 0) g.bmax[s] = g.D;
     }
 }

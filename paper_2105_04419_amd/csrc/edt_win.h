@@ -34,15 +34,23 @@ __device__ inline uint32_t word_of(const uint4& v, int w) {
 // emit(ob, acc, has1): acc[o] holds out(8 ob + o) in the low half and
 // out(8 ob + 8 + o) in the high half; has1 tells whether block ob + 1 is an
 // output block.
+// Uniform skip masks over window positions j (block first - M + j).
+// Every output stays <= D, and group G of offsets (k = max(1, 8G) ..
+// 8G + 7) offers from block b only candidates >= min(b) + k^2; so group G
+// is skipped when every block it reads has bit j of g[G] set, meaning
+// min(b) + max(1, 8G)^2 >= D.  Bit j of d: block b is D everywhere.  A pair
+// whose two output blocks are D everywhere and whose groups are all skipped
+// is D without any arithmetic.
+struct WinSkip {
+    uint64_t g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t d = 0;
+};
+
 // need(ob): false when neither output block ob nor ob + 1 is wanted (must be
 // uniform across the wave); the window still slides over such a pair.
-// F (uniform): bit j set when block first - M + j holds D everywhere (or is
-// absent).  Such a block only offers candidates D + k^2 > D >= acc, so a group
-// of 8 offsets whose candidates all come from flagged blocks is skipped, and
-// a pair whose whole window is flagged is D without any arithmetic.
 template <int M, class Blk, class Emit, class Need>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit,
-                                  Need&& need, uint64_t F) {
+                                  Need&& need, const WinSkip& sk) {
     constexpr int NW = 2 * M + 2;        // window blocks
     constexpr int K = 8 * M - 1;         // largest offset
     constexpr int NP = 8 * (NW - 1);     // input pairs: positions p = -8M .. 8M + 7
@@ -52,11 +60,16 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
         if (need(ob)) {
-            // bit j of FF: block ob - M + j
-            const uint64_t FF = F >> (ob - first);
-            constexpr uint64_t ALL = (1ull << NW) - 1ull;
+            // bit j of the shifted masks: block ob - M + j
+            const int sh = ob - first;
+            bool flat = ((sk.d >> sh) & (3ull << M)) == (3ull << M);
+#pragma unroll
+            for (int G = 0; G < M; ++G) {
+                const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
+                flat = flat && ((sk.g[G] >> sh) & CG) == CG;
+            }
             u16x2 acc[8];
-            if ((FF & ALL) == ALL) {
+            if (flat) {
 #pragma unroll
                 for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
             } else {
@@ -78,7 +91,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
 #pragma unroll
                 for (int G = 0; G < M; ++G) {
                     const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
-                    if ((FF & CG) == CG) continue;
+                    if (((sk.g[G] >> sh) & CG) == CG) continue;
 #pragma unroll
                     for (int k = (G == 0 ? 1 : 8 * G); k <= 8 * G + 7; ++k) {
                         const unsigned short kk = (unsigned short)(k * k);
@@ -113,7 +126,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
 
 template <int M, class Blk, class Emit>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
-    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; }, 0ull);
+    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; }, WinSkip{});
 }
 
 }  // namespace edt
