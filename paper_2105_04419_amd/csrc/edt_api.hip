@@ -392,25 +392,24 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
     hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
                        g, c->tcap);
     if (map->kind == EDT_MAP_DENSE) {
+        // obstacle blocks get their slots and occupancy here, the dilation
+        // adds (and zeroes) the rest of the region
         hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
                            map->d_occ);
-        hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;
-        hipLaunchKernelGGL(k_zero_occ, dim3(grid_for((int64_t)g.max_blocks * 16, 256, 4096)),
-                           dim3(256), 0, st, g, (int)C_SNAP2);
         mark(c, 2, st);
     } else {
+        // obstacle blocks are only marked in their tiles; the dilation
+        // creates every slot of the region, then the bits are ORed in
         const int64_t n = map->n_blocks;
         if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_insert, dim3(grid_for(n, 256, 4096)), dim3(256), 0,
+            hipLaunchKernelGGL(k_ingest_blocks_mark, dim3(grid_for(n, 1, 16384)), dim3(64), 0,
                                st, g, map->d_block_xyz, map->d_block_occ, n);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;
-        hipLaunchKernelGGL(k_zero_occ, dim3(grid_for((int64_t)g.max_blocks * 16, 256, 4096)),
-                           dim3(256), 0, st, g, -1);
         if (n > 0)
             hipLaunchKernelGGL(k_ingest_blocks_write, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st,
                                g, map->d_block_xyz, map->d_block_occ, n);

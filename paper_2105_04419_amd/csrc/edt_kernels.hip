@@ -159,7 +159,11 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int32_t sj = __shfl(slot, j);
-        if (sj >= 0) occ8[(int64_t)sj * 64 + lane] = (uint8_t)bytes[j];
+        if (sj >= 0) {
+            occ8[(int64_t)sj * 64 + lane] = (uint8_t)bytes[j];
+            uint32_t* chg = lane < 16 ? g.chg_add : g.chg_rem;
+            if (lane < 32) chg[(int64_t)sj * 16 + (lane & 15)] = 0u;
+        }
     }
 }
 
@@ -187,57 +191,37 @@ __device__ inline uint32_t block_row_bits(const Grid& g, const int32_t* xyz,
     return b;
 }
 
-// One thread per input block: it reads the block's 512 bytes, decides whether
-// it holds an obstacle inside the extent, and inserts it (one slot-counter
-// atomic per wave).
-__global__ void __launch_bounds__(256) k_ingest_blocks_insert(Grid g, const int32_t* xyz,
-                                                              const uint8_t* data, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - threadIdx.x < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        bool mine = false;
-        int bx = 0, by = 0, bz = 0;
-        if (i < n) {
-            bx = xyz[3 * i];
-            by = xyz[3 * i + 1];
-            bz = xyz[3 * i + 2];
-            const bool ok = bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz;
-            if (!ok) set_error(g, -2 /* EDT_ERR_RANGE */);
-            if (ok) {
-                const int xr = g.nx - 8 * bx;
-                const unsigned long long xm =
-                    xr >= 8 ? ~0ull : 0x0101010101010101ull * ((1u << xr) - 1u);
-                const uint4* p = (const uint4*)(data + i * 512);
-                bool any = false;
-#pragma unroll 8
-                for (int r = 0; r < 32; ++r) {       // 16 bytes = rows 2r and 2r + 1
-                    const uint4 v = p[r];
-                    const int y0 = 8 * by + ((2 * r) & 7), z0 = 8 * bz + ((2 * r) >> 3);
-                    const int y1 = 8 * by + ((2 * r + 1) & 7);
-                    const unsigned long long lo = ((unsigned long long)v.y << 32) | v.x;
-                    const unsigned long long hi = ((unsigned long long)v.w << 32) | v.z;
-                    // a nonzero byte marks an occupied voxel; xm keeps the x < nx bytes
-                    const bool r0 = z0 < g.nz && y0 < g.ny && (lo & (xm * 0xffull)) != 0;
-                    const bool r1 = z0 < g.nz && y1 < g.ny && (hi & (xm * 0xffull)) != 0;
-                    any = any || r0 || r1;
-                }
-                mine = any;
+// Block list, phase 1: record every block holding an obstacle in its tile's
+// obstacle mask (creating the tile).  One wave per input block; lane = row
+// (y + 8z) reads its 8 bytes.  Pool slots are assigned by the dilation.
+__global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t* xyz,
+                                                          const uint8_t* data, int64_t n) {
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        int bx, by, bz;
+        bool ok;
+        const uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
+        if (!ok) {
+            if (lane == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+            continue;
+        }
+        if (__ballot(b != 0u) == 0ull) continue;
+        if (lane == 0) {
+            bool tnew = false;
+            const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
+            if (t < 0) {
+                set_error(g, -3 /* EDT_ERR_CAPACITY */);
+            } else {
+                const int local = block_local(bx, by, bz);
+                atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
+                if (tnew) g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
+                if (atomicOr(&g.tflag[t], 1) == 0) g.olist[atomicAdd(&g.cnt[C_NOTILE], 1)] = t;
             }
         }
-        int64_t e = -1;
-        bool created = false, tnew = false;
-        const unsigned long long key = pack_key(bx, by, bz);
-        if (mine) {
-            e = insert_block(g, bx, by, bz, &created, &tnew);
-            if (e < 0) set_error(g, -3);
-        }
-        note_tile(g, tnew, e, mine);
-        const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
-        const int ndil = __popcll(__ballot(slot >= 0));
-        if (__lane_id() == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
     }
 }
 
-// phase 2 (after zeroing the occupancy of the new slots): OR the bits in.
+// phase 2 (after the dilation created and zeroed every slot): OR the bits in.
 __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_t* xyz,
                                                             const uint8_t* data, int64_t n) {
     const int lane = threadIdx.x;
@@ -249,20 +233,6 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_
         int32_t slot = find_block(g, bx, by, bz);
         if (slot < 0) continue;
         atomicOr(&g.occ[(int64_t)slot * 16 + (lane >> 2)], b << (8 * (lane & 3)));
-    }
-}
-
-// zero the occupancy words of slots [first, NBLK) and the update-change
-// masks of all slots
-__global__ void k_zero_occ(Grid g, int first_counter) {
-    const int64_t first = first_counter < 0 ? 0 : g.cnt[first_counter];
-    const int64_t n = g.cnt[C_NBLK];
-    const int64_t lim = (n < g.max_blocks ? n : g.max_blocks);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < lim * 16;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (i >= first * 16) g.occ[i] = 0u;
-        g.chg_add[i] = 0u;
-        g.chg_rem[i] = 0u;
     }
 }
 
@@ -368,17 +338,63 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
             dil[lane] = (uint8_t)d;
         }
         __syncthreads();
-        // create the dilated blocks that are missing; lane = row (y, z)
+        // create the dilated blocks that are missing; lane = row (y, z), its
+        // 8 table entries are 8 lane .. 8 lane + 7.  One counter atomic per
+        // tile; the new slots are contiguous.
         const int y = lane & 7, z = lane >> 3;
         const int by = 8 * ty + y, bz = 8 * tz + z;
         const uint32_t d = dil[lane];
-        for (int x = 0; x < 8; ++x) {
-            const int bx = 8 * tx + x;
-            const int64_t e = (int64_t)t * 512 + x + 8 * y + 64 * z;
-            const bool want = ((d >> x) & 1u) && bx < g.nbx && by < g.nby && bz < g.nbz &&
-                              g.tslots[e] == -1;
-            if (want) g.tslots[e] = SLOT_PENDING;
-            claim_slots(g, want, e, pack_key(bx, by, bz), 0u);
+        const int64_t e0 = (int64_t)t * 512 + 8 * lane;
+        const int4 ta = *(const int4*)(g.tslots + e0), tb = *(const int4*)(g.tslots + e0 + 4);
+        const int32_t ex[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+        const int nc = TR + w * (TR + w * TR);            // centre tile in nmask
+        const uint32_t ob = (nmask[nc * 16 + (lane >> 2)] >> (8 * (lane & 3))) & 0xffu;
+        uint32_t want = 0u;
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+            if (((d >> x) & 1u) && 8 * tx + x < g.nbx && by < g.nby && bz < g.nbz && ex[x] == -1)
+                want |= 1u << x;
+        const int c = __popc(want);
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        const int total = __shfl(incl, 63);
+        if (total > 0) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&g.cnt[C_NBLK], total);
+            base = __shfl(base, 0);
+            int slot = base + incl - c;
+            int nobst = 0;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                if (!((want >> x) & 1u)) continue;
+                const bool o = (ob >> x) & 1u;
+                if (slot < g.max_blocks) {
+                    g.tslots[e0 + x] = slot;
+                    g.bkey[slot] = pack_key(8 * tx + x, by, bz);
+                    g.flags[slot] = o ? F_DILATED : 0u;
+                    nobst += o ? 1 : 0;
+                } else {
+                    g.tslots[e0 + x] = -1;
+                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                    g.cnt[C_ABORT] = 1;
+                }
+                ++slot;
+            }
+            // obstacle blocks created here (block-list input) are counted as
+            // obstacle blocks; zero the occupancy and change masks of the
+            // new slots [base, base + total)
+            nobst = wave_sum(nobst);
+            if (lane == 0 && nobst) atomicAdd(&g.cnt[C_NDIL], nobst);
+            const int64_t lo = base, hi = min((int64_t)base + total, (int64_t)g.max_blocks);
+            for (int64_t k = lo * 16 + lane; k < hi * 16; k += 64) {
+                g.occ[k] = 0u;
+                g.chg_add[k] = 0u;
+                g.chg_rem[k] = 0u;
+            }
         }
         __syncthreads();
     }
