@@ -49,7 +49,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TFLAG, O_TLIST, O_OLIST, O_BMIN, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -84,7 +84,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
-        L->tcap * 64, L->tcap * 4, L->tcap * 4, L->tcap * 4, mb * 4};
+        L->tcap * 64, L->tcap * 4, mb * 4};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -286,9 +286,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.dummy = (uint32_t*)(b + L.off[O_DUMMY]);
     g.dblock = (uint16_t*)(b + L.off[O_DBLOCK]);
     g.tobst = (uint32_t*)(b + L.off[O_TOBST]);
-    g.tflag = (int32_t*)(b + L.off[O_TFLAG]);
     g.tlist = (int32_t*)(b + L.off[O_TLIST]);
-    g.olist = (int32_t*)(b + L.off[O_OLIST]);
     g.bmin1 = (uint16_t*)(b + L.off[O_BMIN]);
     g.bmin2 = g.bmin1 + L.max_blocks;
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
@@ -402,7 +400,8 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         mark(c, 2, st);
     } else {
         // obstacle blocks are only marked in their tiles; the dilation
-        // creates every slot of the region, then the bits are ORed in
+        // creates (and zeroes) every slot of the region, then the bits are
+        // ORed in
         const int64_t n = map->n_blocks;
         if (n > 0)
             hipLaunchKernelGGL(k_ingest_blocks_mark, dim3(grid_for(n, 1, 16384)), dim3(64), 0,

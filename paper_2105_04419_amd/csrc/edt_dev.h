@@ -62,9 +62,8 @@ struct Grid {
     unsigned long long* tkeys;   // tile hash keys
     int32_t* tslots;             // [tile position][512] pool slot of each block
     uint32_t* tobst;             // [tile position][16] blocks holding an obstacle (global)
-    int32_t* tflag;              // [tile position] tile holds an obstacle block (global)
-    int32_t* tlist;              // tile positions in use (global transform)
-    int32_t* olist;              // tile positions holding obstacle blocks
+    int32_t* tlist;              // tile positions in use (global transform); the first
+                                 // cnt[C_NOTILE] hold obstacle blocks
     unsigned long long* bkey;
     uint32_t* occ;
     uint16_t* g1;

@@ -50,24 +50,22 @@ __global__ void k_begin_global(Grid g, int64_t tcap) {
     int4* ts = (int4*)g.tslots;
     for (int64_t i = tid; i < tcap * 128; i += stride) ts[i] = make_int4(-1, -1, -1, -1);
     for (int64_t i = tid; i < tcap * 16; i += stride) g.tobst[i] = 0u;
-    for (int64_t i = tid; i < tcap; i += stride) g.tflag[i] = 0;
     if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
 }
 
-// Record a new tile (global transform) and, for obstacle blocks, the block in
-// its tile's obstacle mask (the tile goes to the obstacle-tile list once).
+// Record a new tile and, for obstacle blocks, the block in its tile's obstacle
+// mask.  Ingest creates tiles for obstacle blocks only, so the tiles listed
+// before the dilation (cnt[C_NOTILE] of them) are the obstacle tiles.
 __device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bool obstacle) {
     const int t = e >= 0 ? (int)(e >> 9) : -1;
     const int j = wave_append(tile_created, &g.cnt[C_NTILE]);
     if (tile_created) g.tlist[j] = t;
-    bool first = false;
+    const int n = __popcll(__ballot(tile_created));
+    if (__lane_id() == 0 && n) atomicAdd(&g.cnt[C_NOTILE], n);
     if (obstacle && e >= 0) {
         const int local = (int)(e & 511);
         atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-        first = atomicOr(&g.tflag[t], 1) == 0;
     }
-    const int k = wave_append(first, &g.cnt[C_NOTILE]);
-    if (first) g.olist[k] = t;
 }
 
 __global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
@@ -214,25 +212,34 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
             } else {
                 const int local = block_local(bx, by, bz);
                 atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-                if (tnew) g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
-                if (atomicOr(&g.tflag[t], 1) == 0) g.olist[atomicAdd(&g.cnt[C_NOTILE], 1)] = t;
+                if (tnew) {
+                    g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
+                    atomicAdd(&g.cnt[C_NOTILE], 1);
+                }
             }
         }
     }
 }
 
-// phase 2 (after the dilation created and zeroed every slot): OR the bits in.
+// Block list, phase 2 (after the dilation created and zeroed every slot): OR
+// the bits in (repeated listings merge).  One wave per input block; 8 lanes
+// each OR one 64-bit word (8 rows) of the block's occupancy.
 __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_t* xyz,
-                                                            const uint8_t* data, int64_t n) {
+                                                           const uint8_t* data, int64_t n) {
     const int lane = threadIdx.x;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         int bx, by, bz;
         bool ok;
-        uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
-        if (!ok || b == 0) continue;
-        int32_t slot = find_block(g, bx, by, bz);
+        const uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
+        if (!ok || __ballot(b != 0u) == 0ull) continue;
+        const int32_t slot = find_block(g, bx, by, bz);
         if (slot < 0) continue;
-        atomicOr(&g.occ[(int64_t)slot * 16 + (lane >> 2)], b << (8 * (lane & 3)));
+        // gather rows 8q .. 8q + 7 into lane 8q's 64-bit word
+        unsigned long long w = (unsigned long long)b << (8 * (lane & 7));
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) w |= __shfl_xor(w, o);
+        if ((lane & 7) == 0 && w)
+            atomicOr((unsigned long long*)g.occ + (int64_t)slot * 8 + (lane >> 3), w);
     }
 }
 
@@ -250,7 +257,7 @@ __global__ void k_tile_neighbours(Grid g) {
         bool tnew = false;
         int32_t t = -1;
         if (i < total) {
-            const int ot = g.olist[i / w3];
+            const int ot = g.tlist[i / w3];
             const int o = (int)(i % w3);
             int tx, ty, tz;
             unpack_key(g.tkeys[ot], tx, ty, tz);

@@ -95,6 +95,24 @@ def test_block_input_equals_dense_input():
     assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 20))
 
 
+def test_block_input_repeats_beyond_pool_size():
+    """More repeated listings than pool slots: every listing is still merged
+    (the repeat list overflows and all blocks are ORed in again)."""
+    rng = np.random.default_rng(11)
+    occ = np.zeros((16, 16, 16), np.uint8)
+    occ[4:12, 4:12, 4:12] = (rng.random((8, 8, 8)) < 0.3)
+    xyz, data = workloads.dense_to_blocks(occ)
+    # each voxel of each block goes to one of 40 listings of that block
+    pick = rng.integers(0, 40, size=data.shape)
+    xyz_r = np.concatenate([xyz] * 40)
+    data_r = np.concatenate([np.where(pick == k, data, 0) for k in range(40)]).astype(np.uint8)
+    f = Field((16, 16, 16), 5, max_blocks=8)
+    assert len(xyz_r) - len(xyz) > 8
+    f.global_blocks(torch.from_numpy(xyz_r).cuda(), torch.from_numpy(data_r).cuda())
+    assert f.error() == 0
+    assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 5))
+
+
 def test_block_input_ragged_extent_and_range_error():
     """Voxels of a block beyond the extent are ignored; blocks outside the
     extent are skipped and reported."""
