@@ -45,19 +45,30 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def traffic_record(kernel: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    or None if absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_tunnel_traffic.md")
+KERNEL_SOURCES = ("edt_api.hip", "edt_dev.h", "edt_kernels.hip", "edt_win.h")
+
+
+def kernel_source_sha256() -> str:
+    """Digest of the sources that define the global-transform kernels and
+    their launches; a committed counter summary holds only for this digest."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_04419_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_record(kernel: str, kind: str, field: str):
+    """A per-launch figure from the committed rocprofv3 counter summary
+    profiles/{kernel}_tunnel_{kind}.md, or None if absent or taken on other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_tunnel_{kind}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
-    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b:
-        return None
-    src = open(os.path.join(ROOT, "paper_2105_04419_amd", "csrc", "edt_kernels.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != m.group(1):
+    b = re.search(field + r":\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_sha256():
         return None
     return float(b.group(1))
 
@@ -115,7 +126,8 @@ def roofline(g, dmax):
     kern = max(per_launch, key=lambda k: ph[k])
     ms = ph[kern]
     achieved = per_launch[kern] / (ms * 1e-3) / 1e9
-    tr = traffic_record(kern)
+    tr = counter_record(kern, "traffic", "traffic_bytes_per_launch")
+    valu = counter_record(kern, "traffic", "valu_insts_per_launch")
     return {
         "kernel": names[kern],
         "bound": "hbm",
@@ -126,6 +138,10 @@ def roofline(g, dmax):
         "traffic": tr,
         "algorithmic_bytes_per_launch": per_launch[kern],
         "mean_ms": round(ms, 5),
+        # share of the VALU issue cycles of all 1024 SIMDs at 2.4 GHz that the
+        # kernel's counted VALU instructions fill (4 cycles per wave64 op)
+        "valu_busy_frac": (round(valu * 4 / (1024 * 2.4e9 * ms * 1e-3), 3)
+                           if valu is not None else None),
     }
 
 
