@@ -167,6 +167,68 @@ def bench_cpu(g, args, np):
     }, ref
 
 
+def bench_cpu_single(g, args, np):
+    """The oracle on one host thread (the paper times its method on one
+    core): one full separable transform of the tunnel extent."""
+    import oracle
+    prev = oracle.threads()
+    oracle.threads(1)
+    t0 = time.perf_counter()
+    oracle.edt_separable(g["occ"], args.dmax)
+    t = time.perf_counter() - t0
+    oracle.threads(prev)
+    return {"value": g["n_ext"] / t, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"one separable oracle run on the full tunnel extent, {t:.1f} s"}
+
+
+def bench_tunnel_x4(args, torch, np):
+    """The tunnel map tiled 2 x 2 in x and y (2048 x 2048 x 128 extent, four
+    times the region): its pool and intermediates exceed the 256 MB last-level
+    cache, so the pass rates here are HBM rates."""
+    import workloads
+    from paper_2105_04419_amd import Field
+    occ = workloads.tunnels(args.seed)
+    nz, ny, nx = occ.shape
+    bxyz, bocc = workloads.dense_to_blocks(occ)
+    tiles = []
+    for j in range(2):
+        for i in range(2):
+            t = bxyz.copy()
+            t[:, 0] += i * (nx // 8)
+            t[:, 1] += j * (ny // 8)
+            tiles.append(t)
+    xyz_d = torch.from_numpy(np.concatenate(tiles)).cuda()
+    occ_d = torch.from_numpy(np.concatenate([bocc] * 4)).cuda()
+    f = Field((2 * nx, 2 * ny, nz), args.dmax)
+    for _ in range(2):
+        f.global_blocks(xyz_d, occ_d)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    f.timing_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f.global_blocks(xyz_d, occ_d)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ph = f.timing_read()
+    f.timing_begin(0)
+    st = f.stats()
+    assert st["error"] == 0, st
+    nb = st["blocks"]
+    per_voxel = {"pass_x": (64 + 1024 + 2) / 512, "pass_y": 4 + 4 / 512, "pass_z": 4 + 6 / 512}
+    return {
+        "workload": f"tunnel map tiled 2x2: {2 * nx}x{2 * ny}x{nz}, d_max {args.dmax}",
+        "region_blocks": nb,
+        "ms_per_transform": round(ms, 4),
+        "extent_voxels_per_s": 4 * nx * ny * nz / (ms * 1e-3),
+        "region_voxels_per_s": nb * 512 / (ms * 1e-3),
+        "phases_ms": {k: round(v, 5) for k, v in ph.items() if k != "calls"},
+        "pass_algorithmic_GBps": {k: round(nb * 512 * v / (ph[k] * 1e-3) / 1e9, 1)
+                                  for k, v in per_voxel.items()},
+    }
+
+
 def bench_incremental(g, args, torch, np):
     import workloads
     from workloads.scans import ScanSim, tunnel_path
@@ -359,6 +421,9 @@ def main():
         out["cpu_baseline"] = cb
         got = g["f"].dense().cpu().numpy()
         out["parity_global_vs_oracle"] = bool(np.array_equal(got, ref))
+        if not args.no_extra:
+            log("[bench] cpu oracle, one thread")
+            out["cpu_single_thread"] = bench_cpu_single(g, args, np)
     if not args.no_extra:
         log(f"[bench] incremental: {args.scans} scans")
         out["incremental"] = bench_incremental(g, args, torch, np)
@@ -368,6 +433,8 @@ def main():
         out["batched"] = bench_batch(args, torch, np)
         log("[bench] dense 64x64x32 global transform")
         out["dense_small"] = bench_dense_small(args, torch, np)
+        log("[bench] tunnel map tiled 2x2 (working set beyond the last-level cache)")
+        out["tunnel_x4"] = bench_tunnel_x4(args, torch, np)
     print(json.dumps(out), flush=True)
 
 
