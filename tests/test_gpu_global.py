@@ -48,6 +48,11 @@ def test_dense_boxes_matches_oracle(seed):
     ((16, 16, 16), 0.0005, 255), ((24, 40, 72), 0.0002, 255), ((9, 9, 9), 0.3, 1),
     ((64, 8, 8), 0.01, 12), ((8, 64, 8), 0.01, 12), ((8, 8, 64), 0.01, 12),
     ((17, 130, 19), 0.002, 40), ((130, 17, 19), 0.002, 40),
+    # window radii M = 6, 7, 8 and the first radius of the envelope path, on
+    # extents spanning several 64-voxel tiles along every pass axis
+    ((66, 70, 140), 0.0008, 48), ((140, 66, 70), 0.0008, 56),
+    ((72, 150, 80), 0.0004, 64), ((150, 72, 80), 0.0004, 57),
+    ((80, 80, 80), 0.0003, 65), ((70, 140, 66), 0.0006, 100),
 ])
 def test_adversarial_grids(shape, p, dmax):
     rng = np.random.default_rng(hash((shape, p, dmax)) % (1 << 32))

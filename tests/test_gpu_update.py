@@ -62,7 +62,7 @@ def random_batch(rng, occ, n, p_add=0.5):
 
 @pytest.mark.parametrize("shape,p,dmax", [
     ((29, 37, 50), 0.002, 5), ((24, 40, 48), 0.001, 12), ((32, 32, 32), 0.0005, 20),
-    ((16, 24, 96), 0.003, 32),
+    ((16, 24, 96), 0.003, 32), ((40, 72, 72), 0.0005, 64), ((24, 40, 80), 0.0008, 70),
 ])
 def test_random_update_sequences(shape, p, dmax):
     rng = np.random.default_rng(abs(hash((shape, dmax))) % (1 << 32))
