@@ -404,14 +404,14 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         // ORed in
         const int64_t n = map->n_blocks;
         if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_mark, dim3(grid_for(n, 1, 16384)), dim3(64), 0,
-                               st, g, map->d_block_xyz, map->d_block_occ, n);
+            hipLaunchKernelGGL(k_ingest_blocks_mark, dim3(grid_for((n + 7) / 8, 1, 16384)),
+                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;
         if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_write, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st,
-                               g, map->d_block_xyz, map->d_block_occ, n);
+            hipLaunchKernelGGL(k_ingest_blocks_write, dim3(grid_for((n + 7) / 8, 1, 16384)),
+                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n);
         mark(c, 2, st);
     }
     LAUNCH_CHECK();

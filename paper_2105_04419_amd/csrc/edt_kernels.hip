@@ -165,81 +165,92 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
     }
 }
 
-// Block list, phase 1: insert every block holding an obstacle.
-// One wave per input block; lane = row (y + 8z) reads its 8 bytes.
-__device__ inline uint32_t block_row_bits(const Grid& g, const int32_t* xyz,
-                                          const uint8_t* data, int64_t i, int lane,
-                                          int& bx, int& by, int& bz, bool& in_range) {
+// Block list: eight input blocks per wave, eight lanes per block.  Lane q of
+// a block reads rows 8q .. 8q + 7 (64 bytes: z = q, y = 0..7) and returns
+// their bit rows as one 64-bit word, which is word q of the block's
+// occupancy; voxels beyond the extent are dropped.
+__device__ inline unsigned long long block_rows8(const Grid& g, const int32_t* xyz,
+                                                 const uint8_t* data, int64_t i, int q,
+                                                 int& bx, int& by, int& bz, bool& in_range) {
     bx = xyz[3 * i];
     by = xyz[3 * i + 1];
     bz = xyz[3 * i + 2];
     in_range = bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz;
-    const uint2 v = *(const uint2*)(data + i * 512 + 8 * lane);
-    uint32_t b = 0;
+    const uint4* p = (const uint4*)(data + i * 512 + 64 * q);
+    uint4 v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        b |= (((v.x >> (8 * k)) & 0xff) != 0) << k;
-        b |= (((v.y >> (8 * k)) & 0xff) != 0) << (k + 4);
-    }
-    // voxels beyond the extent are not part of the map
-    const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
-    if (y >= g.ny || z >= g.nz) b = 0;
+    for (int w = 0; w < 4; ++w) v[w] = p[w];
     const int xr = g.nx - 8 * bx;
-    if (xr < 8) b &= (xr <= 0) ? 0u : ((1u << xr) - 1u);
-    return b;
+    const uint32_t xm = xr >= 8 ? 0xffu : (xr <= 0 ? 0u : (1u << xr) - 1u);
+    const bool zok = 8 * bz + q < g.nz;
+    unsigned long long rows = 0ull;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t d[4] = {v[w].x, v[w].y, v[w].z, v[w].w};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {              // row y = 2w + h
+            uint32_t b = 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                b |= (((d[2 * h] >> (8 * k)) & 0xffu) != 0u) << k;
+                b |= (((d[2 * h + 1] >> (8 * k)) & 0xffu) != 0u) << (k + 4);
+            }
+            const bool ok = zok && 8 * by + 2 * w + h < g.ny;
+            rows |= (unsigned long long)(ok ? (b & xm) : 0u) << (8 * (2 * w + h));
+        }
+    }
+    return rows;
 }
 
 // Block list, phase 1: record every block holding an obstacle in its tile's
-// obstacle mask (creating the tile).  One wave per input block; lane = row
-// (y + 8z) reads its 8 bytes.  Pool slots are assigned by the dilation.
+// obstacle mask (creating the tile).  Pool slots are assigned by the
+// dilation.
 __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t* xyz,
                                                           const uint8_t* data, int64_t n) {
-    const int lane = threadIdx.x;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        int bx, by, bz;
-        bool ok;
-        const uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
+    const int lane = threadIdx.x, sub = lane >> 3, q = lane & 7;
+    for (int64_t i0 = (int64_t)blockIdx.x * 8; i0 < n; i0 += (int64_t)gridDim.x * 8) {
+        const int64_t i = i0 + sub;
+        int bx = 0, by = 0, bz = 0;
+        bool ok = false;
+        unsigned long long rows = 0ull;
+        if (i < n) rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
+        const bool any = ((__ballot(rows != 0ull) >> (8 * sub)) & 0xffull) != 0ull;
+        if (q != 0 || i >= n) continue;
         if (!ok) {
-            if (lane == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+            set_error(g, -2 /* EDT_ERR_RANGE */);
             continue;
         }
-        if (__ballot(b != 0u) == 0ull) continue;
-        if (lane == 0) {
-            bool tnew = false;
-            const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
-            if (t < 0) {
-                set_error(g, -3 /* EDT_ERR_CAPACITY */);
-            } else {
-                const int local = block_local(bx, by, bz);
-                atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-                if (tnew) {
-                    g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
-                    atomicAdd(&g.cnt[C_NOTILE], 1);
-                }
-            }
+        if (!any) continue;
+        bool tnew = false;
+        const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
+        if (t < 0) {
+            set_error(g, -3 /* EDT_ERR_CAPACITY */);
+            continue;
+        }
+        const int local = block_local(bx, by, bz);
+        atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
+        if (tnew) {
+            g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
+            atomicAdd(&g.cnt[C_NOTILE], 1);
         }
     }
 }
 
 // Block list, phase 2 (after the dilation created and zeroed every slot): OR
-// the bits in (repeated listings merge).  One wave per input block; 8 lanes
-// each OR one 64-bit word (8 rows) of the block's occupancy.
+// the bits in (repeated listings merge), one 64-bit word per lane.
 __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_t* xyz,
                                                            const uint8_t* data, int64_t n) {
-    const int lane = threadIdx.x;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int lane = threadIdx.x, sub = lane >> 3, q = lane & 7;
+    for (int64_t i0 = (int64_t)blockIdx.x * 8; i0 < n; i0 += (int64_t)gridDim.x * 8) {
+        const int64_t i = i0 + sub;
+        if (i >= n) continue;
         int bx, by, bz;
         bool ok;
-        const uint32_t b = block_row_bits(g, xyz, data, i, lane, bx, by, bz, ok);
-        if (!ok || __ballot(b != 0u) == 0ull) continue;
+        const unsigned long long rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
+        if (!ok || rows == 0ull) continue;
         const int32_t slot = find_block(g, bx, by, bz);
         if (slot < 0) continue;
-        // gather rows 8q .. 8q + 7 into lane 8q's 64-bit word
-        unsigned long long w = (unsigned long long)b << (8 * (lane & 7));
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) w |= __shfl_xor(w, o);
-        if ((lane & 7) == 0 && w)
-            atomicOr((unsigned long long*)g.occ + (int64_t)slot * 8 + (lane >> 3), w);
+        atomicOr((unsigned long long*)g.occ + (int64_t)slot * 8 + q, rows);
     }
 }
 
