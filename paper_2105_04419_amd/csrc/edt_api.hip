@@ -205,8 +205,6 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
 edt_status dilate_region(edt_ctx* c, hipStream_t st) {
     Grid& g = c->g;
     const int TR = (g.R + 7) / 8, w = 2 * TR + 1;
-    hipLaunchKernelGGL(k_tile_neighbours, dim3(grid_for(c->tcap * w * w * w, 256, 1024)), dim3(256),
-                       0, st, g);
     const int E = 8 + 2 * g.R;
     const size_t lds = (size_t)w * w * w * 64 + E * E + E * 8 + 64;
     hipLaunchKernelGGL(k_tile_dilate, dim3(grid_for(c->tcap, 1, 4096)), dim3(64), lds, st, g);

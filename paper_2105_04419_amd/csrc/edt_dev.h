@@ -48,7 +48,7 @@ enum : uint32_t {
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_SNAP, C_SNAP2,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
-    C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_NOTILE, C_N
+    C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_N
 };
 
 struct Grid {
@@ -62,8 +62,7 @@ struct Grid {
     unsigned long long* tkeys;   // tile hash keys
     int32_t* tslots;             // [tile position][512] pool slot of each block
     uint32_t* tobst;             // [tile position][16] blocks holding an obstacle (global)
-    int32_t* tlist;              // tile positions in use (global transform); the first
-                                 // cnt[C_NOTILE] hold obstacle blocks
+    int32_t* tlist;              // tile positions in use (global transform)
     unsigned long long* bkey;
     uint32_t* occ;
     uint16_t* g1;

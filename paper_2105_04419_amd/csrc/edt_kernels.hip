@@ -53,19 +53,49 @@ __global__ void k_begin_global(Grid g, int64_t tcap) {
     if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
 }
 
-// Record a new tile and, for obstacle blocks, the block in its tile's obstacle
-// mask.  Ingest creates tiles for obstacle blocks only, so the tiles listed
-// before the dilation (cnt[C_NOTILE] of them) are the obstacle tiles.
-__device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bool obstacle) {
+// Every tile within ceil(R / 8) tiles of an obstacle tile must exist before
+// the dilation.  Called by a whole wave: for each lane that created an
+// obstacle tile (tile coordinates tx, ty, tz), the wave inserts the tile's
+// neighbours, one neighbour per lane.
+__device__ inline void grow_tiles(const Grid& g, bool created, int tx, int ty, int tz) {
+    unsigned long long m = __ballot(created);
+    if (m == 0ull) return;
+    const int TR = (g.R + 7) >> 3, w = 2 * TR + 1, w3 = w * w * w;
+    const int ntx = (g.nbx + 7) >> 3, nty = (g.nby + 7) >> 3, ntz = (g.nbz + 7) >> 3;
+    const int lane = __lane_id();
+    while (m) {
+        const int src = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int cx = __shfl(tx, src), cy = __shfl(ty, src), cz = __shfl(tz, src);
+        for (int o0 = 0; o0 < w3; o0 += 64) {
+            const int o = o0 + lane;
+            bool tnew = false;
+            int32_t t = -1;
+            if (o < w3 && o != w3 / 2) {
+                const int ax = cx + o % w - TR, ay = cy + (o / w) % w - TR, az = cz + o / (w * w) - TR;
+                if (ax >= 0 && ay >= 0 && az >= 0 && ax < ntx && ay < nty && az < ntz) {
+                    t = hinsert(g.tkeys, g.tmask, pack_key(ax, ay, az), &tnew);
+                    if (t < 0) set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                }
+            }
+            const int j = wave_append(tnew, &g.cnt[C_NTILE]);
+            if (tnew) g.tlist[j] = t;
+        }
+    }
+}
+
+// Record a new tile (and its neighbourhood) and, for obstacle blocks, the
+// block in its tile's obstacle mask.  Called by a whole wave.
+__device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bool obstacle,
+                                 int bx, int by, int bz) {
     const int t = e >= 0 ? (int)(e >> 9) : -1;
     const int j = wave_append(tile_created, &g.cnt[C_NTILE]);
     if (tile_created) g.tlist[j] = t;
-    const int n = __popcll(__ballot(tile_created));
-    if (__lane_id() == 0 && n) atomicAdd(&g.cnt[C_NOTILE], n);
     if (obstacle && e >= 0) {
         const int local = (int)(e & 511);
         atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
     }
+    grow_tiles(g, tile_created, bx >> 3, by >> 3, bz >> 3);
 }
 
 __global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
@@ -149,7 +179,7 @@ __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __re
         e = insert_block(g, bx0 + lane, by, bz, &created, &tnew);
         if (e < 0) set_error(g, -3);
     }
-    note_tile(g, tnew, e, mine);
+    note_tile(g, tnew, e, mine, bx0 + lane, by, bz);
     const int32_t slot = claim_slots(g, created, e, key, F_DILATED);
     const int ndil = __popcll(__ballot(slot >= 0));
     if (lane == 0 && ndil) atomicAdd(&g.cnt[C_NDIL], ndil);
@@ -203,8 +233,8 @@ __device__ inline unsigned long long block_rows8(const Grid& g, const int32_t* x
 }
 
 // Block list, phase 1: record every block holding an obstacle in its tile's
-// obstacle mask (creating the tile).  Pool slots are assigned by the
-// dilation.
+// obstacle mask (creating the tile and its neighbourhood).  Pool slots are
+// assigned by the dilation.
 __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t* xyz,
                                                           const uint8_t* data, int64_t n) {
     const int lane = threadIdx.x, sub = lane >> 3, q = lane & 7;
@@ -215,24 +245,27 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
         unsigned long long rows = 0ull;
         if (i < n) rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
         const bool any = ((__ballot(rows != 0ull) >> (8 * sub)) & 0xffull) != 0ull;
-        if (q != 0 || i >= n) continue;
-        if (!ok) {
-            set_error(g, -2 /* EDT_ERR_RANGE */);
-            continue;
+        bool created = false;
+        if (q == 0 && i < n) {
+            if (!ok) {
+                set_error(g, -2 /* EDT_ERR_RANGE */);
+            } else if (any) {
+                bool tnew = false;
+                const int32_t t =
+                    hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
+                if (t < 0) {
+                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                } else {
+                    const int local = block_local(bx, by, bz);
+                    atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
+                    if (tnew) {
+                        g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
+                        created = true;
+                    }
+                }
+            }
         }
-        if (!any) continue;
-        bool tnew = false;
-        const int32_t t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
-        if (t < 0) {
-            set_error(g, -3 /* EDT_ERR_CAPACITY */);
-            continue;
-        }
-        const int local = block_local(bx, by, bz);
-        atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-        if (tnew) {
-            g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
-            atomicAdd(&g.cnt[C_NOTILE], 1);
-        }
+        grow_tiles(g, created, bx >> 3, by >> 3, bz >> 3);
     }
 }
 
@@ -258,33 +291,6 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_
 // region growth on tiles: every block within R blocks (Chebyshev) of an
 // obstacle block joins the pool.  TR = ceil(R / 8) tiles of neighbourhood.
 // ---------------------------------------------------------------------------
-// Every tile within TR tiles of an obstacle tile must exist.
-__global__ void k_tile_neighbours(Grid g) {
-    const int TR = (g.R + 7) >> 3, w = 2 * TR + 1, w3 = w * w * w;
-    const int ntx = (g.nbx + 7) >> 3, nty = (g.nby + 7) >> 3, ntz = (g.nbz + 7) >> 3;
-    const int64_t total = (int64_t)g.cnt[C_NOTILE] * w3;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - threadIdx.x < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        bool tnew = false;
-        int32_t t = -1;
-        if (i < total) {
-            const int ot = g.tlist[i / w3];
-            const int o = (int)(i % w3);
-            int tx, ty, tz;
-            unpack_key(g.tkeys[ot], tx, ty, tz);
-            tx += o % w - TR;
-            ty += (o / w) % w - TR;
-            tz += o / (w * w) - TR;
-            if (tx >= 0 && ty >= 0 && tz >= 0 && tx < ntx && ty < nty && tz < ntz) {
-                t = hinsert(g.tkeys, g.tmask, pack_key(tx, ty, tz), &tnew);
-                if (t < 0) set_error(g, -3);
-            }
-        }
-        const int j = wave_append(tnew, &g.cnt[C_NTILE]);
-        if (tnew) g.tlist[j] = t;
-    }
-}
-
 // One workgroup per tile: OR the obstacle masks of the tile neighbourhood
 // shifted by -R..R along x, then y, then z (separable Chebyshev dilation on
 // bit rows in LDS) and create the missing blocks of the dilated mask.
