@@ -49,7 +49,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -84,7 +84,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
-        L->tcap * 64, L->tcap * 4, mb * 4};
+        L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -285,6 +285,8 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.dblock = (uint16_t*)(b + L.off[O_DBLOCK]);
     g.tobst = (uint32_t*)(b + L.off[O_TOBST]);
     g.tlist = (int32_t*)(b + L.off[O_TLIST]);
+    g.tinfo = (int32_t*)(b + L.off[O_TINFO]);
+    g.tflag = (int32_t*)(b + L.off[O_TFLAG]);
     g.bmin1 = (uint16_t*)(b + L.off[O_BMIN]);
     g.bmin2 = g.bmin1 + L.max_blocks;
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2

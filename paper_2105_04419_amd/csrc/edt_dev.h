@@ -62,7 +62,12 @@ struct Grid {
     unsigned long long* tkeys;   // tile hash keys
     int32_t* tslots;             // [tile position][512] pool slot of each block
     uint32_t* tobst;             // [tile position][16] blocks holding an obstacle (global)
+    int32_t* tflag;              // [tile position] nonzero once the tile holds an obstacle
+                                 // block (global transform)
     int32_t* tlist;              // tile positions in use (global transform)
+    int32_t* tinfo;              // [tile list index][8] tile position, then its face
+                                 // neighbours -x, +x, -y, +y, -z, +z (-1 absent;
+                                 // written by the dilation when d_max <= 64)
     unsigned long long* bkey;
     uint32_t* occ;
     uint16_t* g1;

@@ -50,15 +50,18 @@ __global__ void k_begin_global(Grid g, int64_t tcap) {
     int4* ts = (int4*)g.tslots;
     for (int64_t i = tid; i < tcap * 128; i += stride) ts[i] = make_int4(-1, -1, -1, -1);
     for (int64_t i = tid; i < tcap * 16; i += stride) g.tobst[i] = 0u;
+    for (int64_t i = tid; i < tcap; i += stride) g.tflag[i] = 0;
     if (tid < C_N && tid != C_ERR) g.cnt[tid] = 0;
 }
 
 // Every tile within ceil(R / 8) tiles of an obstacle tile must exist before
-// the dilation.  Called by a whole wave: for each lane that created an
-// obstacle tile (tile coordinates tx, ty, tz), the wave inserts the tile's
-// neighbours, one neighbour per lane.
-__device__ inline void grow_tiles(const Grid& g, bool created, int tx, int ty, int tz) {
-    unsigned long long m = __ballot(created);
+// the dilation.  Called by a whole wave: for each lane whose block is the
+// first obstacle block of its tile (tile coordinates tx, ty, tz), the wave
+// inserts the tile's neighbours, one neighbour per lane.  The trigger is the
+// tile's first obstacle, not the tile's creation: a tile may already exist
+// as the neighbour of another obstacle tile.
+__device__ inline void grow_tiles(const Grid& g, bool first, int tx, int ty, int tz) {
+    unsigned long long m = __ballot(first);
     if (m == 0ull) return;
     const int TR = (g.R + 7) >> 3, w = 2 * TR + 1, w3 = w * w * w;
     const int ntx = (g.nbx + 7) >> 3, nty = (g.nby + 7) >> 3, ntz = (g.nbz + 7) >> 3;
@@ -91,11 +94,13 @@ __device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bo
     const int t = e >= 0 ? (int)(e >> 9) : -1;
     const int j = wave_append(tile_created, &g.cnt[C_NTILE]);
     if (tile_created) g.tlist[j] = t;
+    bool first = false;
     if (obstacle && e >= 0) {
         const int local = (int)(e & 511);
         atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
+        first = atomicOr(&g.tflag[t], 1) == 0;
     }
-    grow_tiles(g, tile_created, bx >> 3, by >> 3, bz >> 3);
+    grow_tiles(g, first, bx >> 3, by >> 3, bz >> 3);
 }
 
 __global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
@@ -245,7 +250,7 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
         unsigned long long rows = 0ull;
         if (i < n) rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
         const bool any = ((__ballot(rows != 0ull) >> (8 * sub)) & 0xffull) != 0ull;
-        bool created = false;
+        bool first = false;
         if (q == 0 && i < n) {
             if (!ok) {
                 set_error(g, -2 /* EDT_ERR_RANGE */);
@@ -258,14 +263,12 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
                 } else {
                     const int local = block_local(bx, by, bz);
                     atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-                    if (tnew) {
-                        g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
-                        created = true;
-                    }
+                    if (tnew) g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
+                    first = atomicOr(&g.tflag[t], 1) == 0;
                 }
             }
         }
-        grow_tiles(g, created, bx >> 3, by >> 3, bz >> 3);
+        grow_tiles(g, first, bx >> 3, by >> 3, bz >> 3);
     }
 }
 
@@ -314,6 +317,13 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
                                ? -1
                                : hpos(g.tkeys, g.tmask, pack_key(tx + dx, ty + dy, tz + dz));
             for (int k = 0; k < 16; ++k) nmask[n * 16 + k] = nt >= 0 ? g.tobst[(int64_t)nt * 16 + k] : 0u;
+            // the tile and its face neighbours for the tile passes
+            // (n = dx + 1 + 3 (dy + 1) + 9 (dz + 1) when TR = 1)
+            if (TR == 1) {
+                const int k = n == 13 ? 0 : n == 12 ? 1 : n == 14 ? 2 : n == 10 ? 3
+                            : n == 16 ? 4 : n == 4 ? 5 : n == 22 ? 6 : -1;
+                if (k >= 0) g.tinfo[it * 8 + k] = nt;
+            }
         }
         __syncthreads();
         for (int r = lane; r < E * E; r += 64) {            // x dilation
@@ -467,6 +477,17 @@ __global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t ru
 // ---------------------------------------------------------------------------
 // per-tile variants for the global transform
 // ---------------------------------------------------------------------------
+// Slot of the block at position a in [-8, 16) along one axis of a tile row
+// or column (other coordinates inside the tile; `local` is the in-tile
+// index with that axis' coordinate zero, `stride` its step): the tile below,
+// the tile itself or the tile above, from the face neighbours recorded by
+// the dilation.
+__device__ inline int32_t axis_slot(const Grid& g, int lo, int self, int hi, int a, int local,
+                                    int stride) {
+    const int t = a < 0 ? lo : (a >= 8 ? hi : self);
+    return t < 0 ? -1 : g.tslots[(int64_t)t * 512 + local + stride * (a & 7)];
+}
+
 // Slot of the block at tile-relative position (x, y, z) (each coordinate in
 // [-8, 16)) of the tile at `tpos`, whose tile coordinates are (tx, ty, tz);
 // neighbouring tiles are looked up in the tile hash.
@@ -536,11 +557,9 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
     const uint8_t* occ8 = (const uint8_t*)g.occ;
     const uint32_t dmax = (uint32_t)g.dmax;
     for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-        const int t = g.tlist[it >> 6];
+        const int32_t* ti = g.tinfo + (it >> 6) * 8;
         const int jy = (int)(it & 7), jz = (int)((it >> 3) & 7);
-        int tx, ty, tz;
-        unpack_key(g.tkeys[t], tx, ty, tz);
-        if (lane < NB) sl[lane] = tile_rel_slot(g, t, tx, ty, tz, lane - M, jy, jz);
+        if (lane < NB) sl[lane] = axis_slot(g, ti[1], ti[0], ti[2], lane - M, 8 * jy + 64 * jz, 1);
         __syncthreads();
         bool any = false;
 #pragma unroll
@@ -1055,13 +1074,11 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
     uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
     const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
     for (int64_t it = blockIdx.x; it < ncol; it += gridDim.x) {
-        const int t = g.tlist[it >> 6];
+        const int32_t* ti = g.tinfo + (it >> 6) * 8;
         const int ca = (int)(it & 7), cb = (int)((it >> 3) & 7);
-        int tx, ty, tz;
-        unpack_key(g.tkeys[t], tx, ty, tz);
         if (lane < NB)
-            sl[lane] = AXIS == 1 ? tile_rel_slot(g, t, tx, ty, tz, ca, lane - M, cb)
-                                 : tile_rel_slot(g, t, tx, ty, tz, ca, cb, lane - M);
+            sl[lane] = AXIS == 1 ? axis_slot(g, ti[3], ti[0], ti[4], lane - M, ca + 64 * cb, 8)
+                                 : axis_slot(g, ti[5], ti[0], ti[6], lane - M, ca + 8 * cb, 64);
         __syncthreads();
         bool any = false;
 #pragma unroll

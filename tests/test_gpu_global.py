@@ -118,6 +118,36 @@ def test_block_input_repeats_beyond_pool_size():
     assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 5))
 
 
+def test_tile_created_as_neighbour_then_obstacle():
+    """A tile first created as the neighbour of an obstacle tile and only then
+    given an obstacle block must still bring its own neighbourhood into the
+    region.  Tile x = 0 holds an obstacle deep inside, tile x = 1 one on its
+    +x face, tile x = 2 none but voxels within d_max of the second obstacle.
+    The block list puts the first obstacle at entry 0 and the second at entry
+    131072 with empty blocks between: the ingest walks its input with at most
+    16384 waves of 8 blocks, so one wave takes both, in that order, and tile
+    x = 1 already exists (as a neighbour) when its obstacle arrives."""
+    nx, ny, nz = 192, 64, 64
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    occ[32, 32, 10] = 1
+    occ[32, 32, 127] = 1
+    ref = oracle.edt_separable(occ, 32)
+    xyz, data = workloads.dense_to_blocks(occ)
+    a = int(np.argmin(xyz[:, 0]))
+    b = int(np.argmax(xyz[:, 0]))
+    n = 16384 * 8 + 1
+    xyz_l = np.zeros((n, 3), np.int32)                 # empty blocks at the origin
+    data_l = np.zeros((n, 512), np.uint8)
+    xyz_l[0], data_l[0] = xyz[a], data[a]
+    xyz_l[n - 1], data_l[n - 1] = xyz[b], data[b]
+    f = Field((nx, ny, nz), 32)
+    f.global_blocks(torch.from_numpy(xyz_l).cuda(), torch.from_numpy(data_l).cuda())
+    assert f.error() == 0
+    assert_same(f.dense().cpu().numpy(), ref, "block input")
+    f.global_(torch.from_numpy(occ).cuda())
+    assert_same(f.dense().cpu().numpy(), ref, "dense input")
+
+
 def test_block_input_ragged_extent_and_range_error():
     """Voxels of a block beyond the extent are ignored; blocks outside the
     extent are skipped and reported."""
