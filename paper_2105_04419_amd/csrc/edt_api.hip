@@ -82,7 +82,7 @@ bool layout_of(const edt_config* c, Layout* L) {
     const int64_t sz[O_N] = {
         L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 1024, mb * 4,
         mb * 4, 64 * 4,
-        mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 8,
+        mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4};
     int64_t o = 0;

@@ -690,12 +690,16 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
         const int y = lane & 7, z = lane >> 3;
         const int dmax = g.dmax;
         uint16_t* dst = g.g1 + (int64_t)slot * 512 + 64 * z + y;
+        int mn = dmax;
 #pragma unroll
         for (int x = 7; x >= 0; --x) {
             if ((c >> x) & 1u) q = x;
             const int d = min(min(dl[x], q - x), dmax);
             dst[8 * x] = (uint16_t)(d * d);
+            mn = min(mn, d);
         }
+        mn = wave_min(mn);
+        if (lane == 0) g.bmin1[slot] = (uint16_t)(mn * mn);
         __syncthreads();
     }
 }
@@ -1044,10 +1048,31 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
         resolve_run(g, sl, mem, bx, by, bz, AXIS, runflag, hb, len, ha);
         const int base = M - hb;          // sl index of item block 0
         const int nb = hb + len + ha;
+        // skip masks over window positions j (block hb - M + j of the run,
+        // the window of output block hb): least input of the block, D for
+        // absent blocks and past the run
+        const uint16_t* bmin = AXIS == 1 ? g.bmin1 : g.bmin2;
+        int bm = g.D;
+        {
+            const int b = hb - M + lane;
+            if (b >= 0 && b < nb) {
+                const int32_t s2 = sl[base + b];
+                if (s2 >= 0) bm = bmin[s2];
+            }
+        }
+        WinSkip sk;
+        sk.d = __ballot(bm >= g.D);
+#pragma unroll
+        for (int G = 0; G < M; ++G) {
+            const int kg = G == 0 ? 1 : 8 * G;
+            sk.g[G] = __ballot(bm + kg * kg >= g.D);
+        }
         auto blk = [&](int b) -> uint4 {
-            const uint4* p = (b >= 0 && b < nb)
-                                 ? (const uint4*)src + (int64_t)sl[base + b] * 64 + lane
-                                 : (const uint4*)g.dblock + lane;
+            const int j = b - hb + M;
+            const bool own = b >= 0 && b < nb && !((sk.d >> j) & 1ull);
+            const int32_t s2 = own ? sl[base + b] : -1;
+            const uint4* p = s2 >= 0 ? (const uint4*)src + (int64_t)s2 * 64 + lane
+                                     : (const uint4*)g.dblock + lane;
             return *p;
         };
         auto emit = [&](int ob, const u16x2* acc, bool has1) {
@@ -1055,7 +1080,7 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
             const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
             win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
         };
-        window_min<M>(hb, len, Dp, blk, emit);
+        window_min<M>(hb, len, Dp, blk, emit, [](int) { return true; }, sk);
         __syncthreads();
     }
 }
@@ -1244,7 +1269,11 @@ __global__ void __launch_bounds__(64) k_init_new(Grid g, int first_counter) {
             ((uint32_t*)(g.g2 + s * 512))[k] = d2;
         }
         for (int k = lane; k < 256; k += 64) ((uint32_t*)(g.s + s * 512))[k] = d2;
-        if (lane == 0) g.bmax[s] = g.D;
+        if (lane == 0) {
+            g.bmax[s] = g.D;
+            g.bmin1[s] = (uint16_t)g.D;
+            g.bmin2[s] = (uint16_t)g.D;
+        }
     }
 }
 
@@ -1339,6 +1368,9 @@ __device__ inline int32_t row_box(uint32_t byte, int lane) {
     return xmn | (xmx << 4) | (ymn << 8) | (ymx << 12) | (zmn << 16) | (zmx << 20) | (1 << 24);
 }
 
+// One wave per seed block: the bounding boxes of its added and removed
+// voxels, its coordinates and, for d_max <= 64 (fronts reach at most one
+// tile beyond the seed's), the positions of the 27 tiles around its tile.
 __global__ void __launch_bounds__(64) k_seed_box(Grid g) {
     const int64_t n = g.cnt[C_NSEED];
     const int lane = threadIdx.x;
@@ -1346,11 +1378,18 @@ __global__ void __launch_bounds__(64) k_seed_box(Grid g) {
         const int32_t slot = g.list_seed[s];
         const uint32_t a = ((const uint8_t*)g.chg_add)[(int64_t)slot * 64 + lane];
         const uint32_t r = ((const uint8_t*)g.chg_rem)[(int64_t)slot * 64 + lane];
+        int sx, sy, sz;
+        unpack_key(g.bkey[slot], sx, sy, sz);
         const int32_t ba = row_box(a, lane);
         const int32_t br = row_box(r, lane);
-        if (lane == 0) {
-            g.seed_box[2 * s] = ba;
-            g.seed_box[2 * s + 1] = br;
+        int32_t* rec = g.seed_box + s * 32;
+        if (lane == 0) *(int4*)rec = make_int4(ba, br, sx, sy);
+        if (lane == 1) *(int4*)(rec + 4) = make_int4(sz, 0, 0, 0);
+        if (g.R <= 8 && lane < 27) {
+            const int tx = (sx >> 3) + lane % 3 - 1, ty = (sy >> 3) + (lane / 3) % 3 - 1,
+                      tz = (sz >> 3) + lane / 9 - 1;
+            rec[5 + lane] = (tx < 0 || ty < 0 || tz < 0) ? -1
+                                                         : hpos(g.tkeys, g.tmask, pack_key(tx, ty, tz));
         }
     }
 }
@@ -1376,50 +1415,71 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
 __global__ void k_upd_mark(Grid g) {
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NSEED] * w3;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+    const int lane = __lane_id();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t si = i / w3;
-        const int o = (int)(i % w3);
-        const int32_t seed = g.list_seed[si];
-        int sx, sy, sz;
-        unpack_key(g.bkey[seed], sx, sy, sz);
-        const int ox = o % w - R, oy = (o / w) % w - R, oz = o / (w * w) - R;
-        const int bx = sx + ox, by = sy + oy, bz = sz + oz;
-        int32_t slot = find_block(g, bx, by, bz);
         bool new_dirty = false, new_xs = false, new_ys = false, raise = false, lower = false;
-        if (slot >= 0) {
-            const int32_t pa = g.seed_box[2 * si], pr = g.seed_box[2 * si + 1];
-            const int bm = g.bmax[slot];
-            lower = pa != 0 && box_dist2(pa, sx, sy, sz, bx, by, bz) < bm;
-            if (pr != 0) {
-                const int d2 = box_dist2(pr, sx, sy, sz, bx, by, bz);
-                raise = d2 <= bm && d2 < g.D;
+        int32_t slot = -1;
+        if (i < total) {
+            const int64_t si = i / w3;
+            const int o = (int)(i % w3);
+            const int32_t* rec = g.seed_box + si * 32;
+            const int4 r0 = *(const int4*)rec;
+            const int32_t pa = r0.x, pr = r0.y, sx = r0.z, sy = r0.w, sz = rec[4];
+            const int ox = o % w - R, oy = (o / w) % w - R, oz = o / (w * w) - R;
+            const int bx = sx + ox, by = sy + oy, bz = sz + oz;
+            if (R <= 8) {
+                // the block's tile among the 27 recorded around the seed's tile
+                if (bx >= 0 && by >= 0 && bz >= 0) {
+                    const int k = ((bx >> 3) - (sx >> 3) + 1) + 3 * ((by >> 3) - (sy >> 3) + 1) +
+                                  9 * ((bz >> 3) - (sz >> 3) + 1);
+                    const int32_t t = rec[5 + k];
+                    if (t >= 0) slot = g.tslots[(int64_t)t * 512 + block_local(bx, by, bz)];
+                }
+            } else {
+                slot = find_block(g, bx, by, bz);
             }
-            uint32_t want = 0;
-            if (lower) want |= F_LOWER | F_DIRTY;
-            if (raise) want |= F_RAISE | F_DIRTY;
-            if (oz == 0) want |= F_YS;
-            if (oz == 0 && oy == 0) want |= F_XS;
-            if (want) {
-                const uint32_t old = atomicOr(&g.flags[slot], want);
-                new_dirty = (want & F_DIRTY) && !(old & F_DIRTY);
-                new_ys = (want & F_YS) && !(old & F_YS);
-                new_xs = (want & F_XS) && !(old & F_XS);
-                raise = raise && !(old & F_RAISE);
-                lower = lower && !(old & F_LOWER);
+            if (slot >= 0) {
+                const int bm = g.bmax[slot];
+                lower = pa != 0 && box_dist2(pa, sx, sy, sz, bx, by, bz) < bm;
+                if (pr != 0) {
+                    const int d2 = box_dist2(pr, sx, sy, sz, bx, by, bz);
+                    raise = d2 <= bm && d2 < g.D;
+                }
+                uint32_t want = 0;
+                if (lower) want |= F_LOWER | F_DIRTY;
+                if (raise) want |= F_RAISE | F_DIRTY;
+                if (oz == 0) want |= F_YS;
+                if (oz == 0 && oy == 0) want |= F_XS;
+                if (want) {
+                    const uint32_t old = atomicOr(&g.flags[slot], want);
+                    new_dirty = (want & F_DIRTY) && !(old & F_DIRTY);
+                    new_ys = (want & F_YS) && !(old & F_YS);
+                    new_xs = (want & F_XS) && !(old & F_XS);
+                    raise = raise && !(old & F_RAISE);
+                    lower = lower && !(old & F_LOWER);
+                }
             }
         }
-        int j = wave_append(new_dirty, &g.cnt[C_NDIRTY]);
-        if (new_dirty) g.list_dirty[j] = slot;
-        j = wave_append(new_ys, &g.cnt[C_NYS]);
-        if (new_ys) g.list_ys[j] = slot;
-        j = wave_append(new_xs, &g.cnt[C_NXS]);
-        if (new_xs) g.list_xs[j] = slot;
-        const unsigned long long mr = __ballot(raise), ml = __ballot(lower);
-        if (__lane_id() == (int)(__ffsll((long long)(mr | ml | 1ull)) - 1) && (mr | ml)) {
-            atomicAdd(&g.cnt[C_NRAISE], __popcll(mr));
-            atomicAdd(&g.cnt[C_NLOWER], __popcll(ml));
+        // the wave's list appends and statistics: the counter atomics are
+        // issued together by one lane
+        const unsigned long long md = __ballot(new_dirty), my = __ballot(new_ys),
+                                 mx = __ballot(new_xs), mr = __ballot(raise), ml = __ballot(lower);
+        int bd = 0, by_ = 0, bx_ = 0;
+        if (lane == 0) {
+            if (md) bd = atomicAdd(&g.cnt[C_NDIRTY], __popcll(md));
+            if (my) by_ = atomicAdd(&g.cnt[C_NYS], __popcll(my));
+            if (mx) bx_ = atomicAdd(&g.cnt[C_NXS], __popcll(mx));
+            if (mr) atomicAdd(&g.cnt[C_NRAISE], __popcll(mr));
+            if (ml) atomicAdd(&g.cnt[C_NLOWER], __popcll(ml));
         }
+        bd = __shfl(bd, 0);
+        by_ = __shfl(by_, 0);
+        bx_ = __shfl(bx_, 0);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (new_dirty) g.list_dirty[bd + __popcll(md & below)] = slot;
+        if (new_ys) g.list_ys[by_ + __popcll(my & below)] = slot;
+        if (new_xs) g.list_xs[bx_ + __popcll(mx & below)] = slot;
     }
 }
 
