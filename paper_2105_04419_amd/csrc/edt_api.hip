@@ -141,9 +141,8 @@ void launch_win(const Grid& g, int grid, hipStream_t st, const int32_t* items, i
     }
 }
 
-void launch_pass(edt_ctx* c, int axis, hipStream_t st, const int32_t* items, int counter,
-                 uint32_t runflag) {
-    const Grid& g = c->g;
+void launch_pass(edt_ctx* c, const Grid& g, int axis, hipStream_t st, const int32_t* items,
+                 int counter, uint32_t runflag) {
     const int grid = grid_for(g.max_blocks, 1, 8192);
     if (g.R <= 8) {
         if (axis == 1) launch_win<1>(g, grid, st, items, counter, runflag);
@@ -192,9 +191,9 @@ edt_status run_passes_global(edt_ctx* c, hipStream_t st) {
         hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 16384)), dim3(64), 0, st, g,
                            (const int32_t*)nullptr, 0);
         mark(c, 4, st);
-        launch_pass(c, 1, st, g.list_yi, (int)C_NYI, 0u);
+        launch_pass(c, g, 1, st, g.list_yi, (int)C_NYI, 0u);
         mark(c, 5, st);
-        launch_pass(c, 2, st, g.list_zi, (int)C_NZI, 0u);
+        launch_pass(c, g, 2, st, g.list_zi, (int)C_NZI, 0u);
         mark(c, 6, st);
     }
     if (c->ev && c->ev_used < c->ev_calls) c->ev_used++;
@@ -255,6 +254,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.D = cfg->d_max * cfg->d_max;
     g.R = (cfg->d_max + 7) / 8;
     g.max_blocks = (int)L.max_blocks;
+    g.lrun = LRUN;
     g.tmask = (uint32_t)(L.tcap - 1);
     g.umask = (uint32_t)(L.ucap - 1);
     g.max_changes = (int)L.max_changes;
@@ -432,22 +432,20 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
     hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n);
     hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
-    hipLaunchKernelGGL(k_init_new, dim3(2048), dim3(64), 0, st, g, (int)C_SNAP);
     hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
-    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, g, (int)C_SNAP2);
     hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
-    hipLaunchKernelGGL(k_init_new, dim3(2048), dim3(64), 0, st, g, (int)C_SNAP2);
     hipLaunchKernelGGL(k_seed_box, dim3(grid_for(n, 1, 4096)), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_upd_mark, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
+    // short work items: the recompute sets are small, and short runs give
+    // more waves to hide each item's latency
+    Grid gu = g;
+    gu.lrun = 4;
+    hipLaunchKernelGGL(k_items_update, dim3(grid_for(2 * (int64_t)mb + 64, 256, 4096)), dim3(256), 0,
+                       st, gu);
     hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 8192)), dim3(64), 0, st, g,
                        (const int32_t*)g.list_xs, (int)C_NXS);
-    const int tg = grid_for(mb, 256, 4096);
-    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_ys,
-                       (int)C_NYS, (uint32_t)F_YS, 1);
-    launch_pass(c, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
-    hipLaunchKernelGGL(k_items, dim3(tg), dim3(256), 0, st, g, (const int32_t*)g.list_dirty,
-                       (int)C_NDIRTY, (uint32_t)F_DIRTY, 2);
-    launch_pass(c, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
+    launch_pass(c, gu, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
+    launch_pass(c, gu, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
     hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,
                        g, n);
     LAUNCH_CHECK();

@@ -31,7 +31,7 @@
 namespace edt {
 
 constexpr unsigned long long KEY_EMPTY = ~0ull;
-constexpr int LRUN = 16;        // max output blocks per y / z work item
+constexpr int LRUN = 16;        // longest y / z work item (blocks); Grid::lrun <= LRUN
 constexpr int32_t FINF = 1 << 28;
 
 enum : uint32_t {
@@ -46,7 +46,7 @@ enum : uint32_t {
 
 // device counters (int32 slots of the counter array)
 enum {
-    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_SNAP, C_SNAP2,
+    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_RESERVED4, C_RESERVED5,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
     C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_N
 };
@@ -56,6 +56,7 @@ struct Grid {
     int nbx, nby, nbz;       // extent (blocks)
     int dmax, D, R;          // radius, D = dmax^2, R = ceil(dmax / 8)
     int max_blocks;
+    int lrun;                // output blocks per y / z work item of the list-driven passes
     uint32_t tmask;          // tile hash capacity - 1
     uint32_t umask;          // update-dedupe hash capacity - 1
     int max_changes;

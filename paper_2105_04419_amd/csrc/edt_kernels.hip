@@ -103,7 +103,6 @@ __device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bo
     grow_tiles(g, first, bx >> 3, by >> 3, bz >> 3);
 }
 
-__global__ void k_snapshot(Grid g, int dst) { g.cnt[dst] = g.cnt[C_NBLK]; }
 
 __device__ inline int32_t load_count(const Grid& g, int idx) {
     return __hip_atomic_load(&g.cnt[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -447,9 +446,34 @@ __device__ inline bool run_member(const Grid& g, int32_t slot, uint32_t runflag)
 __device__ inline bool run_start(const Grid& g, int bx, int by, int bz, int axis,
                                  uint32_t runflag) {
     const int c = axis == 1 ? by : bz;
-    if (c % LRUN == 0) return true;
+    if (c % g.lrun == 0) return true;
     return !run_member(g, axis == 1 ? find_block(g, bx, by - 1, bz) : find_block(g, bx, by, bz - 1),
                        runflag);
+}
+
+// y items from the ys list and z items from the dirty list in one launch
+// (incremental transform).
+__global__ void k_items_update(Grid g) {
+    const int64_t ny = min((int64_t)g.cnt[C_NYS], (int64_t)g.max_blocks);
+    const int64_t nd = min((int64_t)g.cnt[C_NDIRTY], (int64_t)g.max_blocks);
+    // a wave takes entries of one list only (the y part is padded to 64)
+    const int64_t nyp = (ny + 63) & ~(int64_t)63;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - __lane_id() < nyp + nd;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const bool zpart = i - __lane_id() >= nyp;
+        const int64_t k = zpart ? i - nyp : i;
+        const bool ok = zpart ? k < nd : k < ny;
+        bool st = false;
+        int32_t slot = -1;
+        if (ok) {
+            slot = zpart ? g.list_dirty[k] : g.list_ys[k];
+            int bx, by, bz;
+            unpack_key(g.bkey[slot], bx, by, bz);
+            st = run_start(g, bx, by, bz, zpart ? 2 : 1, zpart ? F_DIRTY : F_YS);
+        }
+        const int idx = wave_append(st, &g.cnt[zpart ? C_NZI : C_NYI]);
+        if (st) (zpart ? g.list_zi : g.list_yi)[idx] = slot;
+    }
 }
 
 __global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t runflag,
@@ -528,8 +552,8 @@ __global__ void __launch_bounds__(64) k_items_tiles(Grid g) {
             const bool ex = slot >= 0;
             const int32_t py = y > 0 ? own[i - 8] : below[x + 8 * z];
             const int32_t pz = z > 0 ? own[i - 64] : behind[x + 8 * y];
-            const bool sy = ex && ((by % LRUN) == 0 || py < 0);
-            const bool sz = ex && ((bz % LRUN) == 0 || pz < 0);
+            const bool sy = ex && ((by % g.lrun) == 0 || py < 0);
+            const bool sz = ex && ((bz % g.lrun) == 0 || pz < 0);
             const int jy = wave_append(sy, &g.cnt[C_NYI]);
             if (sy) g.list_yi[jy] = slot;
             const int jz = wave_append(sz, &g.cnt[C_NZI]);
@@ -799,7 +823,7 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
                                    int bz, int axis, uint32_t runflag, int& hb, int& len,
                                    int& ha) {
     const int R = g.R;
-    const int nl = LRUN + 2 * R;
+    const int nl = g.lrun + 2 * R;
     const int lane = threadIdx.x;
     for (int i = lane; i < nl; i += 64) {
         const int o = i - R;
@@ -812,7 +836,7 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
     hb = 0;
     while (hb < R && sl[R - 1 - hb] >= 0) ++hb;
     len = 1;
-    while (len < LRUN && ((start + len) % LRUN) != 0 && mem[R + len]) ++len;
+    while (len < g.lrun && ((start + len) % g.lrun) != 0 && mem[R + len]) ++len;
     ha = 0;
     while (ha < R && sl[R + len + ha] >= 0) ++ha;
 }
@@ -1194,7 +1218,6 @@ __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int3
 // ---------------------------------------------------------------------------
 __global__ void k_upd_begin(Grid g) {
     const int i = threadIdx.x;
-    if (i == 0) g.cnt[C_SNAP] = g.cnt[C_NBLK];
     if (i == C_ABORT || (i >= C_NYI && i < C_N)) g.cnt[i] = 0;
 }
 
@@ -1229,16 +1252,46 @@ __device__ inline bool upd_winner(const Grid& g, int64_t i) {
     return h >= 0 && g.uvals[h] == (int32_t)i;
 }
 
-// New blocks for voxels that become occupied.
+// Fresh pool slots claimed by lanes of this wave: an empty block with
+// background values.  Called by the whole wave (each slot's 1 KiB arrays are
+// written as one 16-byte store per lane).
+__device__ inline void init_slots(const Grid& g, int32_t slot) {
+    unsigned long long m = __ballot(slot >= 0);
+    const int lane = __lane_id();
+    const uint32_t d2 = (uint32_t)g.D | ((uint32_t)g.D << 16);
+    const uint4 dd = make_uint4(d2, d2, d2, d2);
+    while (m) {
+        const int src = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int64_t s = __shfl(slot, src);
+        if (lane < 16) {
+            g.occ[s * 16 + lane] = 0u;
+            g.chg_add[s * 16 + lane] = 0u;
+            g.chg_rem[s * 16 + lane] = 0u;
+        }
+        ((uint4*)(g.g1 + s * 512))[lane] = dd;
+        ((uint4*)(g.g2 + s * 512))[lane] = dd;
+        ((uint4*)(g.s + s * 512))[lane] = dd;
+        if (lane == 0) {
+            g.bmax[s] = g.D;
+            g.bmin1[s] = (uint16_t)g.D;
+            g.bmin2[s] = (uint16_t)g.D;
+        }
+    }
+}
+
+// New blocks for voxels that become occupied (initialised to background by
+// the claiming wave).
 __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
                             const uint8_t* __restrict__ state, int64_t n) {
     if (g.cnt[C_ABORT]) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    const int lane = __lane_id();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         bool created = false;
         int64_t e = -1;
         unsigned long long key = 0;
-        if (state[i] && upd_winner(g, i)) {
+        if (i < n && state[i] && upd_winner(g, i)) {
             const int bx = xyz[3 * i] >> 3, by = xyz[3 * i + 1] >> 3, bz = xyz[3 * i + 2] >> 3;
             key = pack_key(bx, by, bz);
             e = insert_block(g, bx, by, bz, &created);
@@ -1247,33 +1300,7 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
                 g.cnt[C_ABORT] = 1;
             }
         }
-        claim_slots(g, created, e, key, 0u);
-    }
-}
-
-// Fresh slots [cnt[first], NBLK): empty block with background values.
-__global__ void __launch_bounds__(64) k_init_new(Grid g, int first_counter) {
-    const int64_t first = g.cnt[first_counter];
-    const int64_t n0 = g.cnt[C_NBLK];
-    const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
-    const int lane = threadIdx.x;
-    for (int64_t s = first + blockIdx.x; s < n; s += gridDim.x) {
-        if (lane < 16) {
-            g.occ[s * 16 + lane] = 0u;
-            g.chg_add[s * 16 + lane] = 0u;
-            g.chg_rem[s * 16 + lane] = 0u;
-        }
-        const uint32_t d2 = (uint32_t)g.D | ((uint32_t)g.D << 16);
-        for (int k = lane; k < 256; k += 64) {
-            ((uint32_t*)(g.g1 + s * 512))[k] = d2;
-            ((uint32_t*)(g.g2 + s * 512))[k] = d2;
-        }
-        for (int k = lane; k < 256; k += 64) ((uint32_t*)(g.s + s * 512))[k] = d2;
-        if (lane == 0) {
-            g.bmax[s] = g.D;
-            g.bmin1[s] = (uint16_t)g.D;
-            g.bmin2[s] = (uint16_t)g.D;
-        }
+        init_slots(g, claim_slots(g, created, e, key, 0u));
     }
 }
 
@@ -1332,23 +1359,27 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
 __global__ void k_upd_dilate(Grid g) {
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NNEWDIL] * w3;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+    const int lane = __lane_id();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t slot = g.list_newdil[i / w3];
-        const int o = (int)(i % w3);
-        int bx, by, bz;
-        unpack_key(g.bkey[slot], bx, by, bz);
-        bx += o % w - R;
-        by += (o / w) % w - R;
-        bz += o / (w * w) - R;
         bool created = false;
         int64_t e = -1;
-        const unsigned long long key = pack_key(bx, by, bz);
-        if (bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz) {
-            e = insert_block(g, bx, by, bz, &created);
-            if (e < 0) set_error(g, -3);
+        unsigned long long key = 0;
+        if (i < total) {
+            const int32_t slot = g.list_newdil[i / w3];
+            const int o = (int)(i % w3);
+            int bx, by, bz;
+            unpack_key(g.bkey[slot], bx, by, bz);
+            bx += o % w - R;
+            by += (o / w) % w - R;
+            bz += o / (w * w) - R;
+            key = pack_key(bx, by, bz);
+            if (bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz) {
+                e = insert_block(g, bx, by, bz, &created);
+                if (e < 0) set_error(g, -3);
+            }
         }
-        claim_slots(g, created, e, key, 0u);
+        init_slots(g, claim_slots(g, created, e, key, 0u));
     }
 }
 
