@@ -439,7 +439,7 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
     // short work items: the recompute sets are small, and short runs give
     // more waves to hide each item's latency
     Grid gu = g;
-    gu.lrun = 4;
+    gu.lrun = 2;
     hipLaunchKernelGGL(k_items_update, dim3(grid_for(2 * (int64_t)mb + 64, 256, 4096)), dim3(256), 0,
                        st, gu);
     hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 8192)), dim3(64), 0, st, g,
