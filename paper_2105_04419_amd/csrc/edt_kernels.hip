@@ -1385,17 +1385,24 @@ __global__ void k_upd_dilate(Grid g) {
 
 // Bounding boxes (block-local) of the added and removed voxels of each seed.
 // Packed as xmin | xmax<<4 | ymin<<8 | ymax<<12 | zmin<<16 | zmax<<20 | 1<<24.
-__device__ inline int32_t row_box(uint32_t byte, int lane) {
-    int xmn = 8, xmx = -1, ymn = 8, ymx = -1, zmn = 8, zmx = -1;
-    if (byte) {
-        xmn = __ffs(byte) - 1;
-        xmx = 31 - __clz(byte);
-        ymn = ymx = lane & 7;
-        zmn = zmx = lane >> 3;
-    }
-    xmn = wave_min(xmn); ymn = wave_min(ymn); zmn = wave_min(zmn);
-    xmx = wave_max(xmx); ymx = wave_max(ymx); zmx = wave_max(zmx);
-    if (xmx < 0) return 0;
+// byte = the wave's row (y, z) = lane of the voxel set; x from one ballot per
+// bit, y and z from the ballot of nonempty rows (bit y + 8z).
+__device__ inline int32_t row_box(uint32_t byte) {
+    const unsigned long long rows = __ballot(byte != 0u);
+    if (rows == 0ull) return 0;
+    uint32_t xo = 0u;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) xo |= (__ballot((byte >> x) & 1u) != 0ull ? 1u : 0u) << x;
+    unsigned long long f = rows | (rows >> 32);
+    f |= f >> 16;
+    f |= f >> 8;
+    const uint32_t yo = (uint32_t)f & 0xffu;
+    uint32_t zo = 0u;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) zo |= (((rows >> (8 * z)) & 0xffull) != 0ull ? 1u : 0u) << z;
+    const int xmn = __ffs(xo) - 1, xmx = 31 - __clz(xo);
+    const int ymn = __ffs(yo) - 1, ymx = 31 - __clz(yo);
+    const int zmn = __ffs(zo) - 1, zmx = 31 - __clz(zo);
     return xmn | (xmx << 4) | (ymn << 8) | (ymx << 12) | (zmn << 16) | (zmx << 20) | (1 << 24);
 }
 
@@ -1411,8 +1418,8 @@ __global__ void __launch_bounds__(64) k_seed_box(Grid g) {
         const uint32_t r = ((const uint8_t*)g.chg_rem)[(int64_t)slot * 64 + lane];
         int sx, sy, sz;
         unpack_key(g.bkey[slot], sx, sy, sz);
-        const int32_t ba = row_box(a, lane);
-        const int32_t br = row_box(r, lane);
+        const int32_t ba = row_box(a);
+        const int32_t br = row_box(r);
         int32_t* rec = g.seed_box + s * 32;
         if (lane == 0) *(int4*)rec = make_int4(ba, br, sx, sy);
         if (lane == 1) *(int4*)(rec + 4) = make_int4(sz, 0, 0, 0);
