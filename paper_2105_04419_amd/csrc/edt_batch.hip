@@ -40,6 +40,8 @@ struct BArgs {
     const MapDev* maps;
     const int32_t* pref;     // [3][n_maps + 1] item prefix sums (phase-major)
     int32_t* queues;         // [3][n_maps + 1] grab counters
+    const int32_t* itemmap;  // [3][icap] map of each work item
+    int64_t icap;
     const uint8_t* occ;
     int32_t* out;
     uint16_t* g1;
@@ -51,16 +53,6 @@ struct BArgs {
     int lrun, chunk, schedule;
 };
 
-// map whose item range holds global item index i (binary search)
-__device__ inline int map_of(const int32_t* pref, int n_maps, int i) {
-    int lo = 0, hi = n_maps;   // pref[lo] <= i < pref[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pref[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
 
 __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int bx, int by, int bz,
                                        const uint16_t* dblock, int lane) {
@@ -70,56 +62,126 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
     return (const uint4*)arr + b * 64 + lane;
 }
 
-// phase 0: squared distance along x, from the occupancy bytes of one row
-// window per lane (lane = y + 8z), for a strip of 8 blocks.  The row window
-// (blocks bx0-M .. bx0+7+M) becomes a bit string; the nearest obstacle on
-// each side of a voxel is found with count-leading/trailing-zeros on the
-// 64-bit words around it (d_max <= 64, so two words per side suffice).
+// phase 0: squared distance along x for a strip of 8 blocks.  The wave walks
+// the strip's 64 rows (y, z); for each row the lanes read the window
+// x = 8 (bx0 - M) .. 8 (bx0 + 8 + M) - 1 with coalesced byte loads (64 + 16M
+// bytes, up to three per lane) and ballots make it a bit string, which goes
+// through LDS to lane r.  Then every lane holds its own row and
+// sweeps it with a carried distance (left to right, then right to left
+// inside each block), 7 integer ops per voxel; M = ceil(d_max / 8) blocks of
+// context cover d_max.  Results gather in LDS in the g1 block layout
+// (y + 8x + 64z) and leave as 16-byte stores.
 template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
-    constexpr int NBITS = 64 + 16 * M;
-    constexpr int NW64 = (NBITS + 63) / 64;
+    constexpr int LS = 514;                      // u16 per block in LDS (padded)
+    constexpr int NBYTES = 64 + 16 * M;          // window bytes per row
+    constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
+    constexpr int RB = 16;                       // rows whose loads are in flight together
+    constexpr int NB = 8 + 2 * M;                // window blocks
+    __shared__ uint16_t xbuf[4][8 * LS];
+    uint16_t* buf = xbuf[(threadIdx.x >> 6) & 3];
+    // the rows' window words (row r, word w at rowbits[NWIN r + w]) share the
+    // buffer: they are read back before any result is written
+    unsigned long long* rowbits = (unsigned long long*)buf;
     const int lane = threadIdx.x & 63;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int bx0 = 8 * (li % m.nxr);
     const int rest = li / m.nxr;
     const int by = rest % m.nby, bz = rest / m.nby;
-    const int Y = 8 * by + (lane & 7), Z = 8 * bz + (lane >> 3);
-    const bool row_ok = Y < m.ny && Z < m.nz;
     const int xs = 8 * (bx0 - M);
-    const uint8_t* row = a.occ + m.occ_off + ((int64_t)Z * m.ny + Y) * m.nx;
-    unsigned long long w[NW64 + 1];
+    // loads always hit a voxel of the map (clamped); bytes outside it are
+    // dropped afterwards
+    uint32_t xo[NWIN];
+    bool vx[NWIN];
 #pragma unroll
-    for (int k = 0; k <= NW64; ++k) w[k] = 0ull;
-#pragma unroll
-    for (int k = 0; k < NBITS; ++k) {
-        const int x = xs + k;
-        if (row_ok && x >= 0 && x < m.nx && row[x]) w[k >> 6] |= 1ull << (k & 63);
+    for (int w = 0; w < NWIN; ++w) {
+        const int x = xs + 64 * w + lane;
+        vx[w] = 64 * w + lane < NBYTES && x >= 0 && x < nx;
+        xo[w] = (uint32_t)min(max(x, 0), nx - 1);
     }
-    const int dmax = a.dmax;
+    const uint8_t* base = a.occ + m.occ_off;
+    const int64_t zst = (int64_t)ny * nx;
+#pragma unroll
+    for (int r0 = 0; r0 < 64; r0 += RB) {
+        uint32_t bt[RB][NWIN];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int r = r0 + k;
+            const int Y = min(8 * by + (r & 7), ny - 1), Z = min(8 * bz + (r >> 3), nz - 1);
+            const uint8_t* row = base + Z * zst + (int64_t)Y * nx;
+#pragma unroll
+            for (int w = 0; w < NWIN; ++w) bt[k][w] = row[xo[w]];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int r = r0 + k;
+            const bool rok = 8 * by + (r & 7) < ny && 8 * bz + (r >> 3) < nz;
+#pragma unroll
+            for (int w = 0; w < NWIN; ++w) {
+                // every lane stores the same word (no per-lane branch)
+                rowbits[NWIN * r + w] = __ballot(rok && vx[w] && bt[k][w] != 0u);
+            }
+        }
+    }
+    // window words of row `lane` (lo and hi halves)
+    uint32_t rlo[NWIN], rhi[NWIN];
+#pragma unroll
+    for (int w = 0; w < NWIN; ++w) {
+        const unsigned long long W = rowbits[NWIN * lane + w];
+        rlo[w] = (uint32_t)W;
+        rhi[w] = (uint32_t)(W >> 32);
+    }
+    // bytes of the row: block k of the window (k = 0 .. NB - 1)
+    uint32_t b[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int w = k >> 3, h = (k >> 2) & 1, sh = 8 * (k & 3);
+        b[k] = ((h ? rhi[w] : rlo[w]) >> sh) & 0xffu;
+    }
+    constexpr uint32_t FAR = 1u << 20;
+    const uint32_t dmax = (uint32_t)a.dmax;
+    // distance from the last voxel before the strip back to the nearest obstacle
+    uint32_t L = FAR;
+#pragma unroll
+    for (int k = 0; k < M; ++k) L = b[k] ? (uint32_t)__clz(b[k]) - 24u : L + 8u;
+    // rc[j]: distance from the first voxel after strip block j to the nearest
+    // obstacle at or after it
+    uint32_t rc[8];
+    uint32_t R = FAR;
+#pragma unroll
+    for (int k = NB - 1; k >= M + 8; --k) R = b[k] ? (uint32_t)(__ffs(b[k]) - 1) : R + 8u;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        rc[j] = R;
+        const uint32_t bj = b[M + j];
+        R = bj ? (uint32_t)(__ffs(bj) - 1) : R + 8u;
+    }
+    const int rofs = (lane & 7) + 64 * (lane >> 3);      // this row in the g1 block layout
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t bj = b[M + j];
+        uint32_t mk[8], d[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) mk[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) { L = (L + 1u) & ~mk[x]; d[x] = L; }
+        uint32_t rr = rc[j];
+#pragma unroll
+        for (int x = 7; x >= 0; --x) {
+            rr = (rr + 1u) & ~mk[x];
+            const uint32_t v = min(min(d[x], rr), dmax);
+            buf[j * LS + rofs + 8 * x] = (uint16_t)(v * v);
+        }
+    }
+    // block j: lane writes g1 elements 8 lane .. 8 lane + 7 (16 bytes)
     const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int bx = bx0 + j;
-        uint16_t* dst = bx < m.nbx ? a.g1 + (brow + bx) * 512 + 64 * (lane >> 3) + (lane & 7)
-                                   : (uint16_t*)a.dummy + lane;
-        const int dstep = bx < m.nbx ? 8 : 0;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const int k = 8 * M + 8 * j + x;            // bit of this voxel
-            const int q = k >> 6, r = k & 63;
-            // left: highest set bit <= k
-            const unsigned long long l0 = w[q] & (r == 63 ? ~0ull : ((1ull << (r + 1)) - 1ull));
-            int dl = 1000;
-            if (l0) dl = r - (63 - __clzll(l0));
-            else if (q >= 1 && w[q - 1]) dl = r + 1 + __clzll(w[q - 1]);
-            // right: lowest set bit >= k
-            const unsigned long long r0 = w[q] >> r;
-            int dr = 1000;
-            if (r0) dr = __ffsll(r0) - 1;
-            else if (q + 1 <= NW64 && w[q + 1]) dr = (64 - r) + __ffsll(w[q + 1]) - 1;
-            const int d = min(min(dl, dr), dmax);
-            dst[dstep * x] = (uint16_t)(d * d);
-        }
+        if (bx >= m.nbx) break;
+        const uint32_t* src = (const uint32_t*)(buf + j * LS) + 4 * lane;
+        const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
+        *(uint4*)(a.g1 + (brow + bx) * 512 + 8 * lane) = v;
     }
 }
 
@@ -184,7 +246,7 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
 template <int M>
 __device__ inline void run_item(const BArgs& a, int phase, int gi, uint32_t Dp) {
     const int* pref = a.pref + phase * (a.n_maps + 1);
-    const int mi = map_of(pref, a.n_maps, gi);
+    const int mi = a.itemmap[phase * a.icap + gi];
     const MapDev m = a.maps[mi];
     const int li = gi - pref[mi];
     if (phase == 0) item_x<M>(a, m, li);
@@ -251,6 +313,16 @@ __global__ void k_batch_prefix(const MapDev* maps, int n, int lrun, int32_t* pre
     for (int i = threadIdx.x; i < 3 * (n + 1); i += blockDim.x) queues[i] = 0;
 }
 
+// The map of every work item of every phase (one workgroup per map), so an
+// item finds its map with one load.
+__global__ void k_batch_itemmap(const int32_t* pref, int n, int32_t* itemmap, int64_t icap) {
+    const int i = blockIdx.x;
+    for (int p = 0; p < 3; ++p) {
+        const int lo = pref[p * (n + 1) + i], hi = pref[p * (n + 1) + i + 1];
+        for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) itemmap[p * icap + k] = i;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -260,7 +332,8 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 struct BLayout {
-    int64_t off_maps, off_pref, off_queues, off_g1, off_g2, off_dblock, off_dummy, total;
+    int64_t off_maps, off_pref, off_queues, off_itemmap, off_g1, off_g2, off_dblock, off_dummy,
+        total;
     int64_t nblocks;
 };
 
@@ -279,6 +352,7 @@ bool blayout(const edt_batch_map* maps, int n, int dmax, BLayout* L) {
     L->off_maps = o; o += align256((int64_t)n * sizeof(MapDev));
     L->off_pref = o; o += align256((int64_t)3 * (n + 1) * 4);
     L->off_queues = o; o += align256((int64_t)3 * (n + 1) * 4);
+    L->off_itemmap = o; o += align256(3 * nb * 4);   // items per phase <= blocks
     L->off_g1 = o; o += align256(nb * 1024);
     L->off_g2 = o; o += align256(nb * 1024);
     L->off_dblock = o; o += 1024;
@@ -458,8 +532,12 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
     a.lrun = t.lrun;
     a.chunk = t.chunk;
     a.schedule = t.schedule;
+    a.itemmap = (const int32_t*)(b->ws + L.off_itemmap);
+    a.icap = L.nblocks;
     hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(256), 0, st, a.maps, b->n, t.lrun,
                        (int32_t*)a.pref, a.queues);
+    hipLaunchKernelGGL(k_batch_itemmap, dim3(b->n), dim3(256), 0, st, a.pref, b->n,
+                       (int32_t*)a.itemmap, a.icap);
     if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
     switch (b->M) {
         case 1: return launch_batch<1>(b, a, mode, t.waves_per_cu, st);
