@@ -214,21 +214,33 @@ __device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     window_min<M>(by0, len, Dp, blk, emit);
 }
 
-// phase 2: windowed minimum along z (lane = x + 8y), g2 -> dense int32 field
+// phase 2: windowed minimum along z, g2 -> dense int32 field.  An item is a
+// strip of 64 voxels along x (8 blocks) at one y and a run of lrun blocks
+// along z; lane l owns the column x = 8 bx0 + l, so every output store is 256
+// contiguous bytes of the x-fastest field.
 template <int M>
 __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     const int lane = threadIdx.x & 63;
-    const int bx = li % m.nbx;
-    const int rest = li / m.nbx;
-    const int by = rest % m.nby, seg = rest / m.nby;
+    const int bx0 = 8 * (li % m.nxr);
+    const int rest = li / m.nxr;
+    const int Y = rest % m.ny, seg = rest / m.ny;
     const int bz0 = seg * a.lrun;
     const int len = min(a.lrun, m.nbz - bz0);
-    const int X = 8 * bx + (lane & 7), Y = 8 * by + (lane >> 3);
-    const bool col_ok = X < m.nx && Y < m.ny;
+    const int bx = bx0 + (lane >> 3), by = Y >> 3;
+    const int X = 8 * bx0 + lane;
+    const bool col_ok = X < m.nx;
+    const int rofs = (lane & 7) + 8 * (Y & 7);        // z-row (x' + 8y') of a g2 block
+    const int64_t bcol = m.blk_off + (int64_t)by * m.nbx + bx;
+    const int64_t bzst = (int64_t)m.nby * m.nbx;
+    auto blk = [&](int b) -> uint4 {
+        const bool ok = bx < m.nbx && b >= 0 && b < m.nbz;
+        const uint4* p = ok ? (const uint4*)a.g2 + (bcol + b * bzst) * 64 + rofs
+                            : (const uint4*)a.dblock + lane;
+        return *p;
+    };
     int32_t* dummy = (int32_t*)(a.dummy + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 255) * 64);
     int32_t* col = a.out + m.out_off + (int64_t)Y * m.nx + X;
     const int64_t zstride = (int64_t)m.nx * m.ny;
-    auto blk = [&](int b) -> uint4 { return *blk_ptr(a.g2, m, bx, by, b, a.dblock, lane); };
     auto emit = [&](int ob, const u16x2* acc, bool has1) {
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
@@ -307,7 +319,7 @@ __global__ void k_batch_prefix(const MapDev* maps, int n, int lrun, int32_t* pre
             const MapDev m = maps[i];
             acc[0] += m.nxr * m.nby * m.nbz;
             acc[1] += m.nbx * m.nbz * ((m.nby + lrun - 1) / lrun);
-            acc[2] += m.nbx * m.nby * ((m.nbz + lrun - 1) / lrun);
+            acc[2] += m.nxr * m.ny * ((m.nbz + lrun - 1) / lrun);
         }
     }
     for (int i = threadIdx.x; i < 3 * (n + 1); i += blockDim.x) queues[i] = 0;
@@ -335,24 +347,33 @@ struct BLayout {
     int64_t off_maps, off_pref, off_queues, off_itemmap, off_g1, off_g2, off_dblock, off_dummy,
         total;
     int64_t nblocks;
+    int64_t icap;            // item-map entries per phase
 };
 
 bool blayout(const edt_batch_map* maps, int n, int dmax, BLayout* L) {
     if (!maps || n < 1 || n > (1 << 16) || dmax < 1 || dmax > 64) return false;
-    int64_t nb = 0;
+    int64_t nb = 0, ic0 = 0, ic1 = 0, ic2 = 0;
     for (int i = 0; i < n; ++i) {
         const edt_batch_map& m = maps[i];
         if (m.nx < 1 || m.ny < 1 || m.nz < 1 || m.nx > 4096 || m.ny > 4096 || m.nz > 4096)
             return false;
         if (m.occ_offset < 0 || m.out_offset < 0) return false;
         nb += (int64_t)((m.nx + 7) / 8) * ((m.ny + 7) / 8) * ((m.nz + 7) / 8);
+        // most items per phase (run length 1): x strips, y runs, z strips
+        const int64_t nbx = (m.nx + 7) / 8, nby = (m.ny + 7) / 8, nbz = (m.nz + 7) / 8;
+        const int64_t nxr = (nbx + 7) / 8;
+        ic0 += nxr * nby * nbz;
+        ic1 += nbx * nby * nbz;
+        ic2 += nxr * m.ny * nbz;
     }
+    const int64_t icap = ic0 > ic1 ? (ic0 > ic2 ? ic0 : ic2) : (ic1 > ic2 ? ic1 : ic2);
     if (nb > (1ll << 26)) return false;
     int64_t o = 0;
     L->off_maps = o; o += align256((int64_t)n * sizeof(MapDev));
     L->off_pref = o; o += align256((int64_t)3 * (n + 1) * 4);
     L->off_queues = o; o += align256((int64_t)3 * (n + 1) * 4);
-    L->off_itemmap = o; o += align256(3 * nb * 4);   // items per phase <= blocks
+    L->off_itemmap = o; o += align256(3 * icap * 4);
+    L->icap = icap;
     L->off_g1 = o; o += align256(nb * 1024);
     L->off_g2 = o; o += align256(nb * 1024);
     L->off_dblock = o; o += 1024;
@@ -406,7 +427,7 @@ edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu
         const int64_t items[3] = {
             (int64_t)m.nxr * m.nby * m.nbz,
             (int64_t)m.nbx * m.nbz * ((m.nby + a.lrun - 1) / a.lrun),
-            (int64_t)m.nbx * m.nby * ((m.nbz + a.lrun - 1) / a.lrun)};
+            (int64_t)m.nxr * m.ny * ((m.nbz + a.lrun - 1) / a.lrun)};
         for (int phase = 0; phase < 3; ++phase) {
             const int waves = grid_cap(items[phase], b->cus * (waves_per_cu > 0 ? waves_per_cu : 8));
             hipLaunchKernelGGL(k_batch_phase<M>, dim3((waves + 3) / 4), dim3(256), 0, st, a, phase,
@@ -533,7 +554,7 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
     a.chunk = t.chunk;
     a.schedule = t.schedule;
     a.itemmap = (const int32_t*)(b->ws + L.off_itemmap);
-    a.icap = L.nblocks;
+    a.icap = L.icap;
     hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(256), 0, st, a.maps, b->n, t.lrun,
                        (int32_t*)a.pref, a.queues);
     hipLaunchKernelGGL(k_batch_itemmap, dim3(b->n), dim3(256), 0, st, a.pref, b->n,
