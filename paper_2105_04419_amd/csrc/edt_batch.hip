@@ -211,7 +211,7 @@ __device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
             d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
         }
     };
-    window_min<M>(by0, len, Dp, blk, emit);
+    window_min<M, true>(by0, len, Dp, blk, emit);
 }
 
 // phase 2: windowed minimum along z, g2 -> dense int32 field.  An item is a
@@ -252,7 +252,7 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
             *p1 = (int)(v >> 16);
         }
     };
-    window_min<M>(bz0, len, Dp, blk, emit);
+    window_min<M, true>(bz0, len, Dp, blk, emit);
 }
 
 template <int M>

@@ -48,7 +48,12 @@ struct WinSkip {
 
 // need(ob): false when neither output block ob nor ob + 1 is wanted (must be
 // uniform across the wave); the window still slides over such a pair.
-template <int M, class Blk, class Emit, class Need>
+// LB: before each offset group G >= 1, also test a per-lane bound (the least
+// input in the group's position ranges plus (8G)^2 against the lane's largest
+// output) and skip the group when no lane can improve.  It pays on maps where
+// most groups are decided that way (dense maps), not where the block bounds
+// already skip them.
+template <int M, bool LB = false, class Blk, class Emit, class Need>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit,
                                   Need&& need, const WinSkip& sk) {
     constexpr int NW = 2 * M + 2;        // window blocks
@@ -88,10 +93,32 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                 // k >= 1) reads blocks ob - G - 1 .. ob - G + 1 and
                 // ob + G .. ob + G + 2; the two candidates at +-k share k^2,
                 // so min(in(i - k), in(i + k)) + k^2 covers both
+                // per-lane bound: group G offers candidates no smaller than the
+                // least input in its two position ranges plus (8G)^2; mx is the
+                // lane's largest output so far (both halves)
+                u16x2 mx = acc[0];
+#pragma unroll
+                for (int o = 1; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
 #pragma unroll
                 for (int G = 0; G < M; ++G) {
                     const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
                     if (((sk.g[G] >> sh) & CG) == CG) continue;
+                    if (LB && G > 0) {
+                        // candidates of group G for output o lie at o + 8M -+ k,
+                        // k = 8G .. 8G + 7: positions 8M - 8G - 7 .. 8M - 8G + 7
+                        // and 8M + 8G .. 8M + 8G + 14 (packed: the high half
+                        // covers the outputs o + 8)
+                        u16x2 lb = P[8 * M - 8 * G - 7];
+#pragma unroll
+                        for (int q = 8 * M - 8 * G - 6; q <= 8 * M - 8 * G + 7; ++q)
+                            lb = __builtin_elementwise_min(lb, P[q]);
+#pragma unroll
+                        for (int q = 8 * M + 8 * G; q <= 8 * M + 8 * G + 14 && q < NP; ++q)
+                            lb = __builtin_elementwise_min(lb, P[q]);
+                        const unsigned short g2 = (unsigned short)(64 * G * G);
+                        lb = lb + (u16x2){g2, g2};
+                        if (!__any(lb.x < mx.x || lb.y < mx.y)) continue;
+                    }
 #pragma unroll
                     for (int k = (G == 0 ? 1 : 8 * G); k <= 8 * G + 7; ++k) {
                         const unsigned short kk = (unsigned short)(k * k);
@@ -106,7 +133,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                     // stop once no output of the wave can still drop, i.e. all
                     // are <= (8G + 8)^2, the least any further candidate adds
                     if (G + 1 < M) {
-                        u16x2 mx = __builtin_elementwise_max(acc[0], acc[1]);
+                        mx = __builtin_elementwise_max(acc[0], acc[1]);
 #pragma unroll
                         for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
                         const int lim = (8 * G + 8) * (8 * G + 8);
@@ -124,9 +151,9 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
     }
 }
 
-template <int M, class Blk, class Emit>
+template <int M, bool LB = false, class Blk, class Emit>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
-    window_min<M>(first, count, Dp, blk, emit, [](int) { return true; }, WinSkip{});
+    window_min<M, LB>(first, count, Dp, blk, emit, [](int) { return true; }, WinSkip{});
 }
 
 }  // namespace edt
