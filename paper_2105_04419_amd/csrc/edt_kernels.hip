@@ -1466,7 +1466,13 @@ __global__ void k_upd_mark(Grid g) {
             const int32_t pa = r0.x, pr = r0.y, sx = r0.z, sy = r0.w, sz = rec[4];
             const int ox = o % w - R, oy = (o / w) % w - R, oz = o / (w * w) - R;
             const int bx = sx + ox, by = sy + oy, bz = sz + oz;
-            if (R <= 8) {
+            // box distances need no loads: a block beyond D of both boxes can
+            // only join the g1 / g2 sets (its own x row or xy plane of the seed)
+            const int da = pa != 0 ? box_dist2(pa, sx, sy, sz, bx, by, bz) : 0x7fffffff;
+            const int dr = pr != 0 ? box_dist2(pr, sx, sy, sz, bx, by, bz) : 0x7fffffff;
+            const bool maybe = da < g.D || dr < g.D || oz == 0;
+            if (!maybe) {
+            } else if (R <= 8) {
                 // the block's tile among the 27 recorded around the seed's tile
                 if (bx >= 0 && by >= 0 && bz >= 0) {
                     const int k = ((bx >> 3) - (sx >> 3) + 1) + 3 * ((by >> 3) - (sy >> 3) + 1) +
@@ -1479,17 +1485,17 @@ __global__ void k_upd_mark(Grid g) {
             }
             if (slot >= 0) {
                 const int bm = g.bmax[slot];
-                lower = pa != 0 && box_dist2(pa, sx, sy, sz, bx, by, bz) < bm;
-                if (pr != 0) {
-                    const int d2 = box_dist2(pr, sx, sy, sz, bx, by, bz);
-                    raise = d2 <= bm && d2 < g.D;
-                }
+                const uint32_t seen = g.flags[slot];   // bits only get set in this kernel
+                lower = da < bm;
+                raise = dr <= bm && dr < g.D;
                 uint32_t want = 0;
                 if (lower) want |= F_LOWER | F_DIRTY;
                 if (raise) want |= F_RAISE | F_DIRTY;
                 if (oz == 0) want |= F_YS;
                 if (oz == 0 && oy == 0) want |= F_XS;
-                if (want) {
+                if (!(want & ~seen)) {
+                    raise = lower = false;              // already marked by another seed
+                } else {
                     const uint32_t old = atomicOr(&g.flags[slot], want);
                     new_dirty = (want & F_DIRTY) && !(old & F_DIRTY);
                     new_ys = (want & F_YS) && !(old & F_YS);
