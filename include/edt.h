@@ -131,6 +131,17 @@ edt_status edt_update(edt_ctx* ctx, const int32_t* d_xyz, const uint8_t* d_state
 edt_status edt_query(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
                      int32_t* d_out, void* stream);
 
+/* Nearest obstacle (the `obst` of a cell in Algorithm 1; the feature
+ * transform of Eq. 1): for each of n voxel coordinates d_xyz (int32[n][3])
+ * writes to d_nearest (int32[n][3]) the coordinates of one occupied voxel o
+ * with |x - o|^2 = s(x).  Where several obstacles are that close, any one of
+ * them is returned.  Voxels with s(x) = D (no obstacle within d_max) and
+ * out-of-extent coordinates get (-1, -1, -1).  The answer is reconstructed
+ * from the stored per-axis minima (z, then y, then x), so it is consistent
+ * with edt_query after any sequence of updates. */
+edt_status edt_query_nearest(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
+                             int32_t* d_nearest, void* stream);
+
 /* Dense readback: s for the whole extent into d_out (int32[nx*ny*nz]). */
 edt_status edt_read_dense(edt_ctx* ctx, int32_t* d_out, void* stream);
 

@@ -89,6 +89,7 @@ def lib():
         "edt_global": ([vp, ctypes.POINTER(EdtMap), vp], ctypes.c_int),
         "edt_update": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "edt_query_nearest": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_read_dense": ([vp, vp, vp], ctypes.c_int),
         "edt_read_occupancy": ([vp, vp, vp], ctypes.c_int),
         "edt_get_stats": ([vp, ctypes.POINTER(EdtStats), vp], ctypes.c_int),
@@ -212,6 +213,17 @@ class Field:
             xyz = _dev_tensor(xyz, torch.int32, (n, 3))
             _check("edt_query", lib().edt_query(self._ctx, _ptr(xyz), n, _ptr(out),
                                                 _stream(stream)))
+        return out
+
+    def query_nearest(self, xyz: torch.Tensor, stream=None) -> torch.Tensor:
+        """Coordinates (x, y, z) of one nearest obstacle per query voxel,
+        (-1, -1, -1) where none lies within d_max."""
+        n = int(xyz.shape[0])
+        out = torch.empty((n, 3), dtype=torch.int32, device=self.device)
+        if n:
+            xyz = _dev_tensor(xyz, torch.int32, (n, 3))
+            _check("edt_query_nearest", lib().edt_query_nearest(self._ctx, _ptr(xyz), n, _ptr(out),
+                                                                _stream(stream)))
         return out
 
     def dense(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

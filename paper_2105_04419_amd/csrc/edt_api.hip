@@ -462,6 +462,17 @@ edt_status edt_query(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_t* d_out
     return EDT_OK;
 }
 
+edt_status edt_query_nearest(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_t* d_nearest,
+                             void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (n == 0) return EDT_OK;
+    if (!d_xyz || !d_nearest) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_query_nearest, dim3(grid_for(n, 256, 8192)), dim3(256), 0, S(stream),
+                       c->g, d_xyz, n, d_nearest);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
 edt_status edt_read_dense(edt_ctx* c, int32_t* d_out, void* stream) {
     if (!c || !d_out) return EDT_ERR_ARG;
     const Grid& g = c->g;

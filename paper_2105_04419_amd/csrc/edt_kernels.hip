@@ -1200,6 +1200,73 @@ __global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ o
     for (int k = 0; k < nxr; ++k) row[k] = (b >> k) & 1u;
 }
 
+// g1, g2 and s of voxel (x, y, z) inside the extent (absent block: D)
+__device__ inline int field_g1(const Grid& g, int x, int y, int z) {
+    const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
+    return slot < 0 ? g.D : g.g1[(int64_t)slot * 512 + (y & 7) + 8 * (x & 7) + 64 * (z & 7)];
+}
+__device__ inline int field_g2(const Grid& g, int x, int y, int z) {
+    const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
+    return slot < 0 ? g.D : g.g2[(int64_t)slot * 512 + (z & 7) + 8 * (x & 7) + 64 * (y & 7)];
+}
+__device__ inline bool field_occ(const Grid& g, int x, int y, int z) {
+    const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
+    if (slot < 0) return false;
+    const int v = (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+    return (g.occ[(int64_t)slot * 16 + (v >> 5)] >> (v & 31)) & 1u;
+}
+
+// One thread per query.  s = min over k of g2(z + k) + k^2 and
+// g2 = min over j of g1(y + j) + j^2, g1 = (x - x')^2 for the nearest
+// obstacle x' of the row: the offsets are found again by equality, nearest
+// first (uncapped values: s < D), then the obstacle sits at x +- sqrt(g1).
+__global__ void k_query_nearest(Grid g, const int32_t* __restrict__ xyz, int64_t n,
+                                int32_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        int ox = -1, oy = -1, oz = -1;
+        if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz) {
+            const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
+            const int sv = slot < 0 ? g.D : g.s[(int64_t)slot * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+            if (sv < g.D) {
+                // z offset
+                int kz = 0, t2 = -1;
+                for (int a = 0; a * a <= sv && t2 < 0; ++a) {
+                    for (int sg = 0; sg < 2 && t2 < 0; ++sg) {
+                        const int zz = sg ? z + a : z - a;
+                        if ((sg && a == 0) || zz < 0 || zz >= g.nz) continue;
+                        const int v = field_g2(g, x, y, zz);
+                        if (v + a * a == sv) { kz = zz; t2 = v; }
+                    }
+                }
+                // y offset
+                int ky = 0, t1 = -1;
+                for (int a = 0; t2 >= 0 && a * a <= t2 && t1 < 0; ++a) {
+                    for (int sg = 0; sg < 2 && t1 < 0; ++sg) {
+                        const int yy = sg ? y + a : y - a;
+                        if ((sg && a == 0) || yy < 0 || yy >= g.ny) continue;
+                        const int v = field_g1(g, x, yy, kz);
+                        if (v + a * a == t2) { ky = yy; t1 = v; }
+                    }
+                }
+                // x offset: g1 is a perfect square d^2
+                if (t1 >= 0) {
+                    int d = (int)sqrtf((float)t1);
+                    while (d * d > t1) --d;
+                    while ((d + 1) * (d + 1) <= t1) ++d;
+                    if (x - d >= 0 && field_occ(g, x - d, ky, kz)) ox = x - d;
+                    else if (x + d < g.nx && field_occ(g, x + d, ky, kz)) ox = x + d;
+                    if (ox >= 0) { oy = ky; oz = kz; }
+                }
+            }
+        }
+        out[3 * i] = ox;
+        out[3 * i + 1] = oy;
+        out[3 * i + 2] = oz;
+    }
+}
+
 __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int32_t* __restrict__ out) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
