@@ -62,12 +62,16 @@ const char* edt_status_str(int status);
  *                only where the field can differ from D: blocks holding an
  *                obstacle and the blocks within ceil(d_max/8) blocks of them
  *                (Chebyshev distance).
- *   max_changes  capacity for one edt_update call (entries), 0 = 2^20.       */
+ *   max_changes  capacity for one edt_update call (entries), 0 = 2^20.
+ *   max_interior_blocks  capacity for interior distances (edt_interior):
+ *                the number of blocks holding an obstacle it can serve;
+ *                0 = no interior storage.                                   */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t d_max;
     int64_t max_blocks;
     int64_t max_changes;
+    int64_t max_interior_blocks;
 } edt_config;
 
 typedef struct edt_ctx edt_ctx;
@@ -141,6 +145,34 @@ edt_status edt_query(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
  * with edt_query after any sequence of updates. */
 edt_status edt_query_nearest(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
                              int32_t* d_nearest, void* stream);
+
+/* Interior distances, the inside half of a signed distance field (the
+ * Euclidean signed distance fields of the voxel-hashing systems surveyed in
+ * section II): the field's definition (Eq. 1, clamped to D) with occupied
+ * and free voxels exchanged.  For every occupied voxel x,
+ *
+ *     s_in(x) = min( D, min over free voxels y of the extent of |x - y|^2 ),
+ *
+ * so s_in >= 1, and D where no free voxel lies within d_max (voxels outside
+ * the extent are neither free nor occupied).  Computed exactly from the
+ * current occupancy over the blocks holding an obstacle; valid until the next
+ * edt_global or edt_update.  EDT_ERR_STATE if the context was created with
+ * max_interior_blocks = 0.  More blocks holding an obstacle than
+ * max_interior_blocks set the device error word to EDT_ERR_CAPACITY; the
+ * interior values are then not valid. */
+edt_status edt_interior(edt_ctx* ctx, void* stream);
+
+/* Signed squared distance at n voxel coordinates d_xyz (int32[n][3]) into
+ * d_out (int32[n]): s(x) (>= 1) for a free voxel, -s_in(x) (<= -1) for an
+ * occupied one, D out of the extent; the signed Euclidean distance is
+ * sign(v) * sqrt(|v|).  EDT_ERR_STATE unless edt_interior ran after the
+ * last edt_global / edt_update. */
+edt_status edt_query_signed(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
+                            int32_t* d_out, void* stream);
+
+/* Dense signed readback (int32[nx*ny*nz], grid layout, values as
+ * edt_query_signed).  Same state requirement as edt_query_signed. */
+edt_status edt_read_signed_dense(edt_ctx* ctx, int32_t* d_out, void* stream);
 
 /* Dense readback: s for the whole extent into d_out (int32[nx*ny*nz]). */
 edt_status edt_read_dense(edt_ctx* ctx, int32_t* d_out, void* stream);

@@ -9,6 +9,11 @@ Contents
       The truncated squared Euclidean distance transform of the VDB-EDT paper
       (section III, Eq. 1, limited to the transform radius d_max), written in
       plain C in ``edt_oracle.c`` and called through ctypes.
+  interior / signed_field
+      The inside half of a signed distance field: the same definition with
+      occupied and free voxels exchanged (the squared distance from an
+      occupied voxel to the nearest free voxel of the extent, clamped to D),
+      and the signed field that combines the two.
   clearance (module ``oracle.clearance``)
       The trajectory clearance cost built on the distance field (section III,
       Eq. 2 clearance term, squared hinge form), its analytic gradient and a
@@ -104,6 +109,22 @@ def edt_separable(occ: np.ndarray, dmax: int) -> np.ndarray:
     if rc:
         raise ValueError(f"oracle_edt_separable: failed ({rc})")
     return out
+
+
+def interior(occ: np.ndarray, dmax: int) -> np.ndarray:
+    """min(D, min over free voxels y of |x-y|^2) for every voxel: Eq. 1 on
+    the complement of the occupancy.  Voxels outside the extent are neither
+    free nor occupied, so a voxel with no free voxel within d_max gets D."""
+    occ, _, _, _ = _grid(occ)
+    return edt_separable((occ == 0).astype(np.uint8), dmax)
+
+
+def signed_field(occ: np.ndarray, dmax: int) -> np.ndarray:
+    """Signed squared distance: s(x) on free voxels, -interior(x) on
+    occupied voxels (so 0 never occurs: s >= 1 off obstacles, interior >= 1
+    on them)."""
+    occ, _, _, _ = _grid(occ)
+    return np.where(occ != 0, -interior(occ, dmax), edt_separable(occ, dmax)).astype(np.int32)
 
 
 def threads(n: int = 0) -> int:

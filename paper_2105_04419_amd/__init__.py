@@ -39,7 +39,7 @@ class EdtError(RuntimeError):
 class EdtConfig(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("d_max", ctypes.c_int32), ("max_blocks", ctypes.c_int64),
-                ("max_changes", ctypes.c_int64)]
+                ("max_changes", ctypes.c_int64), ("max_interior_blocks", ctypes.c_int64)]
 
 
 class EdtMap(ctypes.Structure):
@@ -90,6 +90,9 @@ def lib():
         "edt_update": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_query_nearest": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "edt_interior": ([vp, vp], ctypes.c_int),
+        "edt_query_signed": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "edt_read_signed_dense": ([vp, vp, vp], ctypes.c_int),
         "edt_read_dense": ([vp, vp, vp], ctypes.c_int),
         "edt_read_occupancy": ([vp, vp, vp], ctypes.c_int),
         "edt_get_stats": ([vp, ctypes.POINTER(EdtStats), vp], ctypes.c_int),
@@ -143,12 +146,13 @@ class Field:
     workspace (a torch uint8 tensor that owns the device memory)."""
 
     def __init__(self, shape, d_max: int, max_blocks: int = 0, max_changes: int = 0,
-                 device=None, stream=None):
+                 max_interior_blocks: int = 0, device=None, stream=None):
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
         self.d_max = int(d_max)
         self.D = self.d_max * self.d_max
-        self.cfg = EdtConfig(nx, ny, nz, self.d_max, int(max_blocks), int(max_changes))
+        self.cfg = EdtConfig(nx, ny, nz, self.d_max, int(max_blocks), int(max_changes),
+                             int(max_interior_blocks))
         L = lib()
         nbytes = L.edt_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes < 0:
@@ -224,6 +228,29 @@ class Field:
             xyz = _dev_tensor(xyz, torch.int32, (n, 3))
             _check("edt_query_nearest", lib().edt_query_nearest(self._ctx, _ptr(xyz), n, _ptr(out),
                                                                 _stream(stream)))
+        return out
+
+    def interior(self, stream=None):
+        """Interior distances of the occupied voxels (squared distance to the
+        nearest free voxel, clamped to D), valid until the next transform."""
+        _check("edt_interior", lib().edt_interior(self._ctx, _stream(stream)))
+        return self
+
+    def query_signed(self, xyz: torch.Tensor, stream=None) -> torch.Tensor:
+        """Signed squared distances: s on free voxels, -(interior) on occupied ones."""
+        n = int(xyz.shape[0])
+        out = torch.empty(n, dtype=torch.int32, device=self.device)
+        xyz = _dev_tensor(xyz, torch.int32, (n, 3)) if n else xyz
+        _check("edt_query_signed", lib().edt_query_signed(self._ctx, _ptr(xyz) if n else None, n,
+                                                          _ptr(out) if n else None,
+                                                          _stream(stream)))
+        return out
+
+    def signed_dense(self, stream=None) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        out = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+        _check("edt_read_signed_dense", lib().edt_read_signed_dense(self._ctx, _ptr(out),
+                                                                    _stream(stream)))
         return out
 
     def dense(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

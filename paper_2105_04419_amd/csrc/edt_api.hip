@@ -30,6 +30,7 @@ struct edt_ctx {
     int64_t tcap;       // tile hash capacity
     int64_t ucap;       // update hash capacity
     int64_t stats_host[C_N];
+    bool interior_valid;   // edt_interior ran after the last global / update
 };
 
 namespace {
@@ -41,15 +42,15 @@ int64_t next_pow2(int64_t v) {
 }
 
 struct Layout {
-    int64_t max_blocks, max_changes, tcap, ucap;
-    int64_t off[32];
+    int64_t max_blocks, max_changes, max_int, tcap, ucap;
+    int64_t off[40];
     int64_t total;
 };
 
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -58,7 +59,7 @@ bool valid_cfg(const edt_config* c) {
     if (c->nx < 1 || c->ny < 1 || c->nz < 1 || c->nx > lim || c->ny > lim || c->nz > lim)
         return false;
     if (c->d_max < 1 || c->d_max > 255) return false;
-    if (c->max_blocks < 0 || c->max_changes < 0) return false;
+    if (c->max_blocks < 0 || c->max_changes < 0 || c->max_interior_blocks < 0) return false;
     return true;
 }
 
@@ -70,8 +71,10 @@ bool layout_of(const edt_config* c, Layout* L) {
     if (mb > (1 << 22)) return false;                   // slot*512 stays in int32
     const int64_t mc = c->max_changes ? c->max_changes : (1 << 20);
     if (mc > (1 << 28)) return false;
+    const int64_t mi = c->max_interior_blocks < mb ? c->max_interior_blocks : mb;
     L->max_blocks = mb;
     L->max_changes = mc;
+    L->max_int = mi;
     // tiles of 8x8x8 blocks: at most one per tile of the extent and one per block
     const int64_t ntx = (nbx + 7) / 8, nty = (nby + 7) / 8, ntz = (nbz + 7) / 8;
     int64_t tiles = ntx * nty * ntz;
@@ -84,7 +87,8 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, 64 * 4,
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
-        L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4};
+        L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4,
+        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -289,6 +293,11 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.tflag = (int32_t*)(b + L.off[O_TFLAG]);
     g.bmin1 = (uint16_t*)(b + L.off[O_BMIN]);
     g.bmin2 = g.bmin1 + L.max_blocks;
+    g.max_int = (int)L.max_int;
+    g.iidx = (int32_t*)(b + L.off[O_IIDX]);
+    g.ilist = (int32_t*)(b + L.off[O_ILIST]);
+    g.ic1 = (uint16_t*)(b + L.off[O_IC1]);
+    g.ic2 = (uint16_t*)(b + L.off[O_IC2]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -386,6 +395,7 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
     } else {
         return EDT_ERR_ARG;
     }
+    c->interior_valid = false;
     mark(c, 0, st);
     hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
                        g, c->tcap);
@@ -424,6 +434,7 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
     if (n == 0) return EDT_OK;
     if (!d_xyz || !d_state) return EDT_ERR_ARG;
     if (n > c->g.max_changes) return EDT_ERR_CAPACITY;
+    c->interior_valid = false;
     Grid& g = c->g;
     hipStream_t st = S(stream);
     const int mb = g.max_blocks;
@@ -469,6 +480,43 @@ edt_status edt_query_nearest(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_
     if (!d_xyz || !d_nearest) return EDT_ERR_ARG;
     hipLaunchKernelGGL(k_query_nearest, dim3(grid_for(n, 256, 8192)), dim3(256), 0, S(stream),
                        c->g, d_xyz, n, d_nearest);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_interior(edt_ctx* c, void* stream) {
+    if (!c) return EDT_ERR_ARG;
+    const Grid& g = c->g;
+    if (g.max_int <= 0) return EDT_ERR_STATE;
+    hipStream_t st = S(stream);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt + C_NINT, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_int_list, dim3(grid_for(g.max_blocks, 4, 16384)), dim3(64), 0, st, g);
+    const int grid = grid_for(g.max_int, 1, 16384);
+    hipLaunchKernelGGL(k_int_x, dim3(grid), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_int_yz<1>, dim3(grid), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_int_yz<2>, dim3(grid), dim3(64), 0, st, g);
+    LAUNCH_CHECK();
+    c->interior_valid = true;
+    return EDT_OK;
+}
+
+edt_status edt_query_signed(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_t* d_out,
+                            void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (!c->interior_valid) return EDT_ERR_STATE;
+    if (n == 0) return EDT_OK;
+    if (!d_xyz || !d_out) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_query_signed, dim3(grid_for(n, 256, 8192)), dim3(256), 0, S(stream),
+                       c->g, d_xyz, n, d_out);
+    LAUNCH_CHECK();
+    return EDT_OK;
+}
+
+edt_status edt_read_signed_dense(edt_ctx* c, int32_t* d_out, void* stream) {
+    if (!c || !d_out) return EDT_ERR_ARG;
+    if (!c->interior_valid) return EDT_ERR_STATE;
+    const Grid& g = c->g;
+    hipLaunchKernelGGL(k_read_signed, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_out);
     LAUNCH_CHECK();
     return EDT_OK;
 }

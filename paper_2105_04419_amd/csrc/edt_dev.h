@@ -17,7 +17,7 @@
 //          block and lane in pass y).
 //   g2     uint16 per voxel, layout (x + 8y) * 8 + z: min over dy of
 //          g1(x, y+dy, z) + dy^2, clamped to D (contiguous z-columns).
-//   s      int32 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
+//   s      uint16 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
 //   bmax   int32: max of s over the block (pruning bound for updates).
 //   flags  uint32: state bits (F_*).
 // Blocks exist exactly where s can differ from D: blocks that held an
@@ -46,7 +46,7 @@ enum : uint32_t {
 
 // device counters (int32 slots of the counter array)
 enum {
-    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_RESERVED4, C_RESERVED5,
+    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_RESERVED5,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
     C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_N
 };
@@ -94,6 +94,13 @@ struct Grid {
     int32_t* upos;
     uint16_t* bmin1;         // [slot] least g1 value of the block (global transform)
     uint16_t* bmin2;         // [slot] least g2 value of the block (global transform)
+    int max_int;             // capacity of the interior-distance blocks
+    int32_t* iidx;           // [slot] index among the blocks holding an obstacle, or -1
+                             // (written by the interior transform)
+    int32_t* ilist;          // [interior index] pool slot
+    uint16_t* ic1;           // [interior index][512] interior pass x (layout y + 8x + 64z),
+                             // then the interior field (layout x + 8y + 64z)
+    uint16_t* ic2;           // [interior index][512] interior pass y (layout z + 8x + 64y)
     uint32_t* dummy;         // 256 x 256 words of write-only scratch rows
     uint16_t* dblock;        // one block of D values (stands for absent blocks)
 };

@@ -1619,6 +1619,245 @@ __global__ void k_upd_cleanup(Grid g, int64_t n) {
     for (int64_t i = tid; i < ny; i += stride) atomicAnd(&g.flags[g.list_ys[i]], clear);
 }
 
+// ---------------------------------------------------------------------------
+// Interior distances: for an occupied voxel, the squared distance to the
+// nearest free voxel of the extent, clamped to D (the definition of the field
+// with occupied and free exchanged: the inside half of a signed distance
+// field).  Only blocks holding an obstacle carry interior values.  Every other
+// block of the extent, in the pool or not, is all free, so both intermediate
+// passes are 0 on it; the passes below take such blocks as 0 without storage.
+// ---------------------------------------------------------------------------
+
+// Lists the pool blocks holding an obstacle (four blocks per wave, one
+// occupancy word per lane) and writes every slot's interior index.
+__global__ void __launch_bounds__(64) k_int_list(Grid g) {
+    const int lane = threadIdx.x;
+    const int64_t n0 = g.cnt[C_NBLK];
+    const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
+    for (int64_t base = 4 * (int64_t)blockIdx.x; base < n; base += 4 * (int64_t)gridDim.x) {
+        const int64_t slot = base + (lane >> 4);
+        const uint32_t w = slot < n ? g.occ[slot * 16 + (lane & 15)] : 0u;
+        const unsigned long long m = __ballot(w != 0u);
+        const bool head = (lane & 15) == 0 && slot < n;
+        const bool has = head && ((m >> (lane & 48)) & 0xffffull) != 0ull;
+        const int idx = wave_append(has, &g.cnt[C_NINT]);
+        if (head) {
+            int32_t v = -1;
+            if (has) {
+                if (idx < g.max_int) {
+                    g.ilist[idx] = (int32_t)slot;
+                    v = idx;
+                } else {
+                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                }
+            }
+            g.iidx[slot] = v;
+        }
+    }
+}
+
+// Interior pass x: per row of a listed block, the distance along x to the
+// nearest free voxel of the extent, squared and clamped to D.  One wave per
+// block, lane = row y + 8z.  Neighbour blocks are read outwards until every
+// lane has met a free voxel on both sides, at most R blocks each way (a voxel
+// farther than that is beyond d_max).  Rows outside the extent get D.
+__global__ void __launch_bounds__(64) k_int_x(Grid g) {
+    __shared__ int32_t nb[72];
+    const int lane = threadIdx.x;
+    const int64_t n0 = g.cnt[C_NINT];
+    const int64_t n = n0 < g.max_int ? n0 : g.max_int;
+    const int R = g.R;
+    const uint8_t* occ8 = (const uint8_t*)g.occ;
+    const int y = lane & 7, z = lane >> 3;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int32_t slot = g.ilist[i];
+        int bx, by, bz;
+        unpack_key(g.bkey[slot], bx, by, bz);
+        for (int k = lane; k < 2 * R + 1; k += 64)
+            nb[k] = k == R ? slot : find_block(g, bx - R + k, by, bz);
+        __syncthreads();
+        const bool in = 8 * by + y < g.ny && 8 * bz + z < g.nz;
+        // free voxels of row (y, z) in block bx + k (extent voxels only)
+        auto freebits = [&](int k) -> uint32_t {
+            const int w = g.nx - 8 * (bx + k);
+            const uint32_t ext = w >= 8 ? 0xffu : (1u << w) - 1u;
+            const int32_t s2 = nb[R + k];
+            return s2 < 0 ? ext : ~(uint32_t)occ8[(int64_t)s2 * 64 + lane] & ext;
+        };
+        const uint32_t own = freebits(0);
+        // nearest free voxel left of the block (offset from voxel 0 of the
+        // block, negative) and right of it (offset, >= 8)
+        int left = -(1 << 16), right = 1 << 16;
+        bool dl = !in, dr = !in;
+        for (int k = 1; k <= R; ++k) {
+            if (!dl) {
+                if (bx - k < 0) {
+                    dl = true;
+                } else {
+                    const uint32_t f = freebits(-k);
+                    if (f) { left = -8 * k + (31 - __clz(f)); dl = true; }
+                }
+            }
+            if (!dr) {
+                if (bx + k >= g.nbx) {
+                    dr = true;
+                } else {
+                    const uint32_t f = freebits(k);
+                    if (f) { right = 8 * k + (__ffs(f) - 1); dr = true; }
+                }
+            }
+            if (__ballot(!(dl && dr)) == 0ull) break;
+        }
+        uint16_t* dst = g.ic1 + i * 512 + y + 64 * z;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            int d = min(x - left, right - x);
+#pragma unroll
+            for (int xx = 0; xx < 8; ++xx)
+                if ((own >> xx) & 1u) d = min(d, abs(x - xx));
+            d = min(d, g.dmax);
+            dst[8 * x] = (uint16_t)(in ? d * d : g.D);
+        }
+        __syncthreads();
+    }
+}
+
+// Interior pass along y (AXIS 1: ic1 -> ic2) or z (AXIS 2: ic2 -> ic1, the
+// interior field): out(t) = min(D, min over t' of in(t') + (t - t')^2) along
+// the axis, where `in` is the previous interior pass on listed blocks and 0
+// on every other voxel of the extent.  One wave per listed block, lane = one
+// column of 8 outputs.  Neighbour blocks are visited outwards and the walk
+// stops once no lane can improve: every voxel of block offset k is at least
+// 8(k - 1) + 1 away.  Columns outside the extent get D.
+template <int AXIS>
+__global__ void __launch_bounds__(64) k_int_yz(Grid g) {
+    __shared__ int32_t nb[72];   // interior index of block offset k - R; -1 all free; -2 outside
+    const int lane = threadIdx.x;
+    const int64_t n0 = g.cnt[C_NINT];
+    const int64_t n = n0 < g.max_int ? n0 : g.max_int;
+    const int R = g.R;
+    const int D = g.D;
+    const uint16_t* src = AXIS == 1 ? g.ic1 : g.ic2;
+    uint16_t* dst = AXIS == 1 ? g.ic2 : g.ic1;
+    const int ca = lane & 7, cb = lane >> 3;   // column (x, z) for y, (x, y) for z
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        int bx, by, bz;
+        unpack_key(g.bkey[g.ilist[i]], bx, by, bz);
+        const int bc = AXIS == 1 ? by : bz;
+        const int nbc = AXIS == 1 ? g.nby : g.nbz;
+        for (int k = lane; k < 2 * R + 1; k += 64) {
+            const int b = bc - R + k;
+            int32_t e = -2;
+            if (k == R) {
+                e = (int32_t)i;
+            } else if (b >= 0 && b < nbc) {
+                const int32_t s2 = AXIS == 1 ? find_block(g, bx, b, bz) : find_block(g, bx, by, b);
+                e = s2 < 0 ? -1 : g.iidx[s2];
+            }
+            nb[k] = e;
+        }
+        __syncthreads();
+        const bool in = 8 * bx + ca < g.nx &&
+                        (AXIS == 1 ? 8 * bz + cb < g.nz : 8 * by + cb < g.ny);
+        int best[8];
+        {
+            const uint4 q = *reinterpret_cast<const uint4*>(src + i * 512 + 8 * lane);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                int b = D;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int v = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+                    b = min(b, v + (t - u) * (t - u));
+                }
+                best[t] = b;
+            }
+        }
+        for (int k = 1; k <= R; ++k) {
+            int worst = 0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) worst = max(worst, best[t]);
+            const int lb = 8 * (k - 1) + 1;
+            if (__ballot(in && lb * lb < worst) == 0ull) break;
+#pragma unroll
+            for (int side = -1; side <= 1; side += 2) {
+                const int32_t e = nb[R + side * k];
+                if (e == -2) continue;
+                if (e == -1) {
+                    // all free: the block's voxel nearest to the column
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int d = side < 0 ? t + 8 * (k - 1) + 1 : 8 * k - t;
+                        best[t] = min(best[t], d * d);
+                    }
+                } else {
+                    const uint4 q = *reinterpret_cast<const uint4*>(src + (int64_t)e * 512 + 8 * lane);
+                    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int v = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+                        const int tu = side * 8 * k + u;
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) best[t] = min(best[t], v + (t - tu) * (t - tu));
+                    }
+                }
+            }
+        }
+        uint16_t* o = dst + i * 512;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const uint16_t v = (uint16_t)(in ? min(best[t], D) : D);
+            if (AXIS == 1) o[cb + 8 * ca + 64 * t] = v;     // layout z + 8x + 64y
+            else o[lane + 64 * t] = v;                      // layout x + 8y + 64z
+        }
+        __syncthreads();
+    }
+}
+
+// Signed squared distance of voxel (x, y, z) inside the extent: s for a free
+// voxel, minus the interior value for an occupied one.
+__device__ inline int32_t signed_at(const Grid& g, int x, int y, int z) {
+    const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
+    if (slot < 0) return g.D;
+    const int v = (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+    if ((g.occ[(int64_t)slot * 16 + (v >> 5)] >> (v & 31)) & 1u) {
+        const int32_t ii = g.iidx[slot];
+        return -(ii >= 0 ? (int32_t)g.ic1[(int64_t)ii * 512 + v] : g.D);
+    }
+    return g.s[(int64_t)slot * 512 + v];
+}
+
+__global__ void k_query_signed(Grid g, const int32_t* __restrict__ xyz, int64_t n,
+                               int32_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        const bool in = x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
+        out[i] = in ? signed_at(g, x, y, z) : g.D;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_read_signed(Grid g, int32_t* __restrict__ out) {
+    const int lane = threadIdx.x;
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int32_t slot = find_block(g, bx, by, bz);
+    const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
+    if (y >= g.ny || z >= g.nz) return;
+    int32_t* row = out + ((int64_t)z * g.ny + y) * (int64_t)g.nx + 8 * bx;
+    const int nxr = min(8, g.nx - 8 * bx);
+    if (slot < 0) {
+        for (int k = 0; k < nxr; ++k) row[k] = g.D;
+        return;
+    }
+    const uint32_t b = ((const uint8_t*)g.occ)[(int64_t)slot * 64 + lane];
+    const int32_t ii = g.iidx[slot];
+    const uint16_t* sv = g.s + (int64_t)slot * 512 + 8 * lane;
+    const uint16_t* iv = ii >= 0 ? g.ic1 + (int64_t)ii * 512 + 8 * lane : nullptr;
+    for (int k = 0; k < nxr; ++k)
+        row[k] = ((b >> k) & 1u) ? -(iv ? (int32_t)iv[k] : g.D) : (int32_t)sv[k];
+}
+
 __global__ void k_clear_error(Grid g) { g.cnt[C_ERR] = 0; }
 
 }  // namespace edt
