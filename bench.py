@@ -16,7 +16,9 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
   batched        64 dense room maps (sides 32..256, d_max 24): autotuned
                  fused persistent launch vs per-map launches;
   dense_small    the 64x64x32 boxes map (d_max 20), microseconds per
-                 global transform.
+                 global transform;
+  interior       interior distances (edt_interior) of the tunnel map's
+                 occupied voxels, the inside half of the signed field.
 """
 from __future__ import annotations
 
@@ -363,6 +365,30 @@ def bench_dense_small(args, torch, np):
             "voxels_per_s": 64 * 64 * 32 / (ms * 1e-3)}
 
 
+def bench_interior(g, args, torch, np):
+    """Interior distances (edt_interior) of the tunnel map's occupied voxels."""
+    from paper_2105_04419_amd import Field
+    nz, ny, nx = g["occ"].shape
+    f = Field((nx, ny, nz), args.dmax, max_interior_blocks=g["n_obst_blocks"])
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    for _ in range(5):
+        f.interior()
+    torch.cuda.synchronize()
+    assert f.error() == 0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = 50
+    e0.record()
+    for _ in range(n):
+        f.interior()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    nb = g["n_obst_blocks"]
+    return {"workload": f"tunnel map, {nb} blocks holding an obstacle, d_max {args.dmax}",
+            "ms": round(ms, 5), "block_voxels_per_s": nb * 512 / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,6 +459,8 @@ def main():
         out["batched"] = bench_batch(args, torch, np)
         log("[bench] dense 64x64x32 global transform")
         out["dense_small"] = bench_dense_small(args, torch, np)
+        log("[bench] interior distances of the tunnel map")
+        out["interior"] = bench_interior(g, args, torch, np)
         log("[bench] tunnel map tiled 2x2 (working set beyond the last-level cache)")
         out["tunnel_x4"] = bench_tunnel_x4(args, torch, np)
     print(json.dumps(out), flush=True)
