@@ -129,6 +129,15 @@ edt_status edt_global(edt_ctx* ctx, const edt_map* map, void* stream);
 edt_status edt_update(edt_ctx* ctx, const int32_t* d_xyz, const uint8_t* d_state,
                       int64_t n, void* stream);
 
+/* Compaction: rebuilds the block pool from the current occupancy and
+ * recomputes s (the global transform of the current map).  Updates only add
+ * blocks; blocks whose obstacles have all been removed stay in the pool.
+ * This drops every block that no longer holds an obstacle and lies beyond
+ * ceil(d_max/8) blocks of all that do (the background-value pruning of a VDB
+ * tree, section IV-A), so the pool follows the map again.  s is unchanged;
+ * pool slots are renumbered. */
+edt_status edt_compact(edt_ctx* ctx, void* stream);
+
 /* s at n voxel coordinates d_xyz (int32[n][3]) into d_out (int32[n]);
  * out-of-extent coordinates and voxels of blocks that hold no field read D
  * (the VDB background value). */

@@ -9,6 +9,8 @@ Contents
       The truncated squared Euclidean distance transform of the VDB-EDT paper
       (section III, Eq. 1, limited to the transform radius d_max), written in
       plain C in ``edt_oracle.c`` and called through ctypes.
+  edt_points_list
+      The same definition for an obstacle list (sparse maps on huge extents).
   interior / signed_field
       The inside half of a signed distance field: the same definition with
       occupied and free voxels exchanged (the squared distance from an
@@ -109,6 +111,24 @@ def edt_separable(occ: np.ndarray, dmax: int) -> np.ndarray:
     if rc:
         raise ValueError(f"oracle_edt_separable: failed ({rc})")
     return out
+
+
+def edt_points_list(obstacles: np.ndarray, dmax: int, xyz: np.ndarray) -> np.ndarray:
+    """Eq. 1 at voxels xyz (int[n, 3], (x, y, z)) for an obstacle set given
+    as a list of voxel coordinates (int[m, 3]) instead of a grid: for sparse
+    maps on extents far too large to hold densely.  Plain all-pairs minimum
+    (numpy, in chunks)."""
+    obs = np.asarray(obstacles, dtype=np.int64).reshape(-1, 3)
+    q = np.asarray(xyz, dtype=np.int64).reshape(-1, 3)
+    D = int(dmax) * int(dmax)
+    out = np.full(len(q), D, dtype=np.int64)
+    if len(obs) == 0:
+        return out.astype(np.int32)
+    step = max(1, (1 << 22) // len(obs))
+    for i in range(0, len(q), step):
+        d2 = ((q[i:i + step, None, :] - obs[None, :, :]) ** 2).sum(-1).min(1)
+        out[i:i + step] = np.minimum(d2, D)
+    return out.astype(np.int32)
 
 
 def interior(occ: np.ndarray, dmax: int) -> np.ndarray:

@@ -90,6 +90,7 @@ def lib():
         "edt_update": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_query_nearest": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "edt_compact": ([vp, vp], ctypes.c_int),
         "edt_interior": ([vp, vp], ctypes.c_int),
         "edt_query_signed": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_read_signed_dense": ([vp, vp, vp], ctypes.c_int),
@@ -207,6 +208,12 @@ class Field:
         _check("edt_update", lib().edt_update(self._ctx, _ptr(xyz), _ptr(state), n,
                                               _stream(stream)))
         self._keep = (xyz, state)
+        return self
+
+    def compact(self, stream=None):
+        """Rebuild the block pool from the current occupancy (drops blocks no
+        longer within reach of an obstacle); the field is unchanged."""
+        _check("edt_compact", lib().edt_compact(self._ctx, _stream(stream)))
         return self
 
     # -- reads ----------------------------------------------------------------

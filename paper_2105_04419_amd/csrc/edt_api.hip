@@ -414,16 +414,49 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
         // ORed in
         const int64_t n = map->n_blocks;
         if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_mark, dim3(grid_for((n + 7) / 8, 1, 16384)),
-                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n);
+            hipLaunchKernelGGL(k_ingest_blocks_mark<false>, dim3(grid_for((n + 7) / 8, 1, 16384)),
+                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n,
+                               (const int32_t*)nullptr);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
         if (r) return r;
         if (n > 0)
-            hipLaunchKernelGGL(k_ingest_blocks_write, dim3(grid_for((n + 7) / 8, 1, 16384)),
-                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n);
+            hipLaunchKernelGGL(k_ingest_blocks_write<false>, dim3(grid_for((n + 7) / 8, 1, 16384)),
+                               dim3(64), 0, st, g, map->d_block_xyz, map->d_block_occ, n,
+                               (const int32_t*)nullptr);
         mark(c, 2, st);
     }
+    LAUNCH_CHECK();
+    return run_passes_global(c, st);
+}
+
+edt_status edt_compact(edt_ctx* c, void* stream) {
+    if (!c) return EDT_ERR_ARG;
+    Grid& g = c->g;
+    hipStream_t st = S(stream);
+    c->interior_valid = false;
+    // the list lives in the g1 storage (rewritten by the passes that follow):
+    // 12 bytes of coordinates and 64 bytes of occupancy per block; the count
+    // in the first word of g2 (rewritten by the passes too)
+    const int64_t mb = g.max_blocks;
+    int32_t* count = (int32_t*)g.g2;
+    int32_t* lxyz = (int32_t*)g.g1;
+    uint8_t* lbits = (uint8_t*)g.g1 + ((12 * mb + 255) & ~(int64_t)255);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, count, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb, 4, 16384)), dim3(64), 0, st, g, count,
+                       lxyz, (uint32_t*)lbits);
+    mark(c, 0, st);
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
+                       g, c->tcap);
+    const int grid = grid_for((mb + 7) / 8, 1, 16384);
+    hipLaunchKernelGGL(k_ingest_blocks_mark<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
+                       (int64_t)0, (const int32_t*)count);
+    mark(c, 1, st);
+    edt_status r = dilate_region(c, st);
+    if (r) return r;
+    hipLaunchKernelGGL(k_ingest_blocks_write<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
+                       (int64_t)0, (const int32_t*)count);
+    mark(c, 2, st);
     LAUNCH_CHECK();
     return run_passes_global(c, st);
 }

@@ -236,18 +236,36 @@ __device__ inline unsigned long long block_rows8(const Grid& g, const int32_t* x
     return rows;
 }
 
+// Word q of input block i's occupancy.  BITS: the input already holds the
+// pool's bit layout (64 bytes per block, as the compaction gathers it);
+// otherwise one byte per voxel (block_rows8).
+template <bool BITS>
+__device__ inline unsigned long long input_rows(const Grid& g, const int32_t* xyz,
+                                                const uint8_t* data, int64_t i, int q, int& bx,
+                                                int& by, int& bz, bool& in_range) {
+    if (!BITS) return block_rows8(g, xyz, data, i, q, bx, by, bz, in_range);
+    bx = xyz[3 * i];
+    by = xyz[3 * i + 1];
+    bz = xyz[3 * i + 2];
+    in_range = bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz;
+    return ((const unsigned long long*)data)[i * 8 + q];
+}
+
 // Block list, phase 1: record every block holding an obstacle in its tile's
 // obstacle mask (creating the tile and its neighbourhood).  Pool slots are
-// assigned by the dilation.
+// assigned by the dilation.  The block count is n, or *n_dev when given.
+template <bool BITS>
 __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t* xyz,
-                                                          const uint8_t* data, int64_t n) {
+                                                          const uint8_t* data, int64_t n0,
+                                                          const int32_t* n_dev) {
     const int lane = threadIdx.x, sub = lane >> 3, q = lane & 7;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     for (int64_t i0 = (int64_t)blockIdx.x * 8; i0 < n; i0 += (int64_t)gridDim.x * 8) {
         const int64_t i = i0 + sub;
         int bx = 0, by = 0, bz = 0;
         bool ok = false;
         unsigned long long rows = 0ull;
-        if (i < n) rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
+        if (i < n) rows = input_rows<BITS>(g, xyz, data, i, q, bx, by, bz, ok);
         const bool any = ((__ballot(rows != 0ull) >> (8 * sub)) & 0xffull) != 0ull;
         bool first = false;
         if (q == 0 && i < n) {
@@ -273,15 +291,18 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
 
 // Block list, phase 2 (after the dilation created and zeroed every slot): OR
 // the bits in (repeated listings merge), one 64-bit word per lane.
+template <bool BITS>
 __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_t* xyz,
-                                                           const uint8_t* data, int64_t n) {
+                                                           const uint8_t* data, int64_t n0,
+                                                           const int32_t* n_dev) {
     const int lane = threadIdx.x, sub = lane >> 3, q = lane & 7;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     for (int64_t i0 = (int64_t)blockIdx.x * 8; i0 < n; i0 += (int64_t)gridDim.x * 8) {
         const int64_t i = i0 + sub;
         if (i >= n) continue;
         int bx, by, bz;
         bool ok;
-        const unsigned long long rows = block_rows8(g, xyz, data, i, q, bx, by, bz, ok);
+        const unsigned long long rows = input_rows<BITS>(g, xyz, data, i, q, bx, by, bz, ok);
         if (!ok || rows == 0ull) continue;
         const int32_t slot = find_block(g, bx, by, bz);
         if (slot < 0) continue;
@@ -1617,6 +1638,38 @@ __global__ void k_upd_cleanup(Grid g, int64_t n) {
     for (int64_t i = tid; i < nd; i += stride) atomicAnd(&g.flags[g.list_dirty[i]], clear);
     const int64_t ny = g.cnt[C_NYS];
     for (int64_t i = tid; i < ny; i += stride) atomicAnd(&g.flags[g.list_ys[i]], clear);
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: the blocks holding an obstacle (coordinates and occupancy
+// words) are copied into a list, from which a global transform rebuilds the
+// pool; blocks that no longer hold an obstacle and lie beyond R blocks of
+// every obstacle block drop out.  Four pool slots per wave, one occupancy
+// word per lane.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_compact_gather(Grid g, int32_t* count, int32_t* xyz,
+                                                       uint32_t* bits) {
+    const int lane = threadIdx.x;
+    const int64_t n0 = g.cnt[C_NBLK];
+    const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
+    for (int64_t base = 4 * (int64_t)blockIdx.x; base < n; base += 4 * (int64_t)gridDim.x) {
+        const int64_t slot = base + (lane >> 4);
+        const uint32_t w = slot < n ? g.occ[slot * 16 + (lane & 15)] : 0u;
+        const unsigned long long m = __ballot(w != 0u);
+        const bool head = (lane & 15) == 0 && slot < n;
+        const bool has = head && ((m >> (lane & 48)) & 0xffffull) != 0ull;
+        const int idx = __shfl(wave_append(has, count), lane & 48);
+        if (((m >> (lane & 48)) & 0xffffull) != 0ull && slot < n) {
+            bits[(int64_t)idx * 16 + (lane & 15)] = w;
+            if (head) {
+                int bx, by, bz;
+                unpack_key(g.bkey[slot], bx, by, bz);
+                xyz[3 * idx] = bx;
+                xyz[3 * idx + 1] = by;
+                xyz[3 * idx + 2] = bz;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

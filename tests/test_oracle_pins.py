@@ -264,3 +264,19 @@ def test_locality_of_change():
 def test_bad_arguments_raise():
     with pytest.raises(ValueError):
         oracle.edt_separable(np.zeros((2, 2, 2), np.uint8), 0)
+
+
+def test_points_list_matches_grid_and_closed_form():
+    rng = np.random.default_rng(21)
+    occ = (rng.random((11, 13, 17)) < 0.02).astype(np.uint8)
+    obs = np.argwhere(occ)[:, ::-1]                     # (x, y, z)
+    z, y, x = np.meshgrid(np.arange(11), np.arange(13), np.arange(17), indexing="ij")
+    xyz = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)
+    for dmax in (1, 4, 30):
+        got = oracle.edt_points_list(obs, dmax, xyz).reshape(occ.shape)
+        assert np.array_equal(got, oracle.edt_bruteforce(occ, dmax))
+    # one obstacle far out on a huge extent: the closed form
+    o = np.array([[1_000_000, 5, 700_000]])
+    q = np.array([[1_000_003, 1, 700_000], [999_990, 5, 700_012], [0, 0, 0]])
+    assert list(oracle.edt_points_list(o, 20, q)) == [25, 244, 400]
+    assert list(oracle.edt_points_list(np.zeros((0, 3)), 9, q)) == [81, 81, 81]
