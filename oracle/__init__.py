@@ -16,6 +16,10 @@ Contents
       occupied and free voxels exchanged (the squared distance from an
       occupied voxel to the nearest free voxel of the extent, clamped to D),
       and the signed field that combines the two.
+  ray_voxels / integrate_scan
+      The occupancy integration of a range scan in front of the transform
+      (``scan_oracle.c``): the exact integer voxel walk of a ray and the
+      free / hit marking of one scan.
   clearance (module ``oracle.clearance``)
       The trajectory clearance cost built on the distance field (section III,
       Eq. 2 clearance term, squared hinge form), its analytic gradient and a
@@ -31,16 +35,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "edt_oracle.c")
+_SRC_SCAN = os.path.join(_HERE, "scan_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile edt_oracle.c with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    """Compile edt_oracle.c and scan_oracle.c with gcc (-O2, OpenMP) into
+    oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                        "-Wall", "-o", tmp, _SRC], check=True)
+                        "-Wall", "-o", tmp, _SRC, _SRC_SCAN], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +64,10 @@ def lib():
         L.oracle_edt_points.argtypes = [u8p, ci, ci, ci, ci, i32p, ctypes.c_int64, i32p]
         L.oracle_edt_separable.argtypes = [u8p, ci, ci, ci, ci, i32p]
         L.oracle_threads.argtypes = [ci]
+        L.oracle_ray_voxels.argtypes = [i32p, i32p, i32p, ctypes.c_int64]
+        L.oracle_ray_voxels.restype = ctypes.c_int64
+        L.oracle_integrate_scan.argtypes = [u8p, ci, ci, ci, i32p, i32p, u8p, ctypes.c_int64]
+        L.oracle_integrate_scan.restype = ctypes.c_int64
         for f in (L.oracle_edt_bruteforce, L.oracle_edt_points,
                   L.oracle_edt_separable, L.oracle_threads):
             f.restype = ci
@@ -145,6 +155,34 @@ def signed_field(occ: np.ndarray, dmax: int) -> np.ndarray:
     on them)."""
     occ, _, _, _ = _grid(occ)
     return np.where(occ != 0, -interior(occ, dmax), edt_separable(occ, dmax)).astype(np.int32)
+
+
+def ray_voxels(o, e) -> np.ndarray:
+    """Voxels (x, y, z) visited by the ray from voxel o to voxel e, in walk
+    order (scan_oracle.c states the traversal rule)."""
+    o = np.ascontiguousarray(o, dtype=np.int32)
+    e = np.ascontiguousarray(e, dtype=np.int32)
+    n = int(np.abs(e.astype(np.int64) - o).sum()) + 1
+    out = np.empty((n, 3), dtype=np.int32)
+    got = lib().oracle_ray_voxels(_i32(o), _i32(e), _i32(out), n)
+    assert got == n
+    return out
+
+
+def integrate_scan(occ: np.ndarray, origin, ends: np.ndarray, hits: np.ndarray):
+    """One scan integrated into a copy of occ (nz, ny, nx): visited voxels
+    free, hit end voxels occupied (hits win).  Returns (new occupancy, number
+    of rays skipped for an endpoint outside the grid)."""
+    occ, nx, ny, nz = _grid(occ)
+    occ = occ.copy()
+    o = np.ascontiguousarray(origin, dtype=np.int32).reshape(3)
+    e = np.ascontiguousarray(ends, dtype=np.int32).reshape(-1, 3)
+    h = np.ascontiguousarray(hits, dtype=np.uint8).reshape(-1)
+    assert len(e) == len(h)
+    sk = lib().oracle_integrate_scan(_u8(occ), nx, ny, nz, _i32(o), _i32(e), _u8(h), len(e))
+    if sk < 0:
+        raise ValueError("oracle_integrate_scan: bad arguments")
+    return occ, int(sk)
 
 
 def threads(n: int = 0) -> int:
