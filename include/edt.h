@@ -129,6 +129,28 @@ edt_status edt_global(edt_ctx* ctx, const edt_map* map, void* stream);
 edt_status edt_update(edt_ctx* ctx, const int32_t* d_xyz, const uint8_t* d_state,
                       int64_t n, void* stream);
 
+/* Occupancy integration of one range scan followed by the incremental
+ * transform: the mapping step in front of the transform in the paper's
+ * online pipeline (section V-B builds its dataset maps from LIDAR scans this
+ * way).  d_origin: int32[3] sensor voxel; d_ends: int32[n][3] end voxels of
+ * the rays; d_hits: uint8[n], nonzero = the ray ended on a return (its end
+ * voxel is an obstacle).  A ray visits its origin voxel and then every voxel
+ * that the segment between the two voxel centres enters through a face: the
+ * i-th crossing on axis a lies at segment parameter (2i + 1) / (2|d_a|),
+ * d = end - origin, and crossings at equal parameters are taken in the order
+ * x, y, z (an exact integer form of the Amanatides-Woo voxel walk).  Every
+ * visited voxel becomes free except a hit's end voxel, which becomes
+ * occupied; a hit wins over any ray passing through the same voxel.  The
+ * resulting changes then go through edt_update, so afterwards s equals
+ * edt_global of the new occupancy.  n > max_changes: EDT_ERR_CAPACITY with
+ * nothing enqueued.  Rays with the origin or end outside the extent are
+ * skipped and set EDT_ERR_RANGE in the device error word.  If more than
+ * max_changes - n voxels would be freed, the excess is dropped (the field
+ * still matches the occupancy) and the error word becomes EDT_ERR_CAPACITY.
+ * Shares the update's scratch: not to be overlapped with edt_update. */
+edt_status edt_integrate_scan(edt_ctx* ctx, const int32_t* d_origin, const int32_t* d_ends,
+                              const uint8_t* d_hits, int64_t n, void* stream);
+
 /* Compaction: rebuilds the block pool from the current occupancy and
  * recomputes s (the global transform of the current map).  Updates only add
  * blocks; blocks whose obstacles have all been removed stay in the pool.

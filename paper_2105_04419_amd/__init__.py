@@ -91,6 +91,7 @@ def lib():
         "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_query_nearest": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_compact": ([vp, vp], ctypes.c_int),
+        "edt_integrate_scan": ([vp, vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_interior": ([vp, vp], ctypes.c_int),
         "edt_query_signed": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_read_signed_dense": ([vp, vp, vp], ctypes.c_int),
@@ -208,6 +209,22 @@ class Field:
         _check("edt_update", lib().edt_update(self._ctx, _ptr(xyz), _ptr(state), n,
                                               _stream(stream)))
         self._keep = (xyz, state)
+        return self
+
+    def integrate_scan(self, origin: torch.Tensor, ends: torch.Tensor, hits: torch.Tensor,
+                       stream=None):
+        """Integrate one range scan (sensor voxel origin int32 (3,), ray end
+        voxels int32 (n, 3), hits uint8 (n,)) into the occupancy and update
+        the field incrementally."""
+        n = int(ends.shape[0])
+        if n == 0:
+            return self
+        origin = _dev_tensor(origin, torch.int32, (3,))
+        ends = _dev_tensor(ends, torch.int32, (n, 3))
+        hits = _dev_tensor(hits, torch.uint8, (n,))
+        _check("edt_integrate_scan", lib().edt_integrate_scan(self._ctx, _ptr(origin), _ptr(ends),
+                                                              _ptr(hits), n, _stream(stream)))
+        self._keep = (origin, ends, hits)
         return self
 
     def compact(self, stream=None):

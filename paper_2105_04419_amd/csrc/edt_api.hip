@@ -31,6 +31,9 @@ struct edt_ctx {
     int64_t ucap;       // update hash capacity
     int64_t stats_host[C_N];
     bool interior_valid;   // edt_interior ran after the last global / update
+    int32_t* scan_xyz;     // change list built by edt_integrate_scan
+    uint8_t* scan_state;
+    int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length
 };
 
 namespace {
@@ -50,7 +53,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -88,7 +91,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4,
-        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024};
+        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -298,6 +301,9 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     g.ilist = (int32_t*)(b + L.off[O_ILIST]);
     g.ic1 = (uint16_t*)(b + L.off[O_IC1]);
     g.ic2 = (uint16_t*)(b + L.off[O_IC2]);
+    c->scan_xyz = (int32_t*)(b + L.off[O_SCANXYZ]);
+    c->scan_state = (uint8_t*)(b + L.off[O_SCANST]);
+    c->scan_cnt = (int32_t*)(b + L.off[O_SCANCNT]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -461,22 +467,19 @@ edt_status edt_compact(edt_ctx* c, void* stream) {
     return run_passes_global(c, st);
 }
 
-edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, int64_t n,
-                      void* stream) {
-    if (!c || n < 0) return EDT_ERR_ARG;
-    if (n == 0) return EDT_OK;
-    if (!d_xyz || !d_state) return EDT_ERR_ARG;
-    if (n > c->g.max_changes) return EDT_ERR_CAPACITY;
+// The incremental transform over n change entries; n_dev, when given, holds
+// the entry count on the device and n is then only its upper bound (grids).
+static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state,
+                             int64_t n, const int32_t* n_dev, hipStream_t st) {
     c->interior_valid = false;
     Grid& g = c->g;
-    hipStream_t st = S(stream);
     const int mb = g.max_blocks;
     const int tn = grid_for(n, 256, 4096);
     const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
     hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(64), 0, st, g);
-    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n);
-    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
-    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n);
+    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev);
+    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev);
+    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev);
     hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
     hipLaunchKernelGGL(k_seed_box, dim3(grid_for(n, 1, 4096)), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_upd_mark, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
@@ -491,9 +494,39 @@ edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, 
     launch_pass(c, gu, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
     launch_pass(c, gu, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
     hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,
-                       g, n);
+                       g, n, n_dev);
     LAUNCH_CHECK();
     return EDT_OK;
+}
+
+edt_status edt_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_state, int64_t n,
+                      void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (n == 0) return EDT_OK;
+    if (!d_xyz || !d_state) return EDT_ERR_ARG;
+    if (n > c->g.max_changes) return EDT_ERR_CAPACITY;
+    return run_update(c, d_xyz, d_state, n, nullptr, S(stream));
+}
+
+edt_status edt_integrate_scan(edt_ctx* c, const int32_t* d_origin, const int32_t* d_ends,
+                              const uint8_t* d_hits, int64_t n, void* stream) {
+    if (!c || n < 0) return EDT_ERR_ARG;
+    if (n == 0) return EDT_OK;
+    if (!d_origin || !d_ends || !d_hits) return EDT_ERR_ARG;
+    const Grid& g = c->g;
+    const int64_t mc = g.max_changes;
+    if (n > mc) return EDT_ERR_CAPACITY;
+    hipStream_t st = S(stream);
+    // list: free entries first (capacity mc - n), then one entry per hit
+    const int64_t cap = mc - n;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->scan_cnt, (int64_t)3, 0);
+    hipLaunchKernelGGL(k_scan_clear, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st, g, d_origin,
+                       d_ends, d_hits, n, c->scan_cnt, c->scan_xyz, c->scan_state, cap);
+    hipLaunchKernelGGL(k_scan_hits, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, d_origin,
+                       d_ends, d_hits, n, c->scan_cnt, c->scan_xyz, c->scan_state, cap);
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, c->scan_cnt, cap);
+    LAUNCH_CHECK();
+    return run_update(c, c->scan_xyz, c->scan_state, mc, c->scan_cnt + 2, st);
 }
 
 edt_status edt_query(edt_ctx* c, const int32_t* d_xyz, int64_t n, int32_t* d_out, void* stream) {

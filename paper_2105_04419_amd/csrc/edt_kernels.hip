@@ -1311,7 +1311,9 @@ __global__ void k_upd_begin(Grid g) {
 
 // Range check (any entry outside the extent cancels the whole call) and
 // last-entry-wins dedupe through a voxel-keyed hash (value = max entry index).
-__global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n) {
+__global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n0,
+                             const int32_t* n_dev) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
@@ -1371,8 +1373,9 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
 // New blocks for voxels that become occupied (initialised to background by
 // the claiming wave).
 __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n) {
+                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev) {
     if (g.cnt[C_ABORT]) return;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     const int lane = __lane_id();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1395,8 +1398,9 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
 // Apply the winning entries: flip occupancy bits, record the changed voxels
 // per block (the wave centres) and list the blocks that hold them.
 __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n) {
+                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev) {
     if (g.cnt[C_ABORT]) return;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         bool add = false, rem = false, first_seed = false, new_dil = false;
@@ -1616,7 +1620,8 @@ __global__ void k_upd_mark(Grid g) {
 }
 
 // Clear per-update state: dedupe table entries, change masks and flags.
-__global__ void k_upd_cleanup(Grid g, int64_t n) {
+__global__ void k_upd_cleanup(Grid g, int64_t n0, const int32_t* n_dev) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i < n; i += stride) {
@@ -1638,6 +1643,132 @@ __global__ void k_upd_cleanup(Grid g, int64_t n) {
     for (int64_t i = tid; i < nd; i += stride) atomicAnd(&g.flags[g.list_dirty[i]], clear);
     const int64_t ny = g.cnt[C_NYS];
     for (int64_t i = tid; i < ny; i += stride) atomicAnd(&g.flags[g.list_ys[i]], clear);
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy integration of a range scan: rays from the sensor voxel o to end
+// voxels e.  A ray visits o and every voxel the segment between the two voxel
+// centres enters through a face; the i-th face crossing on axis a lies at
+// segment parameter (2i + 1) / (2 |d_a|), d = e - o, and crossings at equal
+// parameters are taken in the order x, y, z.  Visited voxels become free, the
+// end voxel of a ray with a return becomes occupied, and hits win.
+// ---------------------------------------------------------------------------
+
+// Voxel entered at crossing j of the ray (crossings numbered per axis: the
+// |dx| crossings on x first, then y, then z).  On every axis b the voxel has
+// moved by the number of b-crossings up to it: all strictly earlier ones, and
+// those at the same parameter when b comes before the crossing's axis (its
+// own axis counts the crossing itself).
+__device__ inline void ray_crossing_voxel(const int o[3], const int d[3], const int ad[3],
+                                          int64_t j, int v[3]) {
+    int a = 0;
+    while (a < 2 && j >= ad[a]) { j -= ad[a]; ++a; }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        int64_t c;
+        if (b == a) {
+            c = j + 1;
+        } else if (ad[b] == 0) {
+            c = 0;
+        } else {
+            // crossing i' of axis b is earlier iff (2i' + 1) |d_a| < (2j + 1) |d_b|
+            const int64_t P = (2 * j + 1) * (int64_t)ad[b], Q = ad[a];
+            c = b < a ? (P / Q + 1) / 2           // (2i' + 1) Q <= P
+                      : ((P + Q - 1) / Q) / 2;    // (2i' + 1) Q <  P
+            if (c > ad[b]) c = ad[b];
+        }
+        v[b] = o[b] + (int)(d[b] < 0 ? -c : c);
+    }
+}
+
+__device__ inline bool in_extent(const Grid& g, const int v[3]) {
+    return v[0] >= 0 && v[1] >= 0 && v[2] >= 0 && v[0] < g.nx && v[1] < g.ny && v[2] < g.nz;
+}
+
+// Change entries "free" for the voxels the rays visit that are occupied now
+// (the end voxel of a hit excepted).  One wave per ray, one visited voxel per
+// lane; entries go to the list front through cnt[0] (capacity cap).
+__global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __restrict__ origin,
+                                                   const int32_t* __restrict__ ends,
+                                                   const uint8_t* __restrict__ hits, int64_t n,
+                                                   int32_t* cnt, int32_t* lxyz, uint8_t* lst,
+                                                   int64_t cap) {
+    const int lane = threadIdx.x;
+    const int o[3] = {origin[0], origin[1], origin[2]};
+    const bool o_in = in_extent(g, o);
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const int e[3] = {ends[3 * r], ends[3 * r + 1], ends[3 * r + 2]};
+        if (!o_in || !in_extent(g, e)) {
+            if (lane == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+            continue;
+        }
+        const bool hit = hits[r] != 0;
+        const int d[3] = {e[0] - o[0], e[1] - o[1], e[2] - o[2]};
+        const int ad[3] = {abs(d[0]), abs(d[1]), abs(d[2])};
+        const int64_t L = (int64_t)ad[0] + ad[1] + ad[2];
+        for (int64_t k0 = 0; k0 <= L; k0 += 64) {
+            const int64_t k = k0 + lane;    // 0: the sensor voxel, k >= 1: crossing k - 1
+            bool emit = false;
+            int v[3] = {o[0], o[1], o[2]};
+            if (k <= L) {
+                if (k > 0) ray_crossing_voxel(o, d, ad, k - 1, v);
+                const bool at_end = v[0] == e[0] && v[1] == e[1] && v[2] == e[2];
+                if (!(hit && at_end)) {
+                    const int32_t slot = find_block(g, v[0] >> 3, v[1] >> 3, v[2] >> 3);
+                    if (slot >= 0) {
+                        const int b = (v[0] & 7) + 8 * (v[1] & 7) + 64 * (v[2] & 7);
+                        emit = (g.occ[(int64_t)slot * 16 + (b >> 5)] >> (b & 31)) & 1u;
+                    }
+                }
+            }
+            const int idx = wave_append(emit, cnt);
+            if (emit) {
+                if (idx < cap) {
+                    lxyz[3 * (int64_t)idx] = v[0];
+                    lxyz[3 * (int64_t)idx + 1] = v[1];
+                    lxyz[3 * (int64_t)idx + 2] = v[2];
+                    lst[idx] = 0;
+                } else {
+                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                }
+            }
+        }
+    }
+}
+
+// Change entries "occupied" for every hit end voxel, after all free entries
+// (the update takes the last entry of a voxel, so hits win).  cnt[1] counts
+// them; cnt[2] receives the list length.
+__global__ void k_scan_hits(Grid g, const int32_t* __restrict__ origin,
+                            const int32_t* __restrict__ ends, const uint8_t* __restrict__ hits,
+                            int64_t n, int32_t* cnt, int32_t* lxyz, uint8_t* lst, int64_t cap) {
+    const int o[3] = {origin[0], origin[1], origin[2]};
+    const bool o_in = in_extent(g, o);
+    const int64_t base = cnt[0] < cap ? cnt[0] : cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r0 = blockIdx.x * (int64_t)blockDim.x; r0 < n; r0 += stride) {
+        const int64_t r = r0 + threadIdx.x;
+        int e[3] = {0, 0, 0};
+        bool emit = false;
+        if (r < n) {
+            e[0] = ends[3 * r];
+            e[1] = ends[3 * r + 1];
+            e[2] = ends[3 * r + 2];
+            emit = hits[r] != 0 && o_in && in_extent(g, e);
+        }
+        const int idx = wave_append(emit, cnt + 1);
+        if (emit) {
+            const int64_t p = base + idx;
+            lxyz[3 * p] = e[0];
+            lxyz[3 * p + 1] = e[1];
+            lxyz[3 * p + 2] = e[2];
+            lst[p] = 1;
+        }
+    }
+}
+
+__global__ void k_scan_total(int32_t* cnt, int64_t cap) {
+    cnt[2] = (int32_t)((cnt[0] < cap ? cnt[0] : cap) + cnt[1]);
 }
 
 // ---------------------------------------------------------------------------

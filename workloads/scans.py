@@ -29,9 +29,11 @@ def ray_directions(n_elev=16, n_azim=1024, elev_deg=15.0):
     return d.reshape(-1, 3)
 
 
-def cast_rays(world: np.ndarray, origin, dirs: np.ndarray, max_range: float):
+def cast_rays(world: np.ndarray, origin, dirs: np.ndarray, max_range: float,
+              ends: bool = False):
     """Voxel traversal of all rays at once.  Returns (traversed linear indices,
-    hit linear indices), both possibly with repeats."""
+    hit linear indices), both possibly with repeats; with ends=True also each
+    ray's last voxel (x, y, z), int32[n, 3], and whether it ended on a hit."""
     nz, ny, nx = world.shape
     flat = world.reshape(-1)
     n = len(dirs)
@@ -46,6 +48,8 @@ def cast_rays(world: np.ndarray, origin, dirs: np.ndarray, max_range: float):
     ext = np.array([nx, ny, nz])
     trav, hits = [], []
     idx = np.arange(n)
+    last = vox.copy()
+    hit_ray = np.zeros(n, dtype=bool)
     while alive.any():
         a = idx[alive]
         v = vox[a]
@@ -55,8 +59,10 @@ def cast_rays(world: np.ndarray, origin, dirs: np.ndarray, max_range: float):
         if len(a) == 0:
             break
         lin = v[:, 0] + nx * (v[:, 1] + ny * v[:, 2])
+        last[a] = v
         occ = flat[lin] != 0
         hits.append(lin[occ])
+        hit_ray[a[occ]] = True
         alive[a[occ]] = False
         a, lin = a[~occ], lin[~occ]
         trav.append(lin)
@@ -67,6 +73,8 @@ def cast_rays(world: np.ndarray, origin, dirs: np.ndarray, max_range: float):
         tmax[a, ax] += inv[a, ax]
         alive[a[t_enter > max_range]] = False
     cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0, np.int64)
+    if ends:
+        return cat(trav), cat(hits), last.astype(np.int32), hit_ray.astype(np.uint8)
     return cat(trav), cat(hits)
 
 
@@ -98,12 +106,19 @@ class ScanSim:
         p = np.round(self.path[k]).astype(np.int64)
         return np.clip(p, 0, [nx - 1, ny - 1, nz - 1])
 
-    def step(self):
-        """Advance one scan.  Returns (xyz int32[n, 3], state uint8[n], pose)."""
+    def rays(self):
+        """Advance one scan of the world only and return the rays as a sensor
+        reports them: (pose int32[3], end voxels int32[n, 3], hits uint8[n]).
+        The map is left to the caller (occupancy integration)."""
         t = self.t
         self.t += 1
         rng = np.random.default_rng([self.seed, t])
         pose = self.pose(t)
+        self._toggle(rng, pose)
+        _, _, last, hit = cast_rays(self.world, pose, self.dirs, self.max_range, ends=True)
+        return pose.astype(np.int32), last, hit
+
+    def _toggle(self, rng, pose):
         if self.toggle_scope == "global":
             cand = self.walls
         else:
@@ -114,6 +129,14 @@ class ScanSim:
             flip = rng.choice(cand, size=k, replace=False)
             w = self.world.reshape(-1)
             w[flip] ^= 1
+
+    def step(self):
+        """Advance one scan.  Returns (xyz int32[n, 3], state uint8[n], pose)."""
+        t = self.t
+        self.t += 1
+        rng = np.random.default_rng([self.seed, t])
+        pose = self.pose(t)
+        self._toggle(rng, pose)
         trav, hits = cast_rays(self.world, pose, self.dirs, self.max_range)
         touched = np.unique(np.concatenate([trav, hits]))
         m = self.map.reshape(-1)
