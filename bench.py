@@ -18,7 +18,10 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
   dense_small    the 64x64x32 boxes map (d_max 20), microseconds per
                  global transform;
   interior       interior distances (edt_interior) of the tunnel map's
-                 occupied voxels, the inside half of the signed field.
+                 occupied voxels, the inside half of the signed field;
+  integrate      the same scans given as rays (sensor voxel, end voxels,
+                 returns): occupancy integration on the GPU plus the
+                 incremental transform, p50 / p99 per scan.
 """
 from __future__ import annotations
 
@@ -286,6 +289,55 @@ def bench_incremental(g, args, torch, np):
     }
 
 
+def bench_integrate(g, args, torch, np):
+    """Occupancy integration of the scans' rays on the GPU followed by the
+    incremental transform (edt_integrate_scan), per scan."""
+    import workloads
+    from workloads.scans import ScanSim, tunnel_path
+    from paper_2105_04419_amd import Field
+    n_scans = args.scans
+    cache = os.path.join(workloads.cache_dir(), f"rays_tunnel_s{args.seed}_{n_scans}.npz")
+    if os.path.exists(cache):
+        z = np.load(cache)
+        scans = [(z[f"p{i}"], z[f"e{i}"], z[f"h{i}"]) for i in range(n_scans)]
+    else:
+        sim = ScanSim(g["occ"], tunnel_path(args.seed), seed=args.seed)
+        scans = [sim.rays() for _ in range(n_scans)]
+        np.savez(cache + ".tmp.npz", **{f"p{i}": p for i, (p, _, _) in enumerate(scans)},
+                 **{f"e{i}": e for i, (_, e, _) in enumerate(scans)},
+                 **{f"h{i}": h for i, (_, _, h) in enumerate(scans)})
+        os.replace(cache + ".tmp.npz", cache)
+    nz, ny, nx = g["occ"].shape
+    f = Field((nx, ny, nz), args.dmax)
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    dev = [tuple(torch.from_numpy(a).cuda() for a in sc) for sc in scans]
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dev_ms, changed = [], []
+    for i, (p, e, h) in enumerate(dev):
+        e0.record()
+        f.integrate_scan(p, e, h)
+        e1.record()
+        e1.synchronize()
+        if i >= args.scan_warmup:
+            dev_ms.append(e0.elapsed_time(e1))
+            changed.append(f.stats()["changed"])
+    assert f.error() == 0
+    h2 = Field(f.shape, args.dmax)
+    h2.global_(f.occupancy())
+    same = bool(torch.equal(h2.dense(), f.dense()))
+    return {
+        "workload": f"tunnel map, {len(scans[0][1])} rays per scan (16 x 1024, range 150), "
+                    f"d_max {args.dmax}",
+        "scans": len(dev_ms),
+        "p50_ms": round(pct(dev_ms, 50), 4),
+        "p99_ms": round(pct(dev_ms, 99), 4),
+        "changed_voxels_mean": round(float(np.mean(changed)), 1),
+        "integrated_equals_global": same,
+    }
+
+
 def bench_clearance(args, torch, np):
     import workloads
     from paper_2105_04419_amd import ClearanceCost, Field
@@ -453,6 +505,8 @@ def main():
     if not args.no_extra:
         log(f"[bench] incremental: {args.scans} scans")
         out["incremental"] = bench_incremental(g, args, torch, np)
+        log(f"[bench] scan integration + incremental: {args.scans} scans")
+        out["integrate"] = bench_integrate(g, args, torch, np)
         log("[bench] clearance 4096 x 64")
         out["clearance"] = bench_clearance(args, torch, np)
         log("[bench] batched: 64 dense maps, autotuned fused launch vs per-map launches")
