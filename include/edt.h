@@ -290,6 +290,25 @@ edt_status edt_batch_run(edt_batch* batch, const uint8_t* d_occ, int32_t* d_out,
 edt_status edt_batch_destroy(edt_batch* batch);
 
 /* ------------------------------------------------------------------------ */
+/* Full (uncapped) transform of a dense grid: the distance field with which
+ * the paper runs its dataset benchmarks, d_max = infinity (section V-B), and
+ * radii beyond the 255 of the sparse field.  Same definition as Eq. 1, with
+ *     s(x) = min over occupied y of |x - y|^2      (d_max = 0: no limit)
+ *     s(x) = min(d_max^2, that)                    (1 <= d_max <= 46340)
+ * and EDT_DENSE_INF for every voxel of a grid without obstacles when
+ * d_max = 0.  d_occ: uint8[nz][ny][nx] (nonzero = occupied); d_out:
+ * int32[nz][ny][nx], written in place by the three passes.  The extent must
+ * satisfy nx^2 + ny^2 + nz^2 < 2^31 (every squared distance fits in int32),
+ * else EDT_ERR_ARG.  The caller's workspace (8-byte aligned,
+ * edt_dense_workspace_bytes) holds the per-column parabola envelopes.
+ * Global only: there is no incremental form of the uncapped transform. */
+#define EDT_DENSE_INF 0x7fffffff
+int64_t edt_dense_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
+                            const uint8_t* d_occ, int32_t* d_out, void* d_ws, int64_t ws_bytes,
+                            void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Clearance cost on a dense field (paper section III, Eq. 2, clearance
  * term, in the squared-hinge form  c(p) = max(0, margin - d(p))^2).
  *   d_s        int32[nz][ny][nx] squared voxel distances (e.g. from

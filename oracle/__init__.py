@@ -11,6 +11,8 @@ Contents
       plain C in ``edt_oracle.c`` and called through ctypes.
   edt_points_list
       The same definition for an obstacle list (sparse maps on huge extents).
+  edt_uncapped
+      The definition without a radius (the full transform).
   interior / signed_field
       The inside half of a signed distance field: the same definition with
       occupied and free voxels exchanged (the squared distance from an
@@ -139,6 +141,22 @@ def edt_points_list(obstacles: np.ndarray, dmax: int, xyz: np.ndarray) -> np.nda
         d2 = ((q[i:i + step, None, :] - obs[None, :, :]) ** 2).sum(-1).min(1)
         out[i:i + step] = np.minimum(d2, D)
     return out.astype(np.int32)
+
+
+INF = 0x7FFFFFFF
+
+
+def edt_uncapped(occ: np.ndarray) -> np.ndarray:
+    """Eq. 1 with no radius: the exact squared distance to the nearest
+    obstacle (INF on a grid without obstacles).  A radius beyond the grid's
+    diagonal never clamps, so this is edt_separable at such a radius."""
+    occ, nx, ny, nz = _grid(occ)
+    if not occ.any():
+        return np.full(occ.shape, INF, dtype=np.int32)
+    r = int(np.ceil(np.sqrt(float(nx) ** 2 + float(ny) ** 2 + float(nz) ** 2))) + 1
+    if r > 4095:
+        raise ValueError("edt_uncapped: grid too large for the windowed oracle")
+    return edt_separable(occ, r)
 
 
 def interior(occ: np.ndarray, dmax: int) -> np.ndarray:

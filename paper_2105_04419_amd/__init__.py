@@ -107,6 +107,8 @@ def lib():
                               ctypes.POINTER(vp)], ctypes.c_int),
         "edt_batch_run": ([vp, vp, vp, i32, ctypes.POINTER(EdtTune), vp], ctypes.c_int),
         "edt_batch_destroy": ([vp], ctypes.c_int),
+        "edt_dense_workspace_bytes": ([i32, i32, i32], i64),
+        "edt_dense_global": ([i32, i32, i32, i32, vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_clearance_fwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp], ctypes.c_int),
         "edt_clearance_bwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp, vp],
                               ctypes.c_int),
@@ -315,6 +317,34 @@ class Field:
     def error(self, stream=None) -> int:
         """Device error word (0 or a negative status); reading clears it."""
         return int(lib().edt_get_error(self._ctx, _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# full (uncapped) transform of a dense grid
+# ---------------------------------------------------------------------------
+DENSE_INF = 0x7fffffff
+
+
+def dense_global(occ: torch.Tensor, d_max: int = 0, out: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Exact squared EDT of a dense grid occ (nz, ny, nx) uint8 with no
+    radius (d_max = 0; voxels of a grid without obstacles get DENSE_INF) or
+    clamped to d_max^2.  Returns int32 (nz, ny, nx)."""
+    nz, ny, nx = (int(v) for v in occ.shape)
+    occ = _dev_tensor(occ, torch.uint8, (nz, ny, nx))
+    L = lib()
+    nbytes = int(L.edt_dense_workspace_bytes(nx, ny, nz))
+    if nbytes < 0:
+        raise EdtError("edt_dense_workspace_bytes", nbytes)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.int32, device=occ.device)
+    out = _dev_tensor(out, torch.int32, (nz, ny, nx))
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=occ.device)
+    _check("edt_dense_global", L.edt_dense_global(nx, ny, nz, int(d_max), _ptr(occ), _ptr(out),
+                                                  _ptr(workspace), workspace.numel(),
+                                                  _stream(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libedt.so")
-SOURCES = ["edt_api.hip", "edt_clearance.hip", "edt_batch.hip"]
+SOURCES = ["edt_api.hip", "edt_clearance.hip", "edt_batch.hip", "edt_dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EDT_OFFLOAD_ARCH", "gfx950")
 

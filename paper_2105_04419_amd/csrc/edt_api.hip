@@ -33,7 +33,10 @@ struct edt_ctx {
     bool interior_valid;   // edt_interior ran after the last global / update
     int32_t* scan_xyz;     // change list built by edt_integrate_scan
     uint8_t* scan_state;
-    int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length
+    int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length,
+                           // [3] finished workgroups of the hit kernel, [4..5] int64
+                           // number of visited-voxel slots
+    int64_t* scan_off;     // per ray: first slot in the flat enumeration
 };
 
 namespace {
@@ -53,7 +56,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_SCANOFF, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -91,7 +94,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4,
-        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256};
+        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256, mc * 8};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -304,6 +307,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     c->scan_xyz = (int32_t*)(b + L.off[O_SCANXYZ]);
     c->scan_state = (uint8_t*)(b + L.off[O_SCANST]);
     c->scan_cnt = (int32_t*)(b + L.off[O_SCANCNT]);
+    c->scan_off = (int64_t*)(b + L.off[O_SCANOFF]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -449,7 +453,7 @@ edt_status edt_compact(edt_ctx* c, void* stream) {
     int32_t* lxyz = (int32_t*)g.g1;
     uint8_t* lbits = (uint8_t*)g.g1 + ((12 * mb + 255) & ~(int64_t)255);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, count, (int64_t)1, 0);
-    hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb, 4, 16384)), dim3(64), 0, st, g, count,
+    hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb, 256, 16384)), dim3(64), 0, st, g, count,
                        lxyz, (uint32_t*)lbits);
     mark(c, 0, st);
     hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
@@ -474,7 +478,9 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     c->interior_valid = false;
     Grid& g = c->g;
     const int mb = g.max_blocks;
-    const int tn = grid_for(n, 256, 4096);
+    // every update kernel loops grid-stride; a device-side count only bounds
+    // n, so its grids stay moderate
+    const int tn = grid_for(n_dev && n > 65536 ? 65536 : n, 256, 4096);
     const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
     hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev);
@@ -519,12 +525,15 @@ edt_status edt_integrate_scan(edt_ctx* c, const int32_t* d_origin, const int32_t
     hipStream_t st = S(stream);
     // list: free entries first (capacity mc - n), then one entry per hit
     const int64_t cap = mc - n;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->scan_cnt, (int64_t)3, 0);
-    hipLaunchKernelGGL(k_scan_clear, dim3(grid_for(n, 1, 16384)), dim3(64), 0, st, g, d_origin,
-                       d_ends, d_hits, n, c->scan_cnt, c->scan_xyz, c->scan_state, cap);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->scan_cnt, (int64_t)4, 0);
+    int64_t* total = (int64_t*)(c->scan_cnt + 4);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, g, d_origin, d_ends, n,
+                       c->scan_off, total);
+    hipLaunchKernelGGL(k_scan_clear, dim3(16384), dim3(64), 0, st, g, d_origin, d_ends, d_hits, n,
+                       (const int64_t*)c->scan_off, (const int64_t*)total, c->scan_cnt,
+                       c->scan_xyz, c->scan_state, cap);
     hipLaunchKernelGGL(k_scan_hits, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, d_origin,
                        d_ends, d_hits, n, c->scan_cnt, c->scan_xyz, c->scan_state, cap);
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, c->scan_cnt, cap);
     LAUNCH_CHECK();
     return run_update(c, c->scan_xyz, c->scan_state, mc, c->scan_cnt + 2, st);
 }
@@ -556,7 +565,7 @@ edt_status edt_interior(edt_ctx* c, void* stream) {
     if (g.max_int <= 0) return EDT_ERR_STATE;
     hipStream_t st = S(stream);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt + C_NINT, (int64_t)1, 0);
-    hipLaunchKernelGGL(k_int_list, dim3(grid_for(g.max_blocks, 4, 16384)), dim3(64), 0, st, g);
+    hipLaunchKernelGGL(k_int_list, dim3(grid_for(g.max_blocks, 256, 16384)), dim3(64), 0, st, g);
     const int grid = grid_for(g.max_int, 1, 16384);
     hipLaunchKernelGGL(k_int_x, dim3(grid), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_int_yz<1>, dim3(grid), dim3(64), 0, st, g);

@@ -1,0 +1,192 @@
+// edt_dense.hip -- uncapped (or arbitrarily capped) exact squared EDT of a
+// dense grid: the full distance transform, d_max = infinity, with which the
+// paper runs its dataset benchmarks (section V-B), and radii beyond the
+// 16-bit storage of the sparse field.
+//
+// s(x) = min over occupied y of |x - y|^2 (Eq. 1 without the limit), then
+// min(D, s) when a radius is given; voxels of a grid without any obstacle get
+// EDT_DENSE_INF.  Values are int32: the extent must satisfy
+// nx^2 + ny^2 + nz^2 < 2^31, so every squared distance fits.
+//
+// Three passes over the caller's int32 output array, in place:
+//   x   one wave per row, 64 voxels per step: a ballot of the occupancy
+//       bytes gives, per lane, the nearest obstacle at or left of it (and in
+//       a second sweep at or right of it), carried across steps;
+//   y,z one lane per column (64 consecutive x per wave, coalesced rows): the
+//       lower envelope of the parabolas q -> f(v) + (q - v)^2 of the column's
+//       finite values (Felzenszwalb and Huttenlocher's separable transform,
+//       the one the paper cites in section I), built left to right with
+//       parabola intersections compared exactly as int64 cross products,
+//       then read off left to right.  The envelope of every column lives in
+//       the workspace (one int2 (v, f) per voxel), entry k of column c at
+//       k * ncols + c.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "edt.h"
+
+namespace {
+
+constexpr int32_t DINF = 0x7fffffff;
+
+// Pass x.  Lanes take x = x0 + lane; left sweep writes the distance to the
+// nearest obstacle at or before x (or DINF) into out, the right sweep
+// combines it with the nearest at or after x and squares it.
+__global__ void __launch_bounds__(64) k_dense_x(int nx, int ny, int nz,
+                                                const uint8_t* __restrict__ occ, int32_t* out) {
+    const int lane = threadIdx.x;
+    const int64_t rows = (int64_t)ny * nz;
+    const unsigned long long below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);  // bits <= lane
+    const unsigned long long above = ~0ull << lane;                                   // bits >= lane
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const uint8_t* row = occ + r * nx;
+        int32_t* o = out + r * nx;
+        int64_t last = -(1ll << 40);     // position of the nearest obstacle so far
+        for (int x0 = 0; x0 < nx; x0 += 64) {
+            const int x = x0 + lane;
+            const bool b = x < nx && row[x] != 0;
+            const unsigned long long m = __ballot(b);
+            const unsigned long long mb = m & below;
+            const int64_t near = mb ? (int64_t)x0 + 63 - __clzll((long long)mb) : last;
+            if (x < nx) {
+                const int64_t d = x - near;
+                o[x] = d > (1ll << 30) ? DINF : (int32_t)d;
+            }
+            if (m) last = (int64_t)x0 + 63 - __clzll((long long)m);
+        }
+        int64_t next = 1ll << 40;
+        const int top = (nx - 1) & ~63;
+        for (int x0 = top; x0 >= 0; x0 -= 64) {
+            const int x = x0 + lane;
+            const bool b = x < nx && row[x] != 0;
+            const unsigned long long m = __ballot(b);
+            const unsigned long long ma = m & above;
+            const int64_t near = ma ? (int64_t)x0 + __ffsll((long long)ma) - 1 : next;
+            if (x < nx) {
+                const int32_t dl = o[x];
+                const int64_t dr = near - x;
+                const int64_t d = dr < (int64_t)dl ? dr : (int64_t)dl;
+                o[x] = d > (1ll << 30) ? DINF : (int32_t)(d * d);
+            }
+            if (m) next = (int64_t)x0 + __ffsll((long long)m) - 1;
+        }
+    }
+}
+
+// Passes y (AXIS 1) and z (AXIS 2), in place on out, with the envelope in
+// env.  Column (x, w): x fastest within a wave; w = z for y, y for z.
+template <int AXIS>
+__global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_t* out, int2* env,
+                                                  int32_t cap) {
+    const int lane = threadIdx.x;
+    const int n = AXIS == 1 ? ny : nz;                 // column length
+    const int nw = AXIS == 1 ? nz : ny;
+    const int64_t stride = AXIS == 1 ? (int64_t)nx : (int64_t)nx * ny;
+    const int nxc = (nx + 63) / 64;
+    const int64_t ncols = (int64_t)nx * nw;
+    const int64_t waves = (int64_t)nxc * nw;
+    for (int64_t wv = blockIdx.x; wv < waves; wv += gridDim.x) {
+        const int x = (int)(wv % nxc) * 64 + lane;
+        const int w = (int)(wv / nxc);
+        if (x >= nx) continue;
+        const int64_t base = AXIS == 1 ? (int64_t)x + (int64_t)nx * ny * w
+                                       : (int64_t)x + (int64_t)nx * w;
+        const int64_t col = (int64_t)x + (int64_t)nx * w;   // column index among ncols
+        int2* E = env + col;                                 // entry k at E[k * ncols]
+        // build the lower envelope; (v1, f1) is the top, (v0, f0) below it
+        int k = -1;
+        int v0 = 0, v1 = 0;
+        int64_t F0 = 0, F1 = 0;                              // f + v^2
+        int32_t f1 = 0;
+        for (int q = 0; q < n; ++q) {
+            const int32_t f = out[base + stride * q];
+            if (f == DINF) continue;
+            const int64_t Fq = (int64_t)f + (int64_t)q * q;
+            // pop while the top parabola's interval is empty: the new one
+            // overtakes it no later than the top overtook the one below
+            while (k >= 1 && (Fq - F1) * (int64_t)(v1 - v0) <= (F1 - F0) * (int64_t)(q - v1)) {
+                --k;
+                v1 = v0;
+                F1 = F0;
+                if (k >= 1) {
+                    const int2 e = E[(int64_t)(k - 1) * ncols];
+                    v0 = e.x;
+                    F0 = (int64_t)e.y + (int64_t)e.x * e.x;
+                }
+            }
+            ++k;
+            E[(int64_t)k * ncols] = make_int2(q, f);
+            if (k >= 1) {
+                v0 = v1;
+                F0 = F1;
+            }
+            v1 = q;
+            F1 = Fq;
+            f1 = f;
+        }
+        (void)f1;
+        // read off: parabola j covers q while the next one is not yet lower
+        if (k < 0) {
+            for (int q = 0; q < n; ++q) out[base + stride * q] = cap;
+            continue;
+        }
+        int j = 0;
+        int2 cur = E[0];
+        int2 nxt = k >= 1 ? E[ncols] : cur;
+        for (int q = 0; q < n; ++q) {
+            // next parabola is at least as low at q: (F_next - F_cur) <= 2 q (v_next - v_cur)
+            while (j < k) {
+                const int64_t Fc = (int64_t)cur.y + (int64_t)cur.x * cur.x;
+                const int64_t Fn = (int64_t)nxt.y + (int64_t)nxt.x * nxt.x;
+                if (Fn - Fc > 2ll * q * (int64_t)(nxt.x - cur.x)) break;
+                ++j;
+                cur = nxt;
+                if (j < k) nxt = E[(int64_t)(j + 1) * ncols];
+            }
+            const int64_t d = (int64_t)(q - cur.x) * (q - cur.x) + cur.y;
+            out[base + stride * q] = d < (int64_t)cap ? (int32_t)d : cap;
+        }
+    }
+}
+
+inline int grid_of(int64_t work, int cap) {
+    return (int)(work < 1 ? 1 : (work > cap ? cap : work));
+}
+
+bool dense_ok(int32_t nx, int32_t ny, int32_t nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return false;
+    const int64_t d2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
+    return d2 < (int64_t)DINF;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t edt_dense_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
+    if (!dense_ok(nx, ny, nz)) return EDT_ERR_ARG;
+    return (int64_t)nx * ny * nz * (int64_t)sizeof(int2);
+}
+
+edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
+                            const uint8_t* d_occ, int32_t* d_out, void* d_ws, int64_t ws_bytes,
+                            void* stream) {
+    if (!dense_ok(nx, ny, nz) || d_max < 0 || d_max > 46340 || !d_occ || !d_out || !d_ws)
+        return EDT_ERR_ARG;
+    if (((uintptr_t)d_ws & 7) != 0) return EDT_ERR_ARG;
+    if (ws_bytes < edt_dense_workspace_bytes(nx, ny, nz)) return EDT_ERR_CAPACITY;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t cap = d_max > 0 ? d_max * d_max : DINF;
+    int2* env = (int2*)d_ws;
+    const int nxc = (nx + 63) / 64;
+    hipLaunchKernelGGL(k_dense_x, dim3(grid_of((int64_t)ny * nz, 65536)), dim3(64), 0, st, nx, ny,
+                       nz, d_occ, d_out);
+    hipLaunchKernelGGL(k_dense_col<1>, dim3(grid_of((int64_t)nxc * nz, 65536)), dim3(64), 0, st,
+                       nx, ny, nz, d_out, env, (int32_t)DINF);
+    hipLaunchKernelGGL(k_dense_col<2>, dim3(grid_of((int64_t)nxc * ny, 65536)), dim3(64), 0, st,
+                       nx, ny, nz, d_out, env, cap);
+    if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
+    return EDT_OK;
+}
+
+}  // extern "C"

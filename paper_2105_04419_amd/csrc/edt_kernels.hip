@@ -1673,8 +1673,19 @@ __device__ inline void ray_crossing_voxel(const int o[3], const int d[3], const 
         } else {
             // crossing i' of axis b is earlier iff (2i' + 1) |d_a| < (2j + 1) |d_b|
             const int64_t P = (2 * j + 1) * (int64_t)ad[b], Q = ad[a];
-            c = b < a ? (P / Q + 1) / 2           // (2i' + 1) Q <= P
-                      : ((P + Q - 1) / Q) / 2;    // (2i' + 1) Q <  P
+            // floor(P / Q) and ceil(P / Q), in 32 bits when P fits
+            int64_t fl, ce;
+            if (P < (1ll << 31)) {
+                const uint32_t p32 = (uint32_t)P, q32 = (uint32_t)Q;
+                const uint32_t f = p32 / q32;
+                fl = f;
+                ce = f + (f * q32 != p32 ? 1 : 0);
+            } else {
+                fl = P / Q;
+                ce = fl + (fl * Q != P ? 1 : 0);
+            }
+            c = b < a ? (fl + 1) / 2     // (2i' + 1) Q <= P
+                      : ce / 2;          // (2i' + 1) Q <  P
             if (c > ad[b]) c = ad[b];
         }
         v[b] = o[b] + (int)(d[b] < 0 ? -c : c);
@@ -1685,52 +1696,153 @@ __device__ inline bool in_extent(const Grid& g, const int v[3]) {
     return v[0] >= 0 && v[1] >= 0 && v[2] >= 0 && v[0] < g.nx && v[1] < g.ny && v[2] < g.nz;
 }
 
-// Change entries "free" for the voxels the rays visit that are occupied now
-// (the end voxel of a hit excepted).  One wave per ray, one visited voxel per
-// lane; entries go to the list front through cnt[0] (capacity cap).
+// Occupancy bit of voxel v (inside the extent) for U voxels at once: the
+// tile-hash probes, the slot-table reads and the occupancy reads of all U
+// are issued together (the first probe position almost always decides; a
+// collision falls back to the probing loop).
+template <int U>
+__device__ inline void occ_bits(const Grid& g, const int (*v)[3], const bool* want, bool* bit) {
+    unsigned long long key[U], got[U];
+    uint32_t h[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        key[u] = pack_key(v[u][0] >> 6, v[u][1] >> 6, v[u][2] >> 6);
+        h[u] = hash_of(key[u], g.tmask);
+        got[u] = want[u] ? g.tkeys[h[u]] : KEY_EMPTY;
+    }
+    int32_t slot[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int32_t t = -1;
+        if (want[u]) {
+            if (got[u] == key[u]) t = (int32_t)h[u];
+            else if (got[u] != KEY_EMPTY) t = hpos(g.tkeys, g.tmask, key[u]);
+        }
+        const int local = ((v[u][0] >> 3) & 7) + 8 * ((v[u][1] >> 3) & 7) + 64 * ((v[u][2] >> 3) & 7);
+        slot[u] = t >= 0 ? g.tslots[(int64_t)t * 512 + local] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = (v[u][0] & 7) + 8 * (v[u][1] & 7) + 64 * (v[u][2] & 7);
+        bit[u] = slot[u] >= 0 && ((g.occ[(int64_t)slot[u] * 16 + (b >> 5)] >> (b & 31)) & 1u);
+    }
+}
+
+// Slots of ray r in the flat enumeration of visited voxels: its origin and one
+// per crossing, or none when an endpoint lies outside the extent.
+__device__ inline int64_t ray_slots(const Grid& g, const int o[3], bool o_in,
+                                    const int32_t* ends, int64_t r) {
+    const int e[3] = {ends[3 * r], ends[3 * r + 1], ends[3 * r + 2]};
+    if (!o_in || !in_extent(g, e)) return 0;
+    return (int64_t)abs(e[0] - o[0]) + abs(e[1] - o[1]) + abs(e[2] - o[2]) + 1;
+}
+
+// Exclusive prefix sum of the rays' slot counts in one workgroup of 1024
+// threads: chunks of 1024 rays, one ray per thread, a shuffle scan per wave,
+// then the 16 wave totals, then the running carry.  off[r], and the total in
+// *total.  Rays with an endpoint outside the extent get no slots and set
+// EDT_ERR_RANGE.
+__global__ void __launch_bounds__(1024) k_scan_offsets(Grid g, const int32_t* __restrict__ origin,
+                                                       const int32_t* __restrict__ ends, int64_t n,
+                                                       int64_t* off, int64_t* total) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int o[3] = {origin[0], origin[1], origin[2]};
+    const bool o_in = in_extent(g, o);
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+        const int64_t r = c0 + t;
+        const int64_t k = r < n ? ray_slots(g, o, o_in, ends, r) : 0;
+        if (r < n && k == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+        int64_t incl = k;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int64_t before = carry;
+        for (int j = 0; j < w; ++j) before += wsum[j];
+        if (r < n) off[r] = before + incl - k;
+        __syncthreads();
+        if (t == 1023) carry = before + incl;
+        __syncthreads();
+    }
+    if (t == 0) *total = carry;
+}
+
+// Change entries "free" for the visited voxels that are occupied now (the
+// end voxel of a hit excepted).  Lanes take consecutive slots of the flat
+// enumeration, so short rays share a wave; each lane finds its ray by binary
+// search over the offsets.  Entries go to the list front through cnt[0]
+// (capacity cap).
 __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __restrict__ origin,
                                                    const int32_t* __restrict__ ends,
                                                    const uint8_t* __restrict__ hits, int64_t n,
-                                                   int32_t* cnt, int32_t* lxyz, uint8_t* lst,
-                                                   int64_t cap) {
+                                                   const int64_t* __restrict__ off,
+                                                   const int64_t* total_p, int32_t* cnt,
+                                                   int32_t* lxyz, uint8_t* lst, int64_t cap) {
     const int lane = threadIdx.x;
     const int o[3] = {origin[0], origin[1], origin[2]};
-    const bool o_in = in_extent(g, o);
-    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
-        const int e[3] = {ends[3 * r], ends[3 * r + 1], ends[3 * r + 2]};
-        if (!o_in || !in_extent(g, e)) {
-            if (lane == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
-            continue;
+    const int64_t total = *total_p;
+    for (int64_t base = 64 * (int64_t)blockIdx.x; base < total; base += 64 * (int64_t)gridDim.x) {
+        const int64_t f = base + lane;
+        // rb: the last ray whose first slot is at or before `base`, by a
+        // 64-way search of the whole wave (rays without slots share the next
+        // ray's offset and are passed over)
+        int64_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int64_t span = hi - lo + 1;
+            const int64_t stp = (span + 63) / 64;
+            const int64_t q = lo + (int64_t)lane * stp;
+            const bool le = q <= hi && off[q] <= base;
+            const unsigned long long m = __ballot(le);   // lane 0 always qualifies
+            const int top = 63 - __clzll((long long)m);
+            lo = lo + (int64_t)top * stp;
+            hi = lo + stp - 1 < hi ? lo + stp - 1 : hi;
+            if (stp == 1) break;
         }
-        const bool hit = hits[r] != 0;
-        const int d[3] = {e[0] - o[0], e[1] - o[1], e[2] - o[2]};
-        const int ad[3] = {abs(d[0]), abs(d[1]), abs(d[2])};
-        const int64_t L = (int64_t)ad[0] + ad[1] + ad[2];
-        for (int64_t k0 = 0; k0 <= L; k0 += 64) {
-            const int64_t k = k0 + lane;    // 0: the sensor voxel, k >= 1: crossing k - 1
-            bool emit = false;
-            int v[3] = {o[0], o[1], o[2]};
-            if (k <= L) {
-                if (k > 0) ray_crossing_voxel(o, d, ad, k - 1, v);
-                const bool at_end = v[0] == e[0] && v[1] == e[1] && v[2] == e[2];
-                if (!(hit && at_end)) {
-                    const int32_t slot = find_block(g, v[0] >> 3, v[1] >> 3, v[2] >> 3);
-                    if (slot >= 0) {
-                        const int b = (v[0] & 7) + 8 * (v[1] & 7) + 64 * (v[2] & 7);
-                        emit = (g.occ[(int64_t)slot * 16 + (b >> 5)] >> (b & 31)) & 1u;
-                    }
-                }
+        const int64_t rb = lo;
+        // each lane: the last ray in rb .. rb + 63 whose first slot is at or
+        // before f, by binary search over the 64 offsets held across lanes
+        const int64_t wj = rb + lane < n ? off[rb + lane] : INT64_MAX;
+        int j = 0;
+#pragma unroll
+        for (int stp = 32; stp > 0; stp >>= 1) {
+            const int64_t x = __shfl(wj, j + stp);
+            if (x <= f) j += stp;
+        }
+        int v[1][3] = {{o[0], o[1], o[2]}};
+        bool want[1] = {false}, bit[1];
+        if (f < total) {
+            int64_t r = rb + j;
+            // more than 63 rays without slots in between: continue linearly
+            while (r + 1 < n && off[r + 1] <= f) ++r;
+            lo = r;
+            const int64_t k = f - off[lo];     // 0: the sensor voxel, k >= 1: crossing k - 1
+            const int e[3] = {ends[3 * lo], ends[3 * lo + 1], ends[3 * lo + 2]};
+            if (k > 0) {
+                const int d[3] = {e[0] - o[0], e[1] - o[1], e[2] - o[2]};
+                const int ad[3] = {abs(d[0]), abs(d[1]), abs(d[2])};
+                ray_crossing_voxel(o, d, ad, k - 1, v[0]);
             }
-            const int idx = wave_append(emit, cnt);
-            if (emit) {
-                if (idx < cap) {
-                    lxyz[3 * (int64_t)idx] = v[0];
-                    lxyz[3 * (int64_t)idx + 1] = v[1];
-                    lxyz[3 * (int64_t)idx + 2] = v[2];
-                    lst[idx] = 0;
-                } else {
-                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
-                }
+            const bool at_end = v[0][0] == e[0] && v[0][1] == e[1] && v[0][2] == e[2];
+            want[0] = !(hits[lo] && at_end);
+        }
+        occ_bits<1>(g, v, want, bit);
+        const bool emit = want[0] && bit[0];
+        const int idx = wave_append(emit, cnt);
+        if (emit) {
+            if (idx < cap) {
+                lxyz[3 * (int64_t)idx] = v[0][0];
+                lxyz[3 * (int64_t)idx + 1] = v[0][1];
+                lxyz[3 * (int64_t)idx + 2] = v[0][2];
+                lst[idx] = 0;
+            } else {
+                set_error(g, -3 /* EDT_ERR_CAPACITY */);
             }
         }
     }
@@ -1738,7 +1850,7 @@ __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __rest
 
 // Change entries "occupied" for every hit end voxel, after all free entries
 // (the update takes the last entry of a voxel, so hits win).  cnt[1] counts
-// them; cnt[2] receives the list length.
+// them, cnt[3] the finished workgroups; cnt[2] receives the list length.
 __global__ void k_scan_hits(Grid g, const int32_t* __restrict__ origin,
                             const int32_t* __restrict__ ends, const uint8_t* __restrict__ hits,
                             int64_t n, int32_t* cnt, int32_t* lxyz, uint8_t* lst, int64_t cap) {
@@ -1765,40 +1877,86 @@ __global__ void k_scan_hits(Grid g, const int32_t* __restrict__ origin,
             lst[p] = 1;
         }
     }
+    // the last workgroup to finish writes the list length into cnt[2]
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(cnt + 3, 1) == (int)gridDim.x - 1)
+            cnt[2] = (int32_t)(base + atomicAdd(cnt + 1, 0));
+    }
 }
 
-__global__ void k_scan_total(int32_t* cnt, int64_t cap) {
-    cnt[2] = (int32_t)((cnt[0] < cap ? cnt[0] : cap) + cnt[1]);
+// Pool slots holding an obstacle, in chunks of 256 slots per wave: lane l
+// reads slots 4l .. 4l + 3 of the chunk whole (four 16-byte loads each, all
+// in flight together), the wave takes an exclusive prefix sum of the lanes'
+// counts, and one counter atomic per chunk reserves the list positions.
+// The occupancy words stay in w[t][0..3] for the caller.
+struct SlotChunk {
+    uint4 w[4][4];
+    uint32_t has;     // bit t: slot 4 lane + t holds an obstacle
+    int pos;          // first list position of this lane's slots
+    int total;        // obstacle slots in the chunk
+};
+
+__device__ inline void scan_chunk(const Grid& g, int64_t c0, int64_t n, int32_t* counter,
+                                  SlotChunk& c) {
+    const int lane = __lane_id();
+    c.has = 0u;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t slot = c0 + 4 * lane + t;
+        const uint4* p = (const uint4*)(g.occ + (slot < n ? slot : 0) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c.w[t][q] = slot < n ? p[q] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint32_t a = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a |= c.w[t][q].x | c.w[t][q].y | c.w[t][q].z | c.w[t][q].w;
+        c.has |= (a != 0u ? 1u : 0u) << t;
+    }
+    const int mine = __popc(c.has);
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    c.total = __shfl(incl, 63);
+    int base = 0;
+    if (lane == 63 && c.total > 0) base = atomicAdd(counter, c.total);
+    base = __shfl(base, 63);
+    c.pos = base + incl - mine;
 }
 
 // ---------------------------------------------------------------------------
 // Compaction: the blocks holding an obstacle (coordinates and occupancy
 // words) are copied into a list, from which a global transform rebuilds the
 // pool; blocks that no longer hold an obstacle and lie beyond R blocks of
-// every obstacle block drop out.  Four pool slots per wave, one occupancy
-// word per lane.
+// every obstacle block drop out.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_compact_gather(Grid g, int32_t* count, int32_t* xyz,
                                                        uint32_t* bits) {
     const int lane = threadIdx.x;
     const int64_t n0 = g.cnt[C_NBLK];
     const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
-    for (int64_t base = 4 * (int64_t)blockIdx.x; base < n; base += 4 * (int64_t)gridDim.x) {
-        const int64_t slot = base + (lane >> 4);
-        const uint32_t w = slot < n ? g.occ[slot * 16 + (lane & 15)] : 0u;
-        const unsigned long long m = __ballot(w != 0u);
-        const bool head = (lane & 15) == 0 && slot < n;
-        const bool has = head && ((m >> (lane & 48)) & 0xffffull) != 0ull;
-        const int idx = __shfl(wave_append(has, count), lane & 48);
-        if (((m >> (lane & 48)) & 0xffffull) != 0ull && slot < n) {
-            bits[(int64_t)idx * 16 + (lane & 15)] = w;
-            if (head) {
-                int bx, by, bz;
-                unpack_key(g.bkey[slot], bx, by, bz);
-                xyz[3 * idx] = bx;
-                xyz[3 * idx + 1] = by;
-                xyz[3 * idx + 2] = bz;
-            }
+    for (int64_t c0 = 256 * (int64_t)blockIdx.x; c0 < n; c0 += 256 * (int64_t)gridDim.x) {
+        SlotChunk c;
+        scan_chunk(g, c0, n, count, c);
+        int idx = c.pos;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (!((c.has >> t) & 1u)) continue;
+            uint4* dst = (uint4*)(bits + (int64_t)idx * 16);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = c.w[t][q];
+            int bx, by, bz;
+            unpack_key(g.bkey[c0 + 4 * lane + t], bx, by, bz);
+            xyz[3 * (int64_t)idx] = bx;
+            xyz[3 * (int64_t)idx + 1] = by;
+            xyz[3 * (int64_t)idx + 2] = bz;
+            ++idx;
         }
     }
 }
@@ -1812,28 +1970,29 @@ __global__ void __launch_bounds__(64) k_compact_gather(Grid g, int32_t* count, i
 // passes are 0 on it; the passes below take such blocks as 0 without storage.
 // ---------------------------------------------------------------------------
 
-// Lists the pool blocks holding an obstacle (four blocks per wave, one
-// occupancy word per lane) and writes every slot's interior index.
+// Lists the pool blocks holding an obstacle and writes every slot's interior
+// index (-1 for the others).
 __global__ void __launch_bounds__(64) k_int_list(Grid g) {
     const int lane = threadIdx.x;
     const int64_t n0 = g.cnt[C_NBLK];
     const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
-    for (int64_t base = 4 * (int64_t)blockIdx.x; base < n; base += 4 * (int64_t)gridDim.x) {
-        const int64_t slot = base + (lane >> 4);
-        const uint32_t w = slot < n ? g.occ[slot * 16 + (lane & 15)] : 0u;
-        const unsigned long long m = __ballot(w != 0u);
-        const bool head = (lane & 15) == 0 && slot < n;
-        const bool has = head && ((m >> (lane & 48)) & 0xffffull) != 0ull;
-        const int idx = wave_append(has, &g.cnt[C_NINT]);
-        if (head) {
+    for (int64_t c0 = 256 * (int64_t)blockIdx.x; c0 < n; c0 += 256 * (int64_t)gridDim.x) {
+        SlotChunk c;
+        scan_chunk(g, c0, n, &g.cnt[C_NINT], c);
+        int idx = c.pos;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t slot = c0 + 4 * lane + t;
+            if (slot >= n) continue;
             int32_t v = -1;
-            if (has) {
+            if ((c.has >> t) & 1u) {
                 if (idx < g.max_int) {
                     g.ilist[idx] = (int32_t)slot;
                     v = idx;
                 } else {
                     set_error(g, -3 /* EDT_ERR_CAPACITY */);
                 }
+                ++idx;
             }
             g.iidx[slot] = v;
         }

@@ -280,3 +280,23 @@ def test_points_list_matches_grid_and_closed_form():
     q = np.array([[1_000_003, 1, 700_000], [999_990, 5, 700_012], [0, 0, 0]])
     assert list(oracle.edt_points_list(o, 20, q)) == [25, 244, 400]
     assert list(oracle.edt_points_list(np.zeros((0, 3)), 9, q)) == [81, 81, 81]
+
+
+def test_uncapped_closed_forms():
+    # one obstacle at the end of a long row: x^2, far beyond 16-bit values
+    occ = np.zeros((3, 3, 400), np.uint8)
+    occ[1, 1, 0] = 1
+    u = oracle.edt_uncapped(occ)
+    z, y, x = np.meshgrid(np.arange(3), np.arange(3), np.arange(400), indexing="ij")
+    assert np.array_equal(u, x ** 2 + (y - 1) ** 2 + (z - 1) ** 2)
+    assert u.max() == 399 ** 2 + 2
+    # two obstacles: the nearer one, all-pairs
+    rng = np.random.default_rng(5)
+    occ = (rng.random((9, 40, 33)) < 0.002).astype(np.uint8)
+    occ[0, 0, 0] = 1
+    obs = np.argwhere(occ)[:, ::-1]
+    zz, yy, xx = np.meshgrid(np.arange(9), np.arange(40), np.arange(33), indexing="ij")
+    q = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1)
+    want = oracle.edt_points_list(obs, 46340, q).reshape(occ.shape)
+    assert np.array_equal(oracle.edt_uncapped(occ), want)
+    assert (oracle.edt_uncapped(np.zeros((4, 5, 6), np.uint8)) == oracle.INF).all()
