@@ -25,50 +25,121 @@
 
 #include "edt.h"
 
-namespace {
+namespace edt {
 
 constexpr int32_t DINF = 0x7fffffff;
 
-// Pass x.  Lanes take x = x0 + lane; left sweep writes the distance to the
-// nearest obstacle at or before x (or DINF) into out, the right sweep
-// combines it with the nearest at or after x and squares it.
+// Pass x.  One wave per row; the row is taken 1024 voxels at a time, 16
+// consecutive voxels per lane (one 16-byte load).  The nearest obstacle at
+// or before each voxel comes from the lane's own bits and an exclusive max
+// scan of the lanes' last obstacle positions (carried across chunks); the
+// nearest at or after it from a min scan the other way.  Rows longer than
+// 1024 keep the left distances in out between the two sweeps.
+__device__ inline uint32_t byte_bits(const uint4& w) {
+    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+    uint32_t m = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m |= (((v[i] >> (8 * k)) & 0xffu) != 0u ? 1u : 0u) << (4 * i + k);
+    return m;
+}
+
+__device__ inline uint32_t chunk_bits(const uint8_t* row, int x0, int nx, int lane) {
+    const int x = x0 + 16 * lane;
+    if (x + 16 <= nx && ((uintptr_t)(row + x) & 15) == 0) return byte_bits(*(const uint4*)(row + x));
+    uint32_t m = 0u;
+    for (int k = 0; k < 16; ++k)
+        if (x + k < nx && row[x + k]) m |= 1u << k;
+    return m;
+}
+
 __global__ void __launch_bounds__(64) k_dense_x(int nx, int ny, int nz,
                                                 const uint8_t* __restrict__ occ, int32_t* out) {
+    constexpr int64_t FAR = 1ll << 40;
     const int lane = threadIdx.x;
     const int64_t rows = (int64_t)ny * nz;
-    const unsigned long long below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);  // bits <= lane
-    const unsigned long long above = ~0ull << lane;                                   // bits >= lane
     for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
         const uint8_t* row = occ + r * nx;
         int32_t* o = out + r * nx;
-        int64_t last = -(1ll << 40);     // position of the nearest obstacle so far
-        for (int x0 = 0; x0 < nx; x0 += 64) {
-            const int x = x0 + lane;
-            const bool b = x < nx && row[x] != 0;
-            const unsigned long long m = __ballot(b);
-            const unsigned long long mb = m & below;
-            const int64_t near = mb ? (int64_t)x0 + 63 - __clzll((long long)mb) : last;
-            if (x < nx) {
-                const int64_t d = x - near;
-                o[x] = d > (1ll << 30) ? DINF : (int32_t)d;
+        const bool one = nx <= 1024;
+        // left sweep
+        int64_t carry = -FAR;
+        uint32_t keep = 0u;
+        for (int x0 = 0; x0 < nx; x0 += 1024) {
+            const uint32_t m = chunk_bits(row, x0, nx, lane);
+            if (one) keep = m;
+            const int64_t mylast = m ? (int64_t)x0 + 16 * lane + 31 - __clz(m) : -FAR;
+            int64_t incl = mylast;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int64_t v = __shfl_up(incl, d);
+                if (lane >= d && v > incl) incl = v;
             }
-            if (m) last = (int64_t)x0 + 63 - __clzll((long long)m);
+            int64_t prev = __shfl_up(incl, 1);
+            if (lane == 0) prev = -FAR;
+            if (carry > prev) prev = carry;
+            if (!one) {
+                int64_t near = prev;
+                for (int k = 0; k < 16; ++k) {
+                    const int x = x0 + 16 * lane + k;
+                    if ((m >> k) & 1u) near = x;
+                    if (x < nx) o[x] = x - near > (1 << 30) ? DINF : (int32_t)(x - near);
+                }
+            }
+            const int64_t tot = __shfl(incl, 63);
+            if (tot > carry) carry = tot;
+            if (one) carry = prev;     // the lane's own carry-in, used below
         }
-        int64_t next = 1ll << 40;
-        const int top = (nx - 1) & ~63;
-        for (int x0 = top; x0 >= 0; x0 -= 64) {
-            const int x = x0 + lane;
-            const bool b = x < nx && row[x] != 0;
-            const unsigned long long m = __ballot(b);
-            const unsigned long long ma = m & above;
-            const int64_t near = ma ? (int64_t)x0 + __ffsll((long long)ma) - 1 : next;
-            if (x < nx) {
-                const int32_t dl = o[x];
-                const int64_t dr = near - x;
-                const int64_t d = dr < (int64_t)dl ? dr : (int64_t)dl;
-                o[x] = d > (1ll << 30) ? DINF : (int32_t)(d * d);
+        // right sweep (and the result)
+        int64_t rcarry = FAR;
+        const int top = (nx - 1) & ~1023;
+        for (int x0 = top; x0 >= 0; x0 -= 1024) {
+            const uint32_t m = one ? keep : chunk_bits(row, x0, nx, lane);
+            const int64_t myfirst = m ? (int64_t)x0 + 16 * lane + __ffs(m) - 1 : FAR;
+            int64_t incl = myfirst;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int64_t v = __shfl_down(incl, d);
+                if (lane + d < 64 && v < incl) incl = v;
             }
-            if (m) next = (int64_t)x0 + __ffsll((long long)m) - 1;
+            int64_t next = __shfl_down(incl, 1);
+            if (lane == 63) next = FAR;
+            if (rcarry < next) next = rcarry;
+            int32_t res[16];
+            int64_t nr = next;
+#pragma unroll
+            for (int k = 15; k >= 0; --k) {
+                const int64_t x = x0 + 16 * lane + k;
+                if ((m >> k) & 1u) nr = x;
+                res[k] = (int32_t)((nr - x) > (1 << 30) ? (1 << 30) + 1 : nr - x);
+            }
+            int64_t nl = carry;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int64_t x = x0 + 16 * lane + k;
+                int64_t dl;
+                if (one) {
+                    if ((m >> k) & 1u) nl = x;
+                    dl = x - nl;
+                } else {
+                    dl = x < nx ? (int64_t)o[x] : FAR;
+                }
+                const int64_t d = (int64_t)res[k] < dl ? (int64_t)res[k] : dl;
+                res[k] = d > (1 << 30) ? DINF : (int32_t)(d * d);
+            }
+            const int xs = x0 + 16 * lane;
+            if (xs + 16 <= nx && ((uintptr_t)(o + xs) & 15) == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *(int4*)(o + xs + 4 * q) =
+                        make_int4(res[4 * q], res[4 * q + 1], res[4 * q + 2], res[4 * q + 3]);
+            } else {
+                for (int k = 0; k < 16; ++k)
+                    if (xs + k < nx) o[xs + k] = res[k];
+            }
+            const int64_t tot = __shfl(incl, 0);
+            if (tot < rcarry) rcarry = tot;
         }
     }
 }
@@ -98,8 +169,14 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
         int v0 = 0, v1 = 0;
         int64_t F0 = 0, F1 = 0;                              // f + v^2
         int32_t f1 = 0;
+        int32_t buf[16];
         for (int q = 0; q < n; ++q) {
-            const int32_t f = out[base + stride * q];
+            if ((q & 15) == 0) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    buf[u] = q + u < n ? out[base + stride * (q + u)] : DINF;
+            }
+            const int32_t f = buf[q & 15];
             if (f == DINF) continue;
             const int64_t Fq = (int64_t)f + (int64_t)q * q;
             // pop while the top parabola's interval is empty: the new one
@@ -149,6 +226,10 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
     }
 }
 
+}  // namespace edt
+
+namespace {
+
 inline int grid_of(int64_t work, int cap) {
     return (int)(work < 1 ? 1 : (work > cap ? cap : work));
 }
@@ -156,10 +237,12 @@ inline int grid_of(int64_t work, int cap) {
 bool dense_ok(int32_t nx, int32_t ny, int32_t nz) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     const int64_t d2 = (int64_t)nx * nx + (int64_t)ny * ny + (int64_t)nz * nz;
-    return d2 < (int64_t)DINF;
+    return d2 < (int64_t)edt::DINF;
 }
 
 }  // namespace
+
+using namespace edt;
 
 extern "C" {
 
