@@ -31,6 +31,7 @@ struct edt_ctx {
     int64_t ucap;       // update hash capacity
     int64_t stats_host[C_N];
     bool interior_valid;   // edt_interior ran after the last global / update
+    int32_t upd_gen;       // number of the current update call (1 .. 2^31 - 1)
     int32_t* scan_xyz;     // change list built by edt_integrate_scan
     uint8_t* scan_state;
     int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length,
@@ -482,10 +483,11 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     // n, so its grids stay moderate
     const int tn = grid_for(n_dev && n > 65536 ? 65536 : n, 256, 4096);
     const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
-    hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(64), 0, st, g);
-    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev);
-    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev);
-    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev);
+    c->upd_gen = c->upd_gen >= 0x7ffffffe ? 1 : c->upd_gen + 1;
+    const int32_t gen = c->upd_gen;
+    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev, gen);
+    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
+    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
     hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
     hipLaunchKernelGGL(k_seed_box, dim3(grid_for(n, 1, 4096)), dim3(64), 0, st, g);
     hipLaunchKernelGGL(k_upd_mark, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
@@ -493,10 +495,9 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     // more waves to hide each item's latency
     Grid gu = g;
     gu.lrun = 2;
-    hipLaunchKernelGGL(k_items_update, dim3(grid_for(2 * (int64_t)mb + 64, 256, 4096)), dim3(256), 0,
-                       st, gu);
-    hipLaunchKernelGGL(k_pass_x, dim3(grid_for(mb, 1, 8192)), dim3(64), 0, st, g,
-                       (const int32_t*)g.list_xs, (int)C_NXS);
+    const int nxw = grid_for(mb, 1, 2048);
+    hipLaunchKernelGGL(k_upd_x_items, dim3(nxw + grid_for(2 * (int64_t)mb + 64, 64, 2048)), dim3(64),
+                       0, st, gu, nxw);
     launch_pass(c, gu, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
     launch_pass(c, gu, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
     hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,

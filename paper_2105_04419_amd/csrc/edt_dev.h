@@ -44,9 +44,11 @@ enum : uint32_t {
     F_LOWER = 64u,   // marked by the lower front
 };
 
-// device counters (int32 slots of the counter array)
+// device counters (int32 slots of the counter array).  C_ABORT: the global
+// transform ran out of pool; C_UABORT: the number of the last cancelled
+// update (each update call has its own nonzero number).
 enum {
-    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_RESERVED5,
+    C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_UABORT,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,
     C_NXS, C_NYS, C_NNEWDIL, C_DONE, C_NTILE, C_N
 };

@@ -474,13 +474,14 @@ __device__ inline bool run_start(const Grid& g, int bx, int by, int bz, int axis
 
 // y items from the ys list and z items from the dirty list in one launch
 // (incremental transform).
-__global__ void k_items_update(Grid g) {
+// Workgroups vb of vgrid (of blockDim.x threads) share the lists.
+__device__ inline void items_update_body(const Grid& g, int64_t vb, int64_t vgrid) {
     const int64_t ny = min((int64_t)g.cnt[C_NYS], (int64_t)g.max_blocks);
     const int64_t nd = min((int64_t)g.cnt[C_NDIRTY], (int64_t)g.max_blocks);
     // a wave takes entries of one list only (the y part is padded to 64)
     const int64_t nyp = (ny + 63) & ~(int64_t)63;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - __lane_id() < nyp + nd;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = vb * blockDim.x + threadIdx.x; i - __lane_id() < nyp + nd;
+         i += vgrid * blockDim.x) {
         const bool zpart = i - __lane_id() >= nyp;
         const int64_t k = zpart ? i - nyp : i;
         const bool ok = zpart ? k < nd : k < ny;
@@ -679,14 +680,14 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
 // pass X: squared 1-D distance along x from the bits, clamped to D.  One wave
 // per block, lane = row (y + 8z).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int list_counter) {
-    __shared__ int32_t nb[72];
+__device__ inline void pass_x_body(const Grid& g, const int32_t* list, int list_counter,
+                                   int64_t vb, int64_t vgrid, int32_t* nb) {
     const int lane = threadIdx.x;
     const int64_t n0 = list ? g.cnt[list_counter] : g.cnt[C_NBLK];
     const int64_t n = n0 < g.max_blocks ? n0 : g.max_blocks;
     const int R = g.R;
     const uint8_t* occ8 = (const uint8_t*)g.occ;
-    for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    for (int64_t w = vb; w < n; w += vgrid) {
         const int32_t slot = list ? list[w] : (int32_t)w;
         int bx, by, bz;
         unpack_key(g.bkey[slot], bx, by, bz);
@@ -747,6 +748,20 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
         if (lane == 0) g.bmin1[slot] = (uint16_t)(mn * mn);
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int list_counter) {
+    __shared__ int32_t nb[72];
+    pass_x_body(g, list, list_counter, blockIdx.x, gridDim.x, nb);
+}
+
+// Incremental transform: pass x over the xs list and the y / z work items
+// are independent, so they share one launch; the first nxw workgroups take
+// pass x.
+__global__ void __launch_bounds__(64) k_upd_x_items(Grid g, int nxw) {
+    __shared__ int32_t nb[72];
+    if ((int)blockIdx.x < nxw) pass_x_body(g, g.list_xs, C_NXS, blockIdx.x, nxw, nb);
+    else items_update_body(g, (int64_t)blockIdx.x - nxw, (int64_t)gridDim.x - nxw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1304,23 +1319,23 @@ __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int3
 // ---------------------------------------------------------------------------
 // incremental update
 // ---------------------------------------------------------------------------
-__global__ void k_upd_begin(Grid g) {
-    const int i = threadIdx.x;
-    if (i == C_ABORT || (i >= C_NYI && i < C_N)) g.cnt[i] = 0;
-}
 
 // Range check (any entry outside the extent cancels the whole call) and
 // last-entry-wins dedupe through a voxel-keyed hash (value = max entry index).
+// Also zeroes the update's counters (no other workgroup of this kernel uses
+// them).  A cancelled update writes its number `gen` (never 0, different
+// for every call) into C_UABORT, so nothing needs clearing between calls.
 __global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n0,
-                             const int32_t* n_dev) {
+                             const int32_t* n_dev, int32_t gen) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    if (blockIdx.x == 0 && threadIdx.x >= C_NYI && threadIdx.x < C_N) g.cnt[threadIdx.x] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         g.upos[i] = -1;
         if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz) {
             set_error(g, -2);
-            g.cnt[C_ABORT] = 1;
+            g.cnt[C_UABORT] = gen;
             continue;
         }
         const unsigned long long key = (unsigned long long)x +
@@ -1329,7 +1344,7 @@ __global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n0
         const int32_t h = hinsert(g.ukeys, g.umask, key, &created);
         if (h < 0) {
             set_error(g, -3);
-            g.cnt[C_ABORT] = 1;
+            g.cnt[C_UABORT] = gen;
             continue;
         }
         g.upos[i] = h;
@@ -1373,8 +1388,9 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
 // New blocks for voxels that become occupied (initialised to background by
 // the claiming wave).
 __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev) {
-    if (g.cnt[C_ABORT]) return;
+                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
+                            int32_t gen) {
+    if (g.cnt[C_UABORT] == gen) return;
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     const int lane = __lane_id();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < n;
@@ -1388,18 +1404,21 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
             e = insert_block(g, bx, by, bz, &created);
             if (e < 0) {
                 set_error(g, -3);
-                g.cnt[C_ABORT] = 1;
+                g.cnt[C_UABORT] = gen;
             }
         }
-        init_slots(g, claim_slots(g, created, e, key, 0u));
+        const int32_t sl = claim_slots(g, created, e, key, 0u);
+        if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
+        init_slots(g, sl);
     }
 }
 
 // Apply the winning entries: flip occupancy bits, record the changed voxels
 // per block (the wave centres) and list the blocks that hold them.
 __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev) {
-    if (g.cnt[C_ABORT]) return;
+                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
+                            int32_t gen) {
+    if (g.cnt[C_UABORT] == gen) return;
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1542,12 +1561,15 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
 //   raise: some removed voxel r has |box(B) - r|^2 <= bmax(B) and < D
 //   xs:    blocks within R along x of a seed (their g1 can change)
 //   ys:    blocks within R in x and y of a seed (their g2 can change)
-__global__ void k_upd_mark(Grid g) {
+__global__ void __launch_bounds__(256) k_upd_mark(Grid g) {
+    __shared__ int wcnt[4][5];      // per wave: dirty, ys, xs, raise, lower
+    __shared__ int bbase[3];        // the block's list positions
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NSEED] * w3;
-    const int lane = __lane_id();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    for (int64_t b0 = blockIdx.x * (int64_t)blockDim.x; b0 < total;
+         b0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
         bool new_dirty = false, new_xs = false, new_ys = false, raise = false, lower = false;
         int32_t slot = -1;
         if (i < total) {
@@ -1597,25 +1619,38 @@ __global__ void k_upd_mark(Grid g) {
                 }
             }
         }
-        // the wave's list appends and statistics: the counter atomics are
-        // issued together by one lane
+        // list appends and statistics: one counter atomic per list and
+        // workgroup, positions from the waves' ballots
         const unsigned long long md = __ballot(new_dirty), my = __ballot(new_ys),
                                  mx = __ballot(new_xs), mr = __ballot(raise), ml = __ballot(lower);
-        int bd = 0, by_ = 0, bx_ = 0;
         if (lane == 0) {
-            if (md) bd = atomicAdd(&g.cnt[C_NDIRTY], __popcll(md));
-            if (my) by_ = atomicAdd(&g.cnt[C_NYS], __popcll(my));
-            if (mx) bx_ = atomicAdd(&g.cnt[C_NXS], __popcll(mx));
-            if (mr) atomicAdd(&g.cnt[C_NRAISE], __popcll(mr));
-            if (ml) atomicAdd(&g.cnt[C_NLOWER], __popcll(ml));
+            wcnt[wid][0] = __popcll(md);
+            wcnt[wid][1] = __popcll(my);
+            wcnt[wid][2] = __popcll(mx);
+            wcnt[wid][3] = __popcll(mr);
+            wcnt[wid][4] = __popcll(ml);
         }
-        bd = __shfl(bd, 0);
-        by_ = __shfl(by_, 0);
-        bx_ = __shfl(bx_, 0);
+        __syncthreads();
+        if (threadIdx.x < 5) {
+            const int c = threadIdx.x;
+            const int sum = wcnt[0][c] + wcnt[1][c] + wcnt[2][c] + wcnt[3][c];
+            const int ctr = c == 0 ? C_NDIRTY : c == 1 ? C_NYS : c == 2 ? C_NXS
+                          : c == 3 ? C_NRAISE : C_NLOWER;
+            const int base = sum ? atomicAdd(&g.cnt[ctr], sum) : 0;
+            if (c < 3) bbase[c] = base;
+        }
+        __syncthreads();
+        int bd = bbase[0], by_ = bbase[1], bx_ = bbase[2];
+        for (int v = 0; v < wid; ++v) {
+            bd += wcnt[v][0];
+            by_ += wcnt[v][1];
+            bx_ += wcnt[v][2];
+        }
         const unsigned long long below = (1ull << lane) - 1ull;
         if (new_dirty) g.list_dirty[bd + __popcll(md & below)] = slot;
         if (new_ys) g.list_ys[by_ + __popcll(my & below)] = slot;
         if (new_xs) g.list_xs[bx_ + __popcll(mx & below)] = slot;
+        __syncthreads();
     }
 }
 

@@ -157,6 +157,11 @@ def test_out_of_range_entry_cancels_call():
     f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
     assert f.error() == -2
     assert np.array_equal(f.dense().cpu().numpy(), before)
+    # a cancelled call does not hold back the next one
+    xyz = np.array([[1, 1, 1], [9, 3, 12]], np.int32)
+    f.update(cu(xyz), cu(np.array([1, 1], np.uint8)))
+    assert f.error() == 0
+    check(f, apply_cpu(occ, xyz, np.ones(2)), 6, "after cancelled calls")
 
 
 def test_change_capacity_is_checked_on_host():
