@@ -37,7 +37,8 @@ struct edt_ctx {
     int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length,
                            // [3] finished workgroups of the hit kernel, [4..5] int64
                            // number of visited-voxel slots
-    int64_t* scan_off;     // per ray: first slot in the flat enumeration
+    int64_t* scan_off;     // per ray: first slot within its group of 1024 rays
+    int64_t* scan_blk;     // per group of 1024 rays: slot total, then first slot
 };
 
 namespace {
@@ -57,7 +58,7 @@ struct Layout {
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
     O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
-    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_SCANOFF, O_N
+    O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_SCANOFF, O_SCANBLK, O_N
 };
 
 bool valid_cfg(const edt_config* c) {
@@ -95,7 +96,7 @@ bool layout_of(const edt_config* c, Layout* L) {
         mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4,
-        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256, mc * 8};
+        mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256, mc * 8, (mc / 1024 + 1) * 16};
     int64_t o = 0;
     for (int i = 0; i < O_N; ++i) {
         L->off[i] = o;
@@ -309,6 +310,7 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     c->scan_state = (uint8_t*)(b + L.off[O_SCANST]);
     c->scan_cnt = (int32_t*)(b + L.off[O_SCANCNT]);
     c->scan_off = (int64_t*)(b + L.off[O_SCANOFF]);
+    c->scan_blk = (int64_t*)(b + L.off[O_SCANBLK]);
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -528,11 +530,16 @@ edt_status edt_integrate_scan(edt_ctx* c, const int32_t* d_origin, const int32_t
     const int64_t cap = mc - n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->scan_cnt, (int64_t)4, 0);
     int64_t* total = (int64_t*)(c->scan_cnt + 4);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, g, d_origin, d_ends, n,
-                       c->scan_off, total);
+    const int64_t nb = (n + 1023) / 1024;
+    int64_t* btot = c->scan_blk;
+    int64_t* bpre = c->scan_blk + nb;
+    hipLaunchKernelGGL(k_scan_offsets, dim3((unsigned)nb), dim3(1024), 0, st, g, d_origin, d_ends,
+                       n, c->scan_off, btot);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, (const int64_t*)btot, nb, bpre,
+                       total);
     hipLaunchKernelGGL(k_scan_clear, dim3(16384), dim3(64), 0, st, g, d_origin, d_ends, d_hits, n,
-                       (const int64_t*)c->scan_off, (const int64_t*)total, c->scan_cnt,
-                       c->scan_xyz, c->scan_state, cap);
+                       (const int64_t*)c->scan_off, (const int64_t*)bpre, (const int64_t*)total,
+                       c->scan_cnt, c->scan_xyz, c->scan_state, cap);
     hipLaunchKernelGGL(k_scan_hits, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, d_origin,
                        d_ends, d_hits, n, c->scan_cnt, c->scan_xyz, c->scan_state, cap);
     LAUNCH_CHECK();

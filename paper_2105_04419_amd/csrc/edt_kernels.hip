@@ -1772,25 +1772,48 @@ __device__ inline int64_t ray_slots(const Grid& g, const int o[3], bool o_in,
     return (int64_t)abs(e[0] - o[0]) + abs(e[1] - o[1]) + abs(e[2] - o[2]) + 1;
 }
 
-// Exclusive prefix sum of the rays' slot counts in one workgroup of 1024
-// threads: chunks of 1024 rays, one ray per thread, a shuffle scan per wave,
-// then the 16 wave totals, then the running carry.  off[r], and the total in
-// *total.  Rays with an endpoint outside the extent get no slots and set
-// EDT_ERR_RANGE.
+// Exclusive prefix sum of the rays' slot counts in two levels: every
+// workgroup of 1024 threads scans its 1024 rays (one ray per thread, a
+// shuffle scan per wave, then the 16 wave totals) into loff[] and its total
+// into btot[]; k_scan_blocks then scans the totals into bpre[].  The first
+// slot of ray r is bpre[r / 1024] + loff[r].  Rays with an endpoint outside
+// the extent get no slots and set EDT_ERR_RANGE.
 __global__ void __launch_bounds__(1024) k_scan_offsets(Grid g, const int32_t* __restrict__ origin,
                                                        const int32_t* __restrict__ ends, int64_t n,
-                                                       int64_t* off, int64_t* total) {
+                                                       int64_t* loff, int64_t* btot) {
     __shared__ int64_t wsum[16];
-    __shared__ int64_t carry;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int o[3] = {origin[0], origin[1], origin[2]};
     const bool o_in = in_extent(g, o);
+    const int64_t r = (int64_t)blockIdx.x * 1024 + t;
+    const int64_t k = r < n ? ray_slots(g, o, o_in, ends, r) : 0;
+    if (r < n && k == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+    int64_t incl = k;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int64_t before = 0;
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    if (r < n) loff[r] = before + incl - k;
+    if (t == 1023) btot[blockIdx.x] = before + incl;
+}
+
+// Exclusive scan of the nb workgroup totals (one workgroup, chunks of 1024
+// with a carried sum); the total slot count goes to *total.
+__global__ void __launch_bounds__(1024) k_scan_blocks(const int64_t* __restrict__ btot, int64_t nb,
+                                                      int64_t* bpre, int64_t* total) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     if (t == 0) carry = 0;
     __syncthreads();
-    for (int64_t c0 = 0; c0 < n; c0 += 1024) {
-        const int64_t r = c0 + t;
-        const int64_t k = r < n ? ray_slots(g, o, o_in, ends, r) : 0;
-        if (r < n && k == 0) set_error(g, -2 /* EDT_ERR_RANGE */);
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t i = c0 + t;
+        const int64_t k = i < nb ? btot[i] : 0;
         int64_t incl = k;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -1801,12 +1824,16 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(Grid g, const int32_t* __
         __syncthreads();
         int64_t before = carry;
         for (int j = 0; j < w; ++j) before += wsum[j];
-        if (r < n) off[r] = before + incl - k;
+        if (i < nb) bpre[i] = before + incl - k;
         __syncthreads();
         if (t == 1023) carry = before + incl;
         __syncthreads();
     }
     if (t == 0) *total = carry;
+}
+
+__device__ inline int64_t ray_first_slot(const int64_t* loff, const int64_t* bpre, int64_t r) {
+    return bpre[r >> 10] + loff[r];
 }
 
 // Change entries "free" for the visited voxels that are occupied now (the
@@ -1817,7 +1844,8 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(Grid g, const int32_t* __
 __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __restrict__ origin,
                                                    const int32_t* __restrict__ ends,
                                                    const uint8_t* __restrict__ hits, int64_t n,
-                                                   const int64_t* __restrict__ off,
+                                                   const int64_t* __restrict__ loff,
+                                                   const int64_t* __restrict__ bpre,
                                                    const int64_t* total_p, int32_t* cnt,
                                                    int32_t* lxyz, uint8_t* lst, int64_t cap) {
     const int lane = threadIdx.x;
@@ -1833,7 +1861,7 @@ __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __rest
             const int64_t span = hi - lo + 1;
             const int64_t stp = (span + 63) / 64;
             const int64_t q = lo + (int64_t)lane * stp;
-            const bool le = q <= hi && off[q] <= base;
+            const bool le = q <= hi && ray_first_slot(loff, bpre, q) <= base;
             const unsigned long long m = __ballot(le);   // lane 0 always qualifies
             const int top = 63 - __clzll((long long)m);
             lo = lo + (int64_t)top * stp;
@@ -1843,7 +1871,7 @@ __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __rest
         const int64_t rb = lo;
         // each lane: the last ray in rb .. rb + 63 whose first slot is at or
         // before f, by binary search over the 64 offsets held across lanes
-        const int64_t wj = rb + lane < n ? off[rb + lane] : INT64_MAX;
+        const int64_t wj = rb + lane < n ? ray_first_slot(loff, bpre, rb + lane) : INT64_MAX;
         int j = 0;
 #pragma unroll
         for (int stp = 32; stp > 0; stp >>= 1) {
@@ -1855,9 +1883,9 @@ __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __rest
         if (f < total) {
             int64_t r = rb + j;
             // more than 63 rays without slots in between: continue linearly
-            while (r + 1 < n && off[r + 1] <= f) ++r;
+            while (r + 1 < n && ray_first_slot(loff, bpre, r + 1) <= f) ++r;
             lo = r;
-            const int64_t k = f - off[lo];     // 0: the sensor voxel, k >= 1: crossing k - 1
+            const int64_t k = f - ray_first_slot(loff, bpre, lo);     // 0: the sensor voxel, k >= 1: crossing k - 1
             const int e[3] = {ends[3 * lo], ends[3 * lo + 1], ends[3 * lo + 2]};
             if (k > 0) {
                 const int d[3] = {e[0] - o[0], e[1] - o[1], e[2] - o[2]};
