@@ -537,7 +537,7 @@ edt_status edt_integrate_scan(edt_ctx* c, const int32_t* d_origin, const int32_t
                        n, c->scan_off, btot);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, (const int64_t*)btot, nb, bpre,
                        total);
-    hipLaunchKernelGGL(k_scan_clear, dim3(16384), dim3(64), 0, st, g, d_origin, d_ends, d_hits, n,
+    hipLaunchKernelGGL(k_scan_clear, dim3(2048), dim3(1024), 0, st, g, d_origin, d_ends, d_hits, n,
                        (const int64_t*)c->scan_off, (const int64_t*)bpre, (const int64_t*)total,
                        c->scan_cnt, c->scan_xyz, c->scan_state, cap);
     hipLaunchKernelGGL(k_scan_hits, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, d_origin,

@@ -1841,17 +1841,22 @@ __device__ inline int64_t ray_first_slot(const int64_t* loff, const int64_t* bpr
 // enumeration, so short rays share a wave; each lane finds its ray by binary
 // search over the offsets.  Entries go to the list front through cnt[0]
 // (capacity cap).
-__global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __restrict__ origin,
+__global__ void __launch_bounds__(1024) k_scan_clear(Grid g, const int32_t* __restrict__ origin,
                                                    const int32_t* __restrict__ ends,
                                                    const uint8_t* __restrict__ hits, int64_t n,
                                                    const int64_t* __restrict__ loff,
                                                    const int64_t* __restrict__ bpre,
                                                    const int64_t* total_p, int32_t* cnt,
                                                    int32_t* lxyz, uint8_t* lst, int64_t cap) {
-    const int lane = threadIdx.x;
+    __shared__ int wcnt[16];
+    __shared__ int wgbase;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int o[3] = {origin[0], origin[1], origin[2]};
     const int64_t total = *total_p;
-    for (int64_t base = 64 * (int64_t)blockIdx.x; base < total; base += 64 * (int64_t)gridDim.x) {
+    // sixteen waves per workgroup, one chunk of 64 slots each; the list
+    // positions take one counter atomic per workgroup
+    for (int64_t b0 = 1024 * (int64_t)blockIdx.x; b0 < total; b0 += 1024 * (int64_t)gridDim.x) {
+        const int64_t base = b0 + 64 * wid;
         const int64_t f = base + lane;
         // rb: the last ray whose first slot is at or before `base`, by a
         // 64-way search of the whole wave (rays without slots share the next
@@ -1897,7 +1902,19 @@ __global__ void __launch_bounds__(64) k_scan_clear(Grid g, const int32_t* __rest
         }
         occ_bits<1>(g, v, want, bit);
         const bool emit = want[0] && bit[0];
-        const int idx = wave_append(emit, cnt);
+        const unsigned long long m = __ballot(emit);
+        if (lane == 0) wcnt[wid] = __popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int sum = 0;
+            for (int j = 0; j < 16; ++j) sum += wcnt[j];
+            wgbase = sum ? atomicAdd(cnt, sum) : 0;
+        }
+        __syncthreads();
+        int idx = wgbase;
+        for (int j = 0; j < wid; ++j) idx += wcnt[j];
+        idx += __popcll(m & ((1ull << lane) - 1ull));
+        __syncthreads();
         if (emit) {
             if (idx < cap) {
                 lxyz[3 * (int64_t)idx] = v[0][0];
