@@ -416,12 +416,21 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
             if (lane >= o) incl += v;
         }
         const int total = __shfl(incl, 63);
+        // obstacle blocks created here (block-list input) are counted as
+        // obstacle blocks; one 64-bit atomic advances both the block count
+        // (low word) and that count (high word)
+        const int nobst = wave_sum(__popc(want & ob));
         if (total > 0) {
             int base = 0;
-            if (lane == 0) base = atomicAdd(&g.cnt[C_NBLK], total);
+            if (lane == 0) {
+                static_assert(C_NDIL == C_NBLK + 1 && C_NBLK == 0, "adjacent counters");
+                const unsigned long long old = atomicAdd(
+                    (unsigned long long*)&g.cnt[C_NBLK],
+                    (unsigned long long)total | ((unsigned long long)nobst << 32));
+                base = (int)(uint32_t)old;
+            }
             base = __shfl(base, 0);
             int slot = base + incl - c;
-            int nobst = 0;
 #pragma unroll
             for (int x = 0; x < 8; ++x) {
                 if (!((want >> x) & 1u)) continue;
@@ -430,7 +439,6 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
                     g.tslots[e0 + x] = slot;
                     g.bkey[slot] = pack_key(8 * tx + x, by, bz);
                     g.flags[slot] = o ? F_DILATED : 0u;
-                    nobst += o ? 1 : 0;
                 } else {
                     g.tslots[e0 + x] = -1;
                     set_error(g, -3 /* EDT_ERR_CAPACITY */);
@@ -438,11 +446,8 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
                 }
                 ++slot;
             }
-            // obstacle blocks created here (block-list input) are counted as
-            // obstacle blocks; zero the occupancy and change masks of the
-            // new slots [base, base + total)
-            nobst = wave_sum(nobst);
-            if (lane == 0 && nobst) atomicAdd(&g.cnt[C_NDIL], nobst);
+            // zero the occupancy and change masks of the new slots
+            // [base, base + total)
             const int64_t lo = base, hi = min((int64_t)base + total, (int64_t)g.max_blocks);
             for (int64_t k = lo * 16 + lane; k < hi * 16; k += 64) {
                 g.occ[k] = 0u;
