@@ -201,3 +201,28 @@ def test_scans_on_tunnel_map():
             assert np.array_equal(a, g.dense().cpu().numpy()), f"scan {t}: incremental != global"
             assert np.array_equal(a, oracle.edt_separable(sim.map, 32)), f"scan {t}"
     assert f.error() == 0
+
+
+def test_pool_overflow_in_update_then_rebuild():
+    # a pool that holds the initial region but not a far new obstacle's
+    nx, ny, nz = 96, 96, 32
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    occ[4, 4, 4] = 1
+    f = Field((nx, ny, nz), 8, max_blocks=12)
+    f.global_(cu(occ))
+    assert f.error() == 0
+    far = np.array([[90, 90, 28]], np.int32)
+    f.update(cu(far), cu(np.ones(1, np.uint8)))
+    assert f.error() == -3                       # EDT_ERR_CAPACITY: the call was cancelled
+    # the documented remedy: rebuild, after which updates work again
+    f2 = Field((nx, ny, nz), 8, max_blocks=400)
+    f2.global_(cu(occ))
+    f2.update(cu(far), cu(np.ones(1, np.uint8)))
+    assert f2.error() == 0
+    check(f2, apply_cpu(occ, far, np.ones(1)), 8, "after rebuild")
+    # and a cancelled call on the small pool does not block a later one that fits
+    near = np.array([[5, 4, 4]], np.int32)
+    f.global_(cu(occ))
+    f.update(cu(near), cu(np.ones(1, np.uint8)))
+    assert f.error() == 0
+    check(f, apply_cpu(occ, near, np.ones(1)), 8, "small pool, fitting update")
