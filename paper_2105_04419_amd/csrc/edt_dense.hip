@@ -164,11 +164,13 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
                                        : (int64_t)x + (int64_t)nx * w;
         const int64_t col = (int64_t)x + (int64_t)nx * w;   // column index among ncols
         int2* E = env + col;                                 // entry k at E[k * ncols]
-        // build the lower envelope; (v1, f1) is the top, (v0, f0) below it
+        // build the lower envelope; (v1, F1) is the top, (v0, F0) the entry
+        // below it and (v2, F2) the one below that, held in registers so a
+        // pop needs no load (the entry under v2 is fetched at each pop and
+        // used only at the next)
         int k = -1;
-        int v0 = 0, v1 = 0;
-        int64_t F0 = 0, F1 = 0;                              // f + v^2
-        int32_t f1 = 0;
+        int v0 = 0, v1 = 0, v2 = 0;
+        int64_t F0 = 0, F1 = 0, F2 = 0;                      // f + v^2
         int32_t buf[16];
         for (int q = 0; q < n; ++q) {
             if ((q & 15) == 0) {
@@ -185,23 +187,23 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
                 --k;
                 v1 = v0;
                 F1 = F0;
-                if (k >= 1) {
-                    const int2 e = E[(int64_t)(k - 1) * ncols];
-                    v0 = e.x;
-                    F0 = (int64_t)e.y + (int64_t)e.x * e.x;
+                v0 = v2;
+                F0 = F2;
+                if (k >= 2) {
+                    const int2 e = E[(int64_t)(k - 2) * ncols];
+                    v2 = e.x;
+                    F2 = (int64_t)e.y + (int64_t)e.x * e.x;
                 }
             }
             ++k;
             E[(int64_t)k * ncols] = make_int2(q, f);
-            if (k >= 1) {
-                v0 = v1;
-                F0 = F1;
-            }
+            v2 = v0;
+            F2 = F0;
+            v0 = v1;
+            F0 = F1;
             v1 = q;
             F1 = Fq;
-            f1 = f;
         }
-        (void)f1;
         // read off: parabola j covers q while the next one is not yet lower
         if (k < 0) {
             for (int q = 0; q < n; ++q) out[base + stride * q] = cap;
@@ -210,6 +212,7 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
         int j = 0;
         int2 cur = E[0];
         int2 nxt = k >= 1 ? E[ncols] : cur;
+        int2 nx2 = k >= 2 ? E[2 * ncols] : nxt;              // fetched one entry ahead
         for (int q = 0; q < n; ++q) {
             // next parabola is at least as low at q: (F_next - F_cur) <= 2 q (v_next - v_cur)
             while (j < k) {
@@ -218,7 +221,8 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
                 if (Fn - Fc > 2ll * q * (int64_t)(nxt.x - cur.x)) break;
                 ++j;
                 cur = nxt;
-                if (j < k) nxt = E[(int64_t)(j + 1) * ncols];
+                nxt = nx2;
+                if (j + 2 <= k) nx2 = E[(int64_t)(j + 2) * ncols];
             }
             const int64_t d = (int64_t)(q - cur.x) * (q - cur.x) + cur.y;
             out[base + stride * q] = d < (int64_t)cap ? (int32_t)d : cap;
