@@ -45,8 +45,8 @@ enum : uint32_t {
 };
 
 // device counters (int32 slots of the counter array).  C_ABORT: the global
-// transform ran out of pool; C_UABORT: the number of the last cancelled
-// update (each update call has its own nonzero number).
+// transform ran out of pool; C_UABORT: nonzero (the call's number) while
+// the running update is cancelled, cleared by its last kernel.
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_UABORT,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,

@@ -1328,8 +1328,8 @@ __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int3
 // Range check (any entry outside the extent cancels the whole call) and
 // last-entry-wins dedupe through a voxel-keyed hash (value = max entry index).
 // Also zeroes the update's counters (no other workgroup of this kernel uses
-// them).  A cancelled update writes its number `gen` (never 0, different
-// for every call) into C_UABORT, so nothing needs clearing between calls.
+// them).  A cancelled update writes its number `gen` (never 0) into
+// C_UABORT; the update's last kernel clears it again.
 __global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n0,
                              const int32_t* n_dev, int32_t gen) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
@@ -1662,6 +1662,10 @@ __global__ void __launch_bounds__(256) k_upd_mark(Grid g) {
 // Clear per-update state: dedupe table entries, change masks and flags.
 __global__ void k_upd_cleanup(Grid g, int64_t n0, const int32_t* n_dev) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    // no other workgroup of this kernel touches the cancel flag: one thread
+    // clears it, so a replayed copy of the update (a captured graph, whose
+    // call number is fixed) starts uncancelled too
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_UABORT] = 0;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i < n; i += stride) {
