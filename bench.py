@@ -10,7 +10,8 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
   cpu_baseline   the CPU oracle (separable windowed minimum, OpenMP) on the
                  same map;
   incremental    p50 / p99 latency of edt_update over simulated range scans
-                 along the tunnels, plus an incremental == global check;
+                 along the tunnels, plus an incremental == global check, and
+                 the same scans replayed from one captured HIP graph;
   clearance      clearance cost forward + backward on the 64x64x32 map field
                  with 4096 x 64 waypoints, points per second;
   batched        64 dense room maps (sides 32..256, d_max 24): autotuned
@@ -279,6 +280,7 @@ def bench_incremental(g, args, torch, np):
     h = Field(f.shape, args.dmax)
     h.global_(torch.from_numpy(final).cuda())
     same = bool(torch.equal(h.dense(), f.dense()))
+    graph = bench_incremental_graph(g, args, torch, np, dev, h)
     return {
         "scans": len(dev_ms),
         "p50_ms": round(pct(dev_ms, 50), 4),
@@ -288,6 +290,71 @@ def bench_incremental(g, args, torch, np):
         "changed_voxels_mean": round(float(np.mean(changed)), 1),
         "dirty_blocks_mean": round(float(np.mean(dirty)), 1),
         "incremental_equals_global": same,
+        "graph": graph,
+    }
+
+
+def bench_incremental_graph(g, args, torch, np, dev, final_field):
+    """The same scans replayed from one captured HIP graph of edt_update: the
+    change lists are padded to the longest (repeating the last entry, a
+    no-op) and copied into the captured buffers before each replay; a scan
+    without changes needs no update and is not replayed."""
+    from paper_2105_04419_amd import Field
+    n = max(int(x.shape[0]) for x, _ in dev)
+    pad = []
+    for x, s in dev:
+        k = n - x.shape[0]
+        if x.shape[0] == 0:
+            pad.append(None)
+            continue
+        pad.append((torch.cat([x, x[-1:].expand(k, 3)]) if k else x,
+                    torch.cat([s, s[-1:].expand(k)]) if k else s))
+    first = next(p for p in pad if p is not None)
+    f = Field(g["f"].shape, args.dmax)
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    xb = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    sb = torch.empty(n, dtype=torch.uint8, device="cuda")
+    # capture on a copy of the first scan, after a warm-up of the same call
+    w = Field(g["f"].shape, args.dmax)
+    w.global_blocks(g["xyz_d"], g["occ_d"])
+    xb.copy_(first[0])
+    sb.copy_(first[1])
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        w.update(xb, sb)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        f.update(xb, sb)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dev_ms, wall_ms = [], []
+    for i, p in enumerate(pad):
+        if p is None:
+            continue
+        xb.copy_(p[0])
+        sb.copy_(p[1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        graph.replay()
+        e1.record()
+        e1.synchronize()
+        t1 = time.perf_counter()
+        if i >= args.scan_warmup:
+            dev_ms.append(e0.elapsed_time(e1))
+            wall_ms.append((t1 - t0) * 1e3)
+    assert f.error() == 0
+    return {
+        "padded_changes": n,
+        "p50_ms": round(pct(dev_ms, 50), 4),
+        "p99_ms": round(pct(dev_ms, 99), 4),
+        "host_p50_ms": round(pct(wall_ms, 50), 4),
+        "host_p99_ms": round(pct(wall_ms, 99), 4),
+        "graph_equals_global": bool(torch.equal(final_field.dense(), f.dense())),
     }
 
 
