@@ -205,7 +205,9 @@ edt_status edt_query_signed(edt_ctx* ctx, const int32_t* d_xyz, int64_t n,
  * edt_query_signed).  Same state requirement as edt_query_signed. */
 edt_status edt_read_signed_dense(edt_ctx* ctx, int32_t* d_out, void* stream);
 
-/* Dense readback: s for the whole extent into d_out (int32[nx*ny*nz]). */
+/* Dense readback: s for the whole extent into d_out (int32[nx*ny*nz]).
+ * The dense forms (dense input, the three dense readbacks) need fewer than
+ * 2^31 blocks of 8^3 in the extent, else EDT_ERR_ARG. */
 edt_status edt_read_dense(edt_ctx* ctx, int32_t* d_out, void* stream);
 
 /* Dense occupancy readback into d_occ (uint8[nx*ny*nz], 0/1). */

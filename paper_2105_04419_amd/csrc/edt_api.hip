@@ -402,6 +402,8 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
     hipStream_t st = S(stream);
     if (map->kind == EDT_MAP_DENSE) {
         if (!map->d_occ) return EDT_ERR_ARG;
+        // one workgroup per strip of 8 blocks along x (a one-dimensional grid)
+        if ((int64_t)((g.nbx + 7) / 8) * g.nby * g.nbz > 0x7fffffff) return EDT_ERR_ARG;
     } else if (map->kind == EDT_MAP_BLOCKS) {
         if (map->n_blocks < 0) return EDT_ERR_ARG;
         if (map->n_blocks > 0 && (!map->d_block_xyz || !map->d_block_occ)) return EDT_ERR_ARG;
@@ -415,7 +417,8 @@ edt_status edt_global(edt_ctx* c, const edt_map* map, void* stream) {
     if (map->kind == EDT_MAP_DENSE) {
         // obstacle blocks get their slots and occupancy here, the dilation
         // adds (and zeroes) the rest of the region
-        hipLaunchKernelGGL(k_ingest_dense, dim3((g.nbx + 7) / 8, g.nby, g.nbz), dim3(64), 0, st, g,
+        const int64_t strips = (int64_t)((g.nbx + 7) / 8) * g.nby * g.nbz;
+        hipLaunchKernelGGL(k_ingest_dense, dim3((unsigned)strips), dim3(64), 0, st, g,
                            map->d_occ);
         mark(c, 1, st);
         edt_status r = dilate_region(c, st);
@@ -599,7 +602,9 @@ edt_status edt_read_signed_dense(edt_ctx* c, int32_t* d_out, void* stream) {
     if (!c || !d_out) return EDT_ERR_ARG;
     if (!c->interior_valid) return EDT_ERR_STATE;
     const Grid& g = c->g;
-    hipLaunchKernelGGL(k_read_signed, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_out);
+    const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
+    if (nblk > 0x7fffffff) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_read_signed, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_out);
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -607,7 +612,9 @@ edt_status edt_read_signed_dense(edt_ctx* c, int32_t* d_out, void* stream) {
 edt_status edt_read_dense(edt_ctx* c, int32_t* d_out, void* stream) {
     if (!c || !d_out) return EDT_ERR_ARG;
     const Grid& g = c->g;
-    hipLaunchKernelGGL(k_read_dense, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_out);
+    const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
+    if (nblk > 0x7fffffff) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_read_dense, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_out);
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -615,7 +622,9 @@ edt_status edt_read_dense(edt_ctx* c, int32_t* d_out, void* stream) {
 edt_status edt_read_occupancy(edt_ctx* c, uint8_t* d_occ, void* stream) {
     if (!c || !d_occ) return EDT_ERR_ARG;
     const Grid& g = c->g;
-    hipLaunchKernelGGL(k_read_occ, dim3(g.nbx, g.nby, g.nbz), dim3(64), 0, S(stream), g, d_occ);
+    const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
+    if (nblk > 0x7fffffff) return EDT_ERR_ARG;
+    hipLaunchKernelGGL(k_read_occ, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_occ);
     LAUNCH_CHECK();
     return EDT_OK;
 }

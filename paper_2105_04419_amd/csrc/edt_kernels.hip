@@ -129,12 +129,24 @@ __device__ inline int32_t claim_slots(const Grid& g, bool created, int64_t e,
 // ---------------------------------------------------------------------------
 // ingest
 // ---------------------------------------------------------------------------
+// Workgroup b of a one-dimensional grid over an (nxb, nyb, nzb) box of
+// blocks (a 3-D grid would cap y and z at 65535 workgroups).
+__device__ inline void block_of(int nxb, int nyb, int& bx, int& by, int& bz) {
+    const int64_t b = blockIdx.x;
+    bx = (int)(b % nxb);
+    const int64_t r = b / nxb;
+    by = (int)(r % nyb);
+    bz = (int)(r / nyb);
+}
+
 // Dense grid.  One wave per strip of 8 blocks along x; lane = row (y + 8z).
 // Each lane reads 64 contiguous bytes of its row, packs 8 bits per block and
 // the wave ballot decides whether a block holds any obstacle.
 __global__ void __launch_bounds__(64) k_ingest_dense(Grid g, const uint8_t* __restrict__ occ) {
     const int lane = threadIdx.x;
-    const int bx0 = blockIdx.x * 8, by = blockIdx.y, bz = blockIdx.z;
+    int sx, by, bz;
+    block_of((g.nbx + 7) / 8, g.nby, sx, by, bz);
+    const int bx0 = sx * 8;
     const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
     const int x0 = 8 * bx0;
     uint32_t bytes[8];
@@ -1215,7 +1227,8 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_read_dense(Grid g, int32_t* __restrict__ out) {
     const int lane = threadIdx.x;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    int bx, by, bz;
+    block_of(g.nbx, g.nby, bx, by, bz);
     const int32_t slot = find_block(g, bx, by, bz);
     const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
     if (y >= g.ny || z >= g.nz) return;
@@ -1231,7 +1244,8 @@ __global__ void __launch_bounds__(64) k_read_dense(Grid g, int32_t* __restrict__
 
 __global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ out) {
     const int lane = threadIdx.x;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    int bx, by, bz;
+    block_of(g.nbx, g.nby, bx, by, bz);
     const int32_t slot = find_block(g, bx, by, bz);
     const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
     if (y >= g.ny || z >= g.nz) return;
@@ -2272,7 +2286,8 @@ __global__ void k_query_signed(Grid g, const int32_t* __restrict__ xyz, int64_t 
 
 __global__ void __launch_bounds__(64) k_read_signed(Grid g, int32_t* __restrict__ out) {
     const int lane = threadIdx.x;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    int bx, by, bz;
+    block_of(g.nbx, g.nby, bx, by, bz);
     const int32_t slot = find_block(g, bx, by, bz);
     const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
     if (y >= g.ny || z >= g.nz) return;

@@ -211,3 +211,16 @@ def test_tunnel_full_extent(seed):
     pts = np.stack([rng.integers(0, nx, 300), rng.integers(0, ny, 300),
                     rng.integers(0, nz, 300)], 1).astype(np.int32)
     assert np.array_equal(got[pts[:, 2], pts[:, 1], pts[:, 0]], oracle.edt_points(occ, 32, pts))
+
+
+def test_thin_extents_beyond_65535_blocks_per_axis():
+    # dense input and readbacks use one-dimensional grids: an extent with
+    # more than 65535 blocks along y (or z) works
+    for shape in [(1, 600000, 2), (600000, 1, 3)]:
+        nz, ny, nx = shape
+        rng = np.random.default_rng(nz)
+        occ = (rng.random(shape) < 0.001).astype(np.uint8)
+        f = gpu_field(occ, 5)
+        assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 5), f"thin {shape}")
+        assert np.array_equal(f.occupancy().cpu().numpy(), occ)
+        assert f.error() == 0
