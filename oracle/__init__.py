@@ -18,6 +18,9 @@ Contents
       occupied and free voxels exchanged (the squared distance from an
       occupied voxel to the nearest free voxel of the extent, clamped to D),
       and the signed field that combines the two.
+  Alg1
+      The paper's Algorithm 1 itself on the CPU (``alg1.c``), to measure what
+      its procedure computes and costs; not an oracle.
   ray_voxels / integrate_scan
       The occupancy integration of a range scan in front of the transform
       (``scan_oracle.c``): the exact integer voxel walk of a ray and the
@@ -38,6 +41,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "edt_oracle.c")
 _SRC_SCAN = os.path.join(_HERE, "scan_oracle.c")
+_SRC_ALG1 = os.path.join(_HERE, "alg1.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -48,7 +52,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                        "-Wall", "-o", tmp, _SRC, _SRC_SCAN], check=True)
+                        "-Wall", "-o", tmp, _SRC, _SRC_SCAN, _SRC_ALG1], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,6 +74,17 @@ def lib():
         L.oracle_ray_voxels.restype = ctypes.c_int64
         L.oracle_integrate_scan.argtypes = [u8p, ci, ci, ci, i32p, i32p, u8p, ctypes.c_int64]
         L.oracle_integrate_scan.restype = ctypes.c_int64
+        vp = ctypes.c_void_p
+        L.alg1_create.argtypes = [ci, ci, ci, ci]
+        L.alg1_create.restype = vp
+        L.alg1_destroy.argtypes = [vp]
+        L.alg1_destroy.restype = None
+        L.alg1_apply.argtypes = [vp, i32p, u8p, ctypes.c_int64]
+        L.alg1_apply.restype = None
+        L.alg1_transform.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.alg1_transform.restype = None
+        L.alg1_read.argtypes = [vp, i32p]
+        L.alg1_read.restype = None
         for f in (L.oracle_edt_bruteforce, L.oracle_edt_points,
                   L.oracle_edt_separable, L.oracle_threads):
             f.restype = ci
@@ -201,6 +216,51 @@ def integrate_scan(occ: np.ndarray, origin, ends: np.ndarray, hits: np.ndarray):
     if sk < 0:
         raise ValueError("oracle_integrate_scan: bad arguments")
     return occ, int(sk)
+
+
+class Alg1:
+    """The paper's Algorithm 1 on the CPU (``alg1.c``): SetObstacle /
+    RemoveObstacle, then DistanceTransform with Raise and Lower over the
+    26-neighbourhood.  Not an oracle: it is the paper's own procedure, whose
+    result the tests compare with the exact field."""
+
+    def __init__(self, shape, dmax: int):
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self._h = lib().alg1_create(nx, ny, nz, int(dmax))
+        if not self._h:
+            raise ValueError("alg1_create failed")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().alg1_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def apply(self, xyz, state):
+        xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+        state = np.ascontiguousarray(state, dtype=np.uint8).reshape(-1)
+        lib().alg1_apply(self._h, _i32(xyz), _u8(state), len(xyz))
+        return self
+
+    def set_map(self, occ):
+        """SetObstacle for every occupied voxel of occ (nz, ny, nx)."""
+        xyz = np.argwhere(np.asarray(occ) != 0)[:, ::-1]
+        return self.apply(xyz, np.ones(len(xyz), np.uint8))
+
+    def transform(self):
+        """DistanceTransform; returns (cells lowered, cells raised)."""
+        c = (ctypes.c_int64 * 2)()
+        lib().alg1_transform(self._h, c)
+        return int(c[0]), int(c[1])
+
+    def field(self) -> np.ndarray:
+        nx, ny, nz = self.shape
+        out = np.empty((nz, ny, nx), dtype=np.int32)
+        lib().alg1_read(self._h, _i32(out))
+        return out
 
 
 def threads(n: int = 0) -> int:
