@@ -24,7 +24,10 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
                  returns): occupancy integration on the GPU plus the
                  incremental transform, p50 / p99 per scan;
   uncapped       the full transform without a radius (int32) of the tunnel
-                 map's dense extent, the paper's dataset setting.
+                 map's dense extent, the paper's dataset setting;
+  paper_alg1_cpu the paper's own Algorithm 1 on one CPU thread: a global
+                 build of a tunnel-map corner (and its deviation from the
+                 exact field) and range scans on the 64x64x32 map.
 """
 from __future__ import annotations
 
@@ -187,6 +190,54 @@ def bench_cpu_single(g, args, np):
     oracle.threads(prev)
     return {"value": g["n_ext"] / t, "unit": "voxels/s", "cores": 1, "kind": "oracle",
             "sample": f"one separable oracle run on the full tunnel extent, {t:.1f} s"}
+
+
+def bench_paper_alg1(g, args, np):
+    """The paper's own procedure (Algorithm 1, one CPU thread, oracle.Alg1):
+    a global build of a 256 x 256 x 128 corner of the tunnel map and its
+    deviation from the exact field, then 30 range scans on the 64 x 64 x 32
+    boxes map (d_max 20) with per-scan time and lowered / raised cells, the
+    counts of the paper's Table II."""
+    import oracle
+    import workloads
+    from workloads.scans import ScanSim, ellipse_path
+    sub = np.ascontiguousarray(g["occ"][:, :256, :256])
+    nz, ny, nx = sub.shape
+    a = oracle.Alg1((nx, ny, nz), args.dmax)
+    t0 = time.perf_counter()
+    a.set_map(sub)
+    lowered, _ = a.transform()
+    t = time.perf_counter() - t0
+    f = a.field()
+    ref = oracle.edt_separable(sub, args.dmax)
+    a.close()
+    out = {"global": {"workload": f"tunnel map corner {nx}x{ny}x{nz}, d_max {args.dmax}",
+                      "ms": round(t * 1e3, 1), "voxels_per_s": sub.size / t,
+                      "lowered": lowered, "voxels_differing_from_exact": int((f != ref).sum()),
+                      "max_overestimate": int((f - ref).max())}}
+    occ = workloads.dense_boxes(0)
+    sim = ScanSim(occ, ellipse_path(64, 64, 32), seed=0)
+    b = oracle.Alg1((64, 64, 32), 20)
+    b.set_map(occ)
+    b.transform()
+    ms, lo, ra, ch = [], [], [], []
+    for _ in range(30):
+        xyz, st, _ = sim.step()
+        t0 = time.perf_counter()
+        b.apply(xyz, st)
+        l, r = b.transform()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        lo.append(l)
+        ra.append(r)
+        ch.append(len(xyz))
+    exact = bool(np.array_equal(b.field(), oracle.edt_separable(sim.map, 20)))
+    b.close()
+    out["incremental"] = {"workload": "30 range scans on the 64x64x32 boxes map, d_max 20",
+                          "p50_ms": round(pct(ms, 50), 3), "changed_mean": float(np.mean(ch)),
+                          "lowered_mean": float(np.mean(lo)), "raised_mean": float(np.mean(ra)),
+                          "equals_exact": exact}
+    out["cores"] = 1
+    return out
 
 
 def bench_tunnel_x4(args, torch, np):
@@ -598,6 +649,8 @@ def main():
         if not args.no_extra:
             log("[bench] cpu oracle, one thread")
             out["cpu_single_thread"] = bench_cpu_single(g, args, np)
+            log("[bench] the paper's Algorithm 1 on one cpu thread")
+            out["paper_alg1_cpu"] = bench_paper_alg1(g, args, np)
     if not args.no_extra:
         log(f"[bench] incremental: {args.scans} scans")
         out["incremental"] = bench_incremental(g, args, torch, np)
