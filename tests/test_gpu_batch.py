@@ -82,3 +82,27 @@ def test_rejects_large_radius():
     from paper_2105_04419_amd import EdtError
     with pytest.raises(EdtError):
         Batch([(8, 8, 8)], 65)
+
+
+def test_degenerate_and_extreme_maps():
+    """Single voxels, empty and full maps, and the longest side the batch
+    accepts (4096) along each axis, in one batch."""
+    rng = np.random.default_rng(3)
+    maps = [np.ones((1, 1, 1), np.uint8), np.zeros((1, 1, 1), np.uint8),
+            np.zeros((9, 10, 11), np.uint8), np.ones((7, 6, 5), np.uint8)]
+    for axis in range(3):
+        shape = [2, 3, 2]
+        shape[axis] = 4096
+        m = np.zeros(shape, np.uint8)
+        m.reshape(-1)[rng.integers(0, m.size, 3)] = 1
+        maps.append(m)
+    for dmax in (1, 24, 64):
+        b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], dmax)
+        occ = b.pack(maps)
+        f = b.run(occ, mode=FUSED)
+        check(b, maps, f, dmax, f"degenerate d={dmax}")
+        assert torch.equal(f, b.run(occ, mode=PER_MAP))
+    single = Batch([(33, 17, 5)], 24)
+    m = (rng.random((5, 17, 33)) < 0.05).astype(np.uint8)
+    out = single.run(single.pack([m]), mode=FUSED)
+    check(single, [m], out, 24, "one map")
