@@ -224,3 +224,16 @@ def test_thin_extents_beyond_65535_blocks_per_axis():
         assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 5), f"thin {shape}")
         assert np.array_equal(f.occupancy().cpu().numpy(), occ)
         assert f.error() == 0
+
+
+def test_empty_block_list_then_updates():
+    f = Field((40, 30, 20), 9)
+    f.global_blocks(torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
+                    torch.zeros((0, 512), dtype=torch.uint8, device="cuda"))
+    assert (f.dense().cpu().numpy() == 81).all() and f.error() == 0
+    xyz = torch.tensor([[3, 4, 5], [39, 29, 19]], dtype=torch.int32, device="cuda")
+    f.update(xyz, torch.ones(2, dtype=torch.uint8, device="cuda"))
+    occ = np.zeros((20, 30, 40), np.uint8)
+    occ[5, 4, 3] = occ[19, 29, 39] = 1
+    assert_same(f.dense().cpu().numpy(), oracle.edt_separable(occ, 9), "after updates")
+    assert f.error() == 0
