@@ -126,19 +126,6 @@ __device__ inline uint32_t hash_of(unsigned long long k, uint32_t mask) {
     return (uint32_t)k & mask;
 }
 
-// Slot of block key `key`, or -1.  Probes are bounded by the capacity.
-__device__ inline int32_t hfind(const unsigned long long* keys, const int32_t* vals,
-                                uint32_t mask, unsigned long long key) {
-    uint32_t h = hash_of(key, mask);
-    for (uint32_t i = 0; i <= mask; ++i) {
-        unsigned long long k = keys[h];
-        if (k == key) return vals[h];
-        if (k == KEY_EMPTY) return -1;
-        h = (h + 1) & mask;
-    }
-    return -1;
-}
-
 // Table position of key, or -1 (read-only probe).
 __device__ inline int32_t hpos(const unsigned long long* keys, uint32_t mask,
                                unsigned long long key) {

@@ -103,11 +103,6 @@ __device__ inline void note_tile(const Grid& g, bool tile_created, int64_t e, bo
     grow_tiles(g, first, bx >> 3, by >> 3, bz >> 3);
 }
 
-
-__device__ inline int32_t load_count(const Grid& g, int idx) {
-    return __hip_atomic_load(&g.cnt[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Pool slots for the lanes that just created a block at tile entry e: one
 // counter atomic per wave.  Returns the slot, or -1 (not created / pool full).
 __device__ inline int32_t claim_slots(const Grid& g, bool created, int64_t e,
@@ -512,28 +507,6 @@ __device__ inline void items_update_body(const Grid& g, int64_t vb, int64_t vgri
         }
         const int idx = wave_append(st, &g.cnt[zpart ? C_NZI : C_NYI]);
         if (st) (zpart ? g.list_zi : g.list_yi)[idx] = slot;
-    }
-}
-
-__global__ void k_items(Grid g, const int32_t* src, int src_counter, uint32_t runflag,
-                        int axes) {
-    const int64_t n = src ? g.cnt[src_counter] : g.cnt[C_NBLK];
-    const int64_t lim = n < g.max_blocks ? n : g.max_blocks;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < lim;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t slot = src ? src[i] : (int32_t)i;
-        int bx, by, bz;
-        unpack_key(g.bkey[slot], bx, by, bz);
-        if (axes & 1) {
-            const bool st = run_start(g, bx, by, bz, 1, runflag);
-            const int idx = wave_append(st, &g.cnt[C_NYI]);
-            if (st) g.list_yi[idx] = slot;
-        }
-        if (axes & 2) {
-            const bool st = run_start(g, bx, by, bz, 2, runflag);
-            const int idx = wave_append(st, &g.cnt[C_NZI]);
-            if (st) g.list_zi[idx] = slot;
-        }
     }
 }
 
