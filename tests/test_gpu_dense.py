@@ -107,3 +107,18 @@ def test_argument_errors():
         dense_global(occ, -1)
     with pytest.raises(EdtError):
         dense_global(occ, 46341)
+
+
+def test_largest_extent_squared_distances_near_int32_max():
+    # nx^2 + ny^2 + nz^2 just below 2^31: one obstacle in a corner gives
+    # squared distances up to 46338^2 + 2, exact in int32
+    nx, ny, nz = 46339, 2, 2
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    occ[0, 0, 0] = 1
+    got = run(occ)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    want = x.astype(np.int64) ** 2 + y ** 2 + z ** 2
+    assert np.array_equal(got.astype(np.int64), want)
+    assert int(got.max()) == 46338 ** 2 + 2
+    # and capped at the largest radius
+    assert np.array_equal(run(occ, 46340).astype(np.int64), np.minimum(want, 46340 ** 2))
