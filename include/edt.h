@@ -257,16 +257,20 @@ typedef struct {
     int64_t out_offset;
 } edt_batch_map;
 
-/* Schedule of a batched run (edt_batch_run; NULL = defaults {8, 8, 4, 0}):
+/* Schedule of a batched run (edt_batch_run; NULL = defaults {8, 8, 4, 0, 4}):
  *   lrun          blocks per work item along y and z (1 .. 64)
  *   waves_per_cu  waves resident per compute unit (0 = default, <= 64)
  *   chunk         work items taken per queue atomic (1 .. 1024)
- *   schedule      0 = dynamic queue, 1 = static stride                      */
+ *   schedule      0 = dynamic queue, 1 = static stride
+ *   wg_waves      waves per workgroup: 1, 2 or 4 (0 = 4); each wave takes
+ *                 its own work items, the workgroup size only changes how
+ *                 the waves are dispatched and share a compute unit      */
 typedef struct {
     int32_t lrun;
     int32_t waves_per_cu;
     int32_t chunk;
     int32_t schedule;
+    int32_t wg_waves;
 } edt_tune;
 
 /* EDT_BATCH_FUSED: one persistent cooperative launch for all maps and

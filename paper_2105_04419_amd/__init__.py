@@ -65,7 +65,8 @@ class EdtBatchMap(ctypes.Structure):
 
 class EdtTune(ctypes.Structure):
     _fields_ = [("lrun", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("wg_waves", ctypes.c_int32)]
 
 
 _lib = None
@@ -397,7 +398,7 @@ def clearance_cost(s, wp, h: float = 0.2, margin: float = 1.0):
 # batched dense maps
 # ---------------------------------------------------------------------------
 FUSED, PER_MAP = 0, 1
-DEFAULT_TUNE = {"lrun": 8, "waves_per_cu": 8, "chunk": 4, "schedule": 0}
+DEFAULT_TUNE = {"lrun": 8, "waves_per_cu": 8, "chunk": 4, "schedule": 0, "wg_waves": 4}
 
 
 class Batch:
@@ -461,7 +462,7 @@ class Batch:
         t = dict(DEFAULT_TUNE)
         if tune:
             t.update(tune)
-        tt = EdtTune(t["lrun"], t["waves_per_cu"], t["chunk"], t["schedule"])
+        tt = EdtTune(t["lrun"], t["waves_per_cu"], t["chunk"], t["schedule"], t["wg_waves"])
         _check("edt_batch_run", lib().edt_batch_run(self._h, _ptr(occ_flat), _ptr(out), int(mode),
                                                     ctypes.byref(tt), _stream(stream)))
         return out

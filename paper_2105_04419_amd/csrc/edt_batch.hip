@@ -71,15 +71,20 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
 // inside each block), 7 integer ops per voxel; M = ceil(d_max / 8) blocks of
 // context cover d_max.  Results gather in LDS in the g1 block layout
 // (y + 8x + 64z) and leave as 16-byte stores.
+// LDS of item_x: each wave owns 8 blocks of XLS u16 (padded from 512); the
+// workgroup's share is sized at launch, one slice per wave
+constexpr int XLS = 514;
+constexpr size_t XBYTES_PER_WAVE = 8 * XLS * sizeof(uint16_t);
+extern __shared__ __align__(16) uint16_t xlds[];
+
 template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
-    constexpr int LS = 514;                      // u16 per block in LDS (padded)
+    constexpr int LS = XLS;
     constexpr int NBYTES = 64 + 16 * M;          // window bytes per row
     constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
     constexpr int RB = 16;                       // rows whose loads are in flight together
     constexpr int NB = 8 + 2 * M;                // window blocks
-    __shared__ uint16_t xbuf[4][8 * LS];
-    uint16_t* buf = xbuf[(threadIdx.x >> 6) & 3];
+    uint16_t* buf = xlds + (threadIdx.x >> 6) * (8 * LS);
     // the rows' window words (row r, word w at rowbits[NWIN r + w]) share the
     // buffer: they are read back before any result is written
     unsigned long long* rowbits = (unsigned long long*)buf;
@@ -405,19 +410,22 @@ struct edt_batch {
 namespace {
 
 template <int M>
-edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu,
+edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu, int wg_waves,
                         hipStream_t st) {
+    const int bs = 64 * wg_waves;
+    const size_t lds = wg_waves * XBYTES_PER_WAVE;
     if (mode == EDT_BATCH_FUSED) {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<M>, 256, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<M>, bs, lds) !=
             hipSuccess)
             return EDT_ERR_HIP;
-        const int wgs_per_cu = waves_per_cu > 0 ? (waves_per_cu + 3) / 4 : 2;
+        const int wgs_per_cu =
+            waves_per_cu > 0 ? (waves_per_cu + wg_waves - 1) / wg_waves : 8 / wg_waves;
         const int g = b->cus * (wgs_per_cu < per_cu ? wgs_per_cu : per_cu);
         if (g < 1) return EDT_ERR_HIP;
         void* args[] = {(void*)&a};
-        if (hipLaunchCooperativeKernel((const void*)k_batch_fused<M>, dim3(g), dim3(256), args, 0,
-                                       st) != hipSuccess)
+        if (hipLaunchCooperativeKernel((const void*)k_batch_fused<M>, dim3(g), dim3(bs), args,
+                                       (unsigned)lds, st) != hipSuccess)
             return EDT_ERR_HIP;
         return EDT_OK;
     }
@@ -430,8 +438,8 @@ edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu
             (int64_t)m.nxr * m.ny * ((m.nbz + a.lrun - 1) / a.lrun)};
         for (int phase = 0; phase < 3; ++phase) {
             const int waves = grid_cap(items[phase], b->cus * (waves_per_cu > 0 ? waves_per_cu : 8));
-            hipLaunchKernelGGL(k_batch_phase<M>, dim3((waves + 3) / 4), dim3(256), 0, st, a, phase,
-                               mi);
+            hipLaunchKernelGGL(k_batch_phase<M>, dim3((waves + wg_waves - 1) / wg_waves), dim3(bs),
+                               lds, st, a, phase, mi);
         }
     }
     return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_HIP;
@@ -530,10 +538,12 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
                          const edt_tune* tune, void* stream) {
     if (!b || !d_occ || !d_out) return EDT_ERR_ARG;
     if (mode != EDT_BATCH_FUSED && mode != EDT_BATCH_PER_MAP) return EDT_ERR_ARG;
-    edt_tune t = {8, 8, 4, 0};
+    edt_tune t = {8, 8, 4, 0, 4};
     if (tune) t = *tune;
+    if (t.wg_waves == 0) t.wg_waves = 4;
     if (t.lrun < 1 || t.lrun > 64 || t.chunk < 1 || t.chunk > 1024 || t.waves_per_cu < 0 ||
-        t.waves_per_cu > 64 || (t.schedule != 0 && t.schedule != 1))
+        t.waves_per_cu > 64 || (t.schedule != 0 && t.schedule != 1) ||
+        (t.wg_waves != 1 && t.wg_waves != 2 && t.wg_waves != 4))
         return EDT_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     const BLayout& L = b->L;
@@ -561,14 +571,14 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
                        (int32_t*)a.itemmap, a.icap);
     if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
     switch (b->M) {
-        case 1: return launch_batch<1>(b, a, mode, t.waves_per_cu, st);
-        case 2: return launch_batch<2>(b, a, mode, t.waves_per_cu, st);
-        case 3: return launch_batch<3>(b, a, mode, t.waves_per_cu, st);
-        case 4: return launch_batch<4>(b, a, mode, t.waves_per_cu, st);
-        case 5: return launch_batch<5>(b, a, mode, t.waves_per_cu, st);
-        case 6: return launch_batch<6>(b, a, mode, t.waves_per_cu, st);
-        case 7: return launch_batch<7>(b, a, mode, t.waves_per_cu, st);
-        case 8: return launch_batch<8>(b, a, mode, t.waves_per_cu, st);
+        case 1: return launch_batch<1>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 2: return launch_batch<2>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 3: return launch_batch<3>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 4: return launch_batch<4>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 5: return launch_batch<5>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 6: return launch_batch<6>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 7: return launch_batch<7>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
+        case 8: return launch_batch<8>(b, a, mode, t.waves_per_cu, t.wg_waves, st);
         default: return EDT_ERR_ARG;
     }
 }

@@ -51,10 +51,11 @@ def test_small_batch_all_modes(dmax):
 
 
 @pytest.mark.parametrize("tune", [
-    {"lrun": 1, "chunk": 1, "schedule": 0, "waves_per_cu": 4},
-    {"lrun": 3, "chunk": 7, "schedule": 0, "waves_per_cu": 16},
-    {"lrun": 16, "chunk": 64, "schedule": 1, "waves_per_cu": 8},
-    {"lrun": 64, "chunk": 2, "schedule": 1, "waves_per_cu": 1},
+    {"lrun": 1, "chunk": 1, "schedule": 0, "waves_per_cu": 4, "wg_waves": 1},
+    {"lrun": 3, "chunk": 7, "schedule": 0, "waves_per_cu": 16, "wg_waves": 2},
+    {"lrun": 16, "chunk": 64, "schedule": 1, "waves_per_cu": 8, "wg_waves": 4},
+    {"lrun": 64, "chunk": 2, "schedule": 1, "waves_per_cu": 1, "wg_waves": 1},
+    {"lrun": 8, "chunk": 4, "schedule": 0, "waves_per_cu": 5, "wg_waves": 2},
 ])
 def test_schedules_are_bit_identical(tune):
     maps = small_maps(11, 9, 8, 90)
@@ -64,6 +65,18 @@ def test_schedules_are_bit_identical(tune):
     check(b, maps, ref, 24, "per_map")
     assert torch.equal(b.run(occ, mode=FUSED, tune=tune), ref)
     assert torch.equal(b.run(occ, mode=PER_MAP, tune=tune), ref)
+
+
+def test_rejects_bad_schedule():
+    from paper_2105_04419_amd import EdtError
+    b = Batch([(8, 8, 8)], 4)
+    occ = b.pack([np.zeros((8, 8, 8), np.uint8)])
+    for bad in ({"wg_waves": 3}, {"wg_waves": 8}, {"lrun": 0}, {"chunk": 2000},
+                {"schedule": 2}, {"waves_per_cu": 65}):
+        t = {"lrun": 8, "chunk": 4, "schedule": 0, "waves_per_cu": 8, "wg_waves": 4}
+        t.update(bad)
+        with pytest.raises(EdtError):
+            b.run(occ, mode=FUSED, tune=t)
 
 
 def test_full_batch_of_64_room_maps():
