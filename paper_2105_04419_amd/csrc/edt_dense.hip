@@ -145,8 +145,9 @@ __global__ void __launch_bounds__(64) k_dense_x(int nx, int ny, int nz,
 }
 
 // Passes y (AXIS 1) and z (AXIS 2), in place on out, with the envelope in
-// env.  Column (x, w): x fastest within a wave; w = z for y, y for z.
-template <int AXIS>
+// env.  Column (x, w): x fastest within a wave; w = z for y, y for z.  The
+// column is read and written CH values at a time.
+template <int AXIS, int CH>
 __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_t* out, int2* env,
                                                   int32_t cap) {
     const int lane = threadIdx.x;
@@ -171,38 +172,48 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
         int k = -1;
         int v0 = 0, v1 = 0, v2 = 0;
         int64_t F0 = 0, F1 = 0, F2 = 0;                      // f + v^2
-        int32_t buf[16];
-        for (int q = 0; q < n; ++q) {
-            if ((q & 15) == 0) {
+        // the column is read CH values at a time, the next CH in flight while
+        // the current ones are pushed (positions past the end read as DINF)
+        const int32_t* src = out + base;
+        int32_t buf[CH], nbuf[CH];
 #pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    buf[u] = q + u < n ? out[base + stride * (q + u)] : DINF;
-            }
-            const int32_t f = buf[q & 15];
-            if (f == DINF) continue;
-            const int64_t Fq = (int64_t)f + (int64_t)q * q;
-            // pop while the top parabola's interval is empty: the new one
-            // overtakes it no later than the top overtook the one below
-            while (k >= 1 && (Fq - F1) * (int64_t)(v1 - v0) <= (F1 - F0) * (int64_t)(q - v1)) {
-                --k;
-                v1 = v0;
-                F1 = F0;
-                v0 = v2;
-                F0 = F2;
-                if (k >= 2) {
-                    const int2 e = E[(int64_t)(k - 2) * ncols];
-                    v2 = e.x;
-                    F2 = (int64_t)e.y + (int64_t)e.x * e.x;
+        for (int u = 0; u < CH; ++u) buf[u] = u < n ? src[stride * u] : DINF;
+        for (int q0 = 0; q0 < n; q0 += CH) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                nbuf[u] = q0 + CH + u < n ? src[stride * (q0 + CH + u)] : DINF;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int q = q0 + u;
+                const int32_t f = buf[u];
+                if (f == DINF) continue;
+                const int64_t Fq = (int64_t)f + (int64_t)q * q;
+                // pop while the top parabola's interval is empty: the new one
+                // overtakes it no later than the top overtook the one below
+                while (k >= 1 &&
+                       (Fq - F1) * (int64_t)(v1 - v0) <= (F1 - F0) * (int64_t)(q - v1)) {
+                    --k;
+                    v1 = v0;
+                    F1 = F0;
+                    v0 = v2;
+                    F0 = F2;
+                    if (k >= 2) {
+                        const int2 e = E[(int64_t)(k - 2) * ncols];
+                        v2 = e.x;
+                        F2 = (int64_t)e.y + (int64_t)e.x * e.x;
+                    }
                 }
+                ++k;
+                E[(int64_t)k * ncols] = make_int2(q, f);
+                v2 = v0;
+                F2 = F0;
+                v0 = v1;
+                F0 = F1;
+                v1 = q;
+                F1 = Fq;
             }
-            ++k;
-            E[(int64_t)k * ncols] = make_int2(q, f);
-            v2 = v0;
-            F2 = F0;
-            v0 = v1;
-            F0 = F1;
-            v1 = q;
-            F1 = Fq;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) buf[u] = nbuf[u];
         }
         // read off: parabola j covers q while the next one is not yet lower
         if (k < 0) {
@@ -213,19 +224,30 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, int32_
         int2 cur = E[0];
         int2 nxt = k >= 1 ? E[ncols] : cur;
         int2 nx2 = k >= 2 ? E[2 * ncols] : nxt;              // fetched one entry ahead
-        for (int q = 0; q < n; ++q) {
-            // next parabola is at least as low at q: (F_next - F_cur) <= 2 q (v_next - v_cur)
-            while (j < k) {
-                const int64_t Fc = (int64_t)cur.y + (int64_t)cur.x * cur.x;
-                const int64_t Fn = (int64_t)nxt.y + (int64_t)nxt.x * nxt.x;
-                if (Fn - Fc > 2ll * q * (int64_t)(nxt.x - cur.x)) break;
-                ++j;
-                cur = nxt;
-                nxt = nx2;
-                if (j + 2 <= k) nx2 = E[(int64_t)(j + 2) * ncols];
+        // CH outputs are computed, then stored together
+        int32_t* dst = out + base;
+        for (int q0 = 0; q0 < n; q0 += CH) {
+            int32_t res[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int q = q0 + u;
+                // next parabola is at least as low at q:
+                // (F_next - F_cur) <= 2 q (v_next - v_cur)
+                while (j < k) {
+                    const int64_t Fc = (int64_t)cur.y + (int64_t)cur.x * cur.x;
+                    const int64_t Fn = (int64_t)nxt.y + (int64_t)nxt.x * nxt.x;
+                    if (Fn - Fc > 2ll * q * (int64_t)(nxt.x - cur.x)) break;
+                    ++j;
+                    cur = nxt;
+                    nxt = nx2;
+                    if (j + 2 <= k) nx2 = E[(int64_t)(j + 2) * ncols];
+                }
+                const int64_t d = (int64_t)(q - cur.x) * (q - cur.x) + cur.y;
+                res[u] = d < (int64_t)cap ? (int32_t)d : cap;
             }
-            const int64_t d = (int64_t)(q - cur.x) * (q - cur.x) + cur.y;
-            out[base + stride * q] = d < (int64_t)cap ? (int32_t)d : cap;
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (q0 + u < n) dst[stride * (q0 + u)] = res[u];
         }
     }
 }
@@ -268,10 +290,12 @@ edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
     const int nxc = (nx + 63) / 64;
     hipLaunchKernelGGL(k_dense_x, dim3(grid_of((int64_t)ny * nz, 65536)), dim3(64), 0, st, nx, ny,
                        nz, d_occ, d_out);
-    hipLaunchKernelGGL(k_dense_col<1>, dim3(grid_of((int64_t)nxc * nz, 65536)), dim3(64), 0, st,
-                       nx, ny, nz, d_out, env, (int32_t)DINF);
-    hipLaunchKernelGGL(k_dense_col<2>, dim3(grid_of((int64_t)nxc * ny, 65536)), dim3(64), 0, st,
-                       nx, ny, nz, d_out, env, cap);
+    // chunk lengths measured on a 1024x1024x128 extent: 16 for the long y
+    // columns, 8 for z (fewer registers, more resident waves)
+    hipLaunchKernelGGL((k_dense_col<1, 16>), dim3(grid_of((int64_t)nxc * nz, 65536)), dim3(64),
+                       0, st, nx, ny, nz, d_out, env, (int32_t)DINF);
+    hipLaunchKernelGGL((k_dense_col<2, 8>), dim3(grid_of((int64_t)nxc * ny, 65536)), dim3(64), 0,
+                       st, nx, ny, nz, d_out, env, cap);
     if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
     return EDT_OK;
 }
