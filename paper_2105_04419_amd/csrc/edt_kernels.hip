@@ -338,6 +338,10 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
         const int t = g.tlist[it];
         int tx, ty, tz;
         unpack_key(g.tkeys[t], tx, ty, tz);
+        // this lane's 8 table entries (row y + 8z), read now so the load
+        // overlaps the dilation; only this workgroup writes them
+        const int64_t e0 = (int64_t)t * 512 + 8 * lane;
+        const int4 ta = *(const int4*)(g.tslots + e0), tb = *(const int4*)(g.tslots + e0 + 4);
         for (int n = lane; n < NN; n += 64) {
             const int dx = n % w - TR, dy = (n / w) % w - TR, dz = n / (w * w) - TR;
             const int nt = (tx + dx < 0 || ty + dy < 0 || tz + dz < 0)
@@ -405,8 +409,6 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
         const int y = lane & 7, z = lane >> 3;
         const int by = 8 * ty + y, bz = 8 * tz + z;
         const uint32_t d = dil[lane];
-        const int64_t e0 = (int64_t)t * 512 + 8 * lane;
-        const int4 ta = *(const int4*)(g.tslots + e0), tb = *(const int4*)(g.tslots + e0 + 4);
         const int32_t ex[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
         const int nc = TR + w * (TR + w * TR);            // centre tile in nmask
         const uint32_t ob = (nmask[nc * 16 + (lane >> 2)] >> (8 * (lane & 3))) & 0xffu;
@@ -454,12 +456,13 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
                 ++slot;
             }
             // zero the occupancy and change masks of the new slots
-            // [base, base + total)
+            // [base, base + total), 16-byte stores (4 per mask of 64 bytes)
             const int64_t lo = base, hi = min((int64_t)base + total, (int64_t)g.max_blocks);
-            for (int64_t k = lo * 16 + lane; k < hi * 16; k += 64) {
-                g.occ[k] = 0u;
-                g.chg_add[k] = 0u;
-                g.chg_rem[k] = 0u;
+            const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+            for (int64_t k = lo * 4 + lane; k < hi * 4; k += 64) {
+                ((uint4*)g.occ)[k] = zero;
+                ((uint4*)g.chg_add)[k] = zero;
+                ((uint4*)g.chg_rem)[k] = zero;
             }
         }
         __syncthreads();
