@@ -274,24 +274,44 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_mark(Grid g, const int32_t
         unsigned long long rows = 0ull;
         if (i < n) rows = input_rows<BITS>(g, xyz, data, i, q, bx, by, bz, ok);
         const bool any = ((__ballot(rows != 0ull) >> (8 * sub)) & 0xffull) != 0ull;
-        bool first = false;
+        // lane q = 0 of each obstacle block finds or creates the block's tile
+        bool act = false, tnew = false;
+        int32_t t = -1;
         if (q == 0 && i < n) {
             if (!ok) {
                 set_error(g, -2 /* EDT_ERR_RANGE */);
             } else if (any) {
-                bool tnew = false;
-                const int32_t t =
-                    hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
-                if (t < 0) {
-                    set_error(g, -3 /* EDT_ERR_CAPACITY */);
-                } else {
-                    const int local = block_local(bx, by, bz);
-                    atomicOr(&g.tobst[(int64_t)t * 16 + (local >> 5)], 1u << (local & 31));
-                    if (tnew) g.tlist[atomicAdd(&g.cnt[C_NTILE], 1)] = t;
-                    first = atomicOr(&g.tflag[t], 1) == 0;
+                t = hinsert(g.tkeys, g.tmask, pack_key(bx >> 3, by >> 3, bz >> 3), &tnew);
+                if (t < 0) set_error(g, -3 /* EDT_ERR_CAPACITY */);
+                else act = true;
+            }
+        }
+        const int j = wave_append(tnew, &g.cnt[C_NTILE]);
+        if (tnew) g.tlist[j] = t;
+        // the wave's blocks of one tile merge their mask bits into one atomic
+        // per mask word, and only the first of them sets the tile's flag
+        const int local = block_local(bx, by, bz);
+        const int word = act ? local >> 5 : -1;
+        const uint32_t bit = act ? 1u << (local & 31) : 0u;
+        const int32_t tk = act ? t : -1;
+        uint32_t bits = 0u;
+        bool wlead = act, tlead = act;
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int32_t ot = __shfl(tk, 8 * s2);
+            const int ow = __shfl(word, 8 * s2);
+            const uint32_t ob = __shfl(bit, 8 * s2);
+            if (act && ot == t) {
+                if (8 * s2 < lane) tlead = false;
+                if (ow == word) {
+                    bits |= ob;
+                    if (8 * s2 < lane) wlead = false;
                 }
             }
         }
+        if (wlead) atomicOr(&g.tobst[(int64_t)t * 16 + word], bits);
+        bool first = false;
+        if (tlead) first = atomicOr(&g.tflag[t], 1) == 0;
         grow_tiles(g, first, bx >> 3, by >> 3, bz >> 3);
     }
 }
