@@ -117,8 +117,10 @@ def bench_global(args, torch, np):
 def roofline(g, dmax):
     """Dominant kernel of the global step and its algorithmic HBM bytes per
     launch, nb region blocks of 512 voxels:
-      pass_x  reads 64 B of occupancy bits, writes 1 KiB of g1 (uint16) and a
-              2 B block minimum per block;
+      pass_x  reads 64 B of occupancy bits, writes a 2 B block minimum and,
+              unless the block is D everywhere (then nothing reads it), 1 KiB
+              of g1 (uint16); the figure counts the 1 KiB for every block, an
+              upper bound;
       pass_y  reads g1 and a block minimum, writes g2 and its minimum
               (2 + 2 B per voxel, 4 B per block);
       pass_z  reads g2 and its minimum, writes s (uint16) and the int32 block

@@ -668,8 +668,10 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                     d[x] = v * v;
                 }
                 const int32_t slot = sl[M + j];
-                if (slot >= 0) {
-                    if (lane == 0) g.bmin1[slot] = (uint16_t)bmin;
+                if (lane == 0 && slot >= 0) g.bmin1[slot] = (uint16_t)bmin;
+                // a block that is D everywhere is not stored: its readers see
+                // the block minimum D and take the shared D block instead
+                if (slot >= 0 && bmin < g.D) {
                     uint4* buf = tr[j & 1];
                     buf[lane + (lane >> 3)] = make_uint4(d[0] | (d[1] << 16), d[2] | (d[3] << 16),
                                                          d[4] | (d[5] << 16), d[6] | (d[7] << 16));
@@ -1251,10 +1253,13 @@ __global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ o
     for (int k = 0; k < nxr; ++k) row[k] = (b >> k) & 1u;
 }
 
-// g1, g2 and s of voxel (x, y, z) inside the extent (absent block: D)
+// g1, g2 and s of voxel (x, y, z) inside the extent (absent block: D).  The
+// global pass X does not store g1 of a block that is D everywhere, so g1 is
+// D wherever the block minimum is.
 __device__ inline int field_g1(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
-    return slot < 0 ? g.D : g.g1[(int64_t)slot * 512 + (y & 7) + 8 * (x & 7) + 64 * (z & 7)];
+    if (slot < 0 || (int)g.bmin1[slot] >= g.D) return g.D;
+    return g.g1[(int64_t)slot * 512 + (y & 7) + 8 * (x & 7) + 64 * (z & 7)];
 }
 __device__ inline int field_g2(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
