@@ -122,7 +122,9 @@ def roofline(g, dmax):
               of g1 (uint16); the figure counts the 1 KiB for every block, an
               upper bound;
       pass_y  reads g1 and a block minimum, writes g2 and its minimum
-              (2 + 2 B per voxel, 4 B per block);
+              (2 + 2 B per voxel, 4 B per block; an upper bound, as blocks D
+              everywhere are not read, nor written in a column whose window
+              is D everywhere);
       pass_z  reads g2 and its minimum, writes s (uint16) and the int32 block
               maximum (2 + 2 B per voxel, 6 B per block)."""
     ph = g["phases"]

@@ -1199,6 +1199,25 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                 const int kg = G == 0 ? 1 : 8 * G;
                 sk.g[G] = __ballot(bm + kg * kg >= g.D);
             }
+            if (sk.d == ~0ull) {
+                // every block of the window is D everywhere, so is every
+                // output: pass Y records the block minimum D and stores no
+                // g2 (its readers take the shared D block); pass Z stores s
+                // as whole D blocks, 16 bytes per lane, and the maximum D
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t slot = __builtin_amdgcn_readfirstlane(sl[M + j]);
+                    if (slot < 0) continue;
+                    if (AXIS == 1) {
+                        if (lane == 0) g.bmin2[slot] = (uint16_t)g.D;
+                    } else {
+                        ((uint4*)(g.s + (int64_t)slot * 512))[lane] = make_uint4(Dp, Dp, Dp, Dp);
+                        if (lane == 0) g.bmax[slot] = g.D;
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
             // a block that is D everywhere reads the shared D block (cache
             // resident) instead of its own copy
             auto blk = [&](int b) -> uint4 {
@@ -1254,8 +1273,8 @@ __global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ o
 }
 
 // g1, g2 and s of voxel (x, y, z) inside the extent (absent block: D).  The
-// global pass X does not store g1 of a block that is D everywhere, so g1 is
-// D wherever the block minimum is.
+// global passes X and Y do not always store a block that is D everywhere, so
+// g1 and g2 are D wherever their block minimum is.
 __device__ inline int field_g1(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
     if (slot < 0 || (int)g.bmin1[slot] >= g.D) return g.D;
@@ -1263,7 +1282,8 @@ __device__ inline int field_g1(const Grid& g, int x, int y, int z) {
 }
 __device__ inline int field_g2(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
-    return slot < 0 ? g.D : g.g2[(int64_t)slot * 512 + (z & 7) + 8 * (x & 7) + 64 * (y & 7)];
+    if (slot < 0 || (int)g.bmin2[slot] >= g.D) return g.D;
+    return g.g2[(int64_t)slot * 512 + (z & 7) + 8 * (x & 7) + 64 * (y & 7)];
 }
 __device__ inline bool field_occ(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
