@@ -625,10 +625,23 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
         for (int j = 0; j < 8; ++j) any = any || sl[M + j] >= 0;
         if (any) {
             uint32_t b[NB];
+            uint32_t orb = 0u;
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 const int32_t s2 = sl[k];
                 b[k] = s2 >= 0 ? (uint32_t)occ8[(int64_t)s2 * 64 + lane] : 0u;
+                orb |= b[k];
+            }
+            if (!__any(orb != 0u)) {
+                // no obstacle in the strip or its context: every g1 is D,
+                // and a block that is D everywhere needs only its minimum
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t slot = sl[M + j];
+                    if (lane == 0 && slot >= 0) g.bmin1[slot] = (uint16_t)g.D;
+                }
+                __syncthreads();
+                continue;
             }
             // distance from the last voxel before the central blocks back to
             // the nearest obstacle at or before it
