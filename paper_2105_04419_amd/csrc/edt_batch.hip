@@ -476,6 +476,11 @@ edt_status edt_batch_create(const edt_batch_map* maps, int32_t n_maps, int32_t d
     b->ws = (char*)d_ws;
     // processing order: largest map first (longest-processing-time first)
     int* order = (int*)malloc(sizeof(int) * (size_t)n_maps);
+    if (!order) {
+        free(b->host_maps);
+        free(b);
+        return EDT_ERR_CAPACITY;
+    }
     for (int i = 0; i < n_maps; ++i) order[i] = i;
     for (int i = 1; i < n_maps; ++i) {   // insertion sort by volume, descending
         const int v = order[i];
