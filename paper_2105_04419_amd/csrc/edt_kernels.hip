@@ -912,13 +912,16 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
 // stores of the steps before it.
 //
 // pass Y: lane = x + 8z.  Reads g1 (layout (x + 8z) * 8 + y: one 16-byte
-// load per block and lane), writes g2 (layout (x + 8y) * 8 + z).
+// load per block and lane), writes g2 (layout (x + 8y) * 8 + z) and the
+// least g2 value of each output block (bmin2, read by the nearest-obstacle
+// query to tell blocks that are D everywhere).
 struct PassYItem {
     const Grid& g;
     const int32_t* sl;
     Envelope& env;
     int base, nb, o0, o1, qa, qb, dmax, D, lane, out_lane;
     uint16_t* dummy;
+    int bm;
 
     __device__ uint4 load(int j) const {
         const int jj = j < nb ? j : nb - 1;
@@ -944,6 +947,13 @@ struct PassYItem {
             uint16_t* dst = out ? g.g2 + (int64_t)slot * 512 + out_lane + 64 * (i & 7)
                                 : dummy + lane;
             *dst = (uint16_t)v;
+            bm = min(bm, v);
+            if (((k - dmax) & 7) == 7) {          // the step that ends an output block
+                const int m = wave_min(bm);
+                uint16_t* bd = out ? g.bmin2 + slot : dummy + 64 + lane;
+                *bd = (uint16_t)m;
+                bm = D;
+            }
         }
     }
 };
@@ -969,7 +979,7 @@ __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int
         const int nb = hb + len + ha;
         const int o0 = 8 * hb, o1 = 8 * (hb + len);
         PassYItem P{g, sl, env, R - hb, nb, o0, o1, max(0, o0 - g.dmax), min(8 * nb, o1 + g.dmax),
-                    g.dmax, g.D, lane, (lane & 7) * 8 + (lane >> 3), dummy};
+                    g.dmax, g.D, lane, (lane & 7) * 8 + (lane >> 3), dummy, g.D};
         const int jlo = P.qa >> 3, jhi = (o1 + g.dmax - 1) >> 3;
         uint4 A = P.load(jlo), B = P.load(jlo + 1);
         for (int j = jlo; j <= jhi; j += 2) {

@@ -194,7 +194,7 @@ def test_capacity_error_reported():
     assert f.error() == -3
 
 
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2])
 def test_tunnel_full_extent(seed):
     occ = workloads.tunnels(seed)
     nz, ny, nx = occ.shape

@@ -84,10 +84,13 @@ def test_tunnel_map_sample():
     check_nearest(occ, ref, xyz, got, 1024, "tunnel")
 
 
-def test_after_updates():
+@pytest.mark.parametrize("dmax", [20, 100])
+def test_after_updates(dmax):
+    # d_max 100 takes the envelope passes (radius beyond 64), whose pass Y
+    # must leave the block minima the query reads for fresh and old blocks
     occ = workloads.dense_boxes(6)
     nz, ny, nx = occ.shape
-    f = Field((nx, ny, nz), 20)
+    f = Field((nx, ny, nz), dmax)
     f.global_(torch.from_numpy(occ).cuda())
     rng = np.random.default_rng(2)
     xyz_all = all_voxels(nx, ny, nz)
@@ -100,5 +103,5 @@ def test_after_updates():
             occ[z, y, x] = v
         f.update(torch.from_numpy(xyz).cuda(), torch.from_numpy(st).cuda())
         got = f.query_nearest(torch.from_numpy(xyz_all).cuda()).cpu().numpy()
-        check_nearest(occ, oracle.edt_separable(occ, 20).reshape(-1), xyz_all, got, 400,
-                      f"after update {step}")
+        check_nearest(occ, oracle.edt_separable(occ, dmax).reshape(-1), xyz_all, got,
+                      dmax * dmax, f"after update {step} d={dmax}")

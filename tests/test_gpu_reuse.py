@@ -32,7 +32,7 @@ def sparse_map(rng, nx, ny, nz):
     return occ
 
 
-@pytest.mark.parametrize("dmax", [16, 32])
+@pytest.mark.parametrize("dmax", [16, 32, 100])
 def test_sparse_map_after_dense_map(dmax):
     rng = np.random.default_rng(dmax)
     nx, ny, nz = 96, 80, 48
