@@ -314,6 +314,22 @@ edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
                             const uint8_t* d_occ, int32_t* d_out, void* d_ws, int64_t ws_bytes,
                             void* stream);
 
+/* Allocation-free form of edt_dense_global, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and result, without the
+ * workspace: the column envelopes live in a static device buffer of the
+ * library, EDT_DENSE_STATIC_BYTES (64 MiB) on each GPU it runs on, held
+ * until the process ends.  Grids with edt_dense_workspace_bytes(nx, ny, nz)
+ * above that (more than 8,388,608 voxels, e.g. beyond 256 x 256 x 128)
+ * return EDT_ERR_CAPACITY with nothing enqueued.  Runs on the current
+ * device; `stream` must belong to it.  The call allocates nothing (its first
+ * call on a device looks up the buffer's device address).  Every call on one
+ * GPU uses the same buffer: calls that overlap on one GPU (several streams
+ * or host threads) race, and the caller must serialise them. */
+#define EDT_DENSE_STATIC_BYTES (64ll << 20)
+edt_status edt_dense_global_noalloc(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
+                                    const uint8_t* d_occ, int32_t* d_out, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Clearance cost on a dense field (paper section III, Eq. 2, clearance
  * term, in the squared-hinge form  c(p) = max(0, margin - d(p))^2).

@@ -110,6 +110,7 @@ def lib():
         "edt_batch_destroy": ([vp], ctypes.c_int),
         "edt_dense_workspace_bytes": ([i32, i32, i32], i64),
         "edt_dense_global": ([i32, i32, i32, i32, vp, vp, vp, i64, vp], ctypes.c_int),
+        "edt_dense_global_noalloc": ([i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "edt_clearance_fwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp], ctypes.c_int),
         "edt_clearance_bwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp, vp],
                               ctypes.c_int),
@@ -345,6 +346,26 @@ def dense_global(occ: torch.Tensor, d_max: int = 0, out: torch.Tensor | None = N
     _check("edt_dense_global", L.edt_dense_global(nx, ny, nz, int(d_max), _ptr(occ), _ptr(out),
                                                   _ptr(workspace), workspace.numel(),
                                                   _stream(stream)))
+    return out
+
+
+DENSE_STATIC_BYTES = 64 << 20
+
+
+def dense_global_noalloc(occ: torch.Tensor, d_max: int = 0, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """dense_global without a workspace (edt_dense_global_noalloc): the
+    library's static per-GPU buffer holds the envelopes, so grids are limited
+    to DENSE_STATIC_BYTES / 8 voxels.  Calls that overlap on one GPU race.
+    With `out` given, the call itself allocates nothing."""
+    nz, ny, nx = (int(v) for v in occ.shape)
+    occ = _dev_tensor(occ, torch.uint8, (nz, ny, nx))
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.int32, device=occ.device)
+    out = _dev_tensor(out, torch.int32, (nz, ny, nx))
+    _check("edt_dense_global_noalloc",
+           lib().edt_dense_global_noalloc(nx, ny, nz, int(d_max), _ptr(occ), _ptr(out),
+                                          _stream(stream)))
     return out
 
 

@@ -23,7 +23,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "edt.h"
+
+// Scratch of the allocation-free entry point (edt_dense_global_noalloc): the
+// column envelopes of grids up to EDT_DENSE_STATIC_BYTES / 8 voxels.  Each
+// device holds its own copy for the life of the process.  Host code never
+// passes this name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returned on
+// that device (scratch_address below).  Nothing in it has to start at zero:
+// every envelope entry is written before it is read.
+static __device__ __align__(256) unsigned char scratch[EDT_DENSE_STATIC_BYTES];
 
 namespace edt {
 
@@ -266,6 +277,43 @@ bool dense_ok(int32_t nx, int32_t ny, int32_t nz) {
     return d2 < (int64_t)edt::DINF;
 }
 
+// The three passes of the dense transform on `st`, envelopes in env.
+edt_status launch_dense(int32_t nx, int32_t ny, int32_t nz, int32_t d_max, const uint8_t* d_occ,
+                        int32_t* d_out, int2* env, hipStream_t st) {
+    using namespace edt;
+    const int32_t cap = d_max > 0 ? d_max * d_max : DINF;
+    const int nxc = (nx + 63) / 64;
+    hipLaunchKernelGGL(k_dense_x, dim3(grid_of((int64_t)ny * nz, 65536)), dim3(64), 0, st, nx, ny,
+                       nz, d_occ, d_out);
+    // chunk lengths measured on a 1024x1024x128 extent: 16 for the long y
+    // columns, 8 for z (fewer registers, more resident waves)
+    hipLaunchKernelGGL((k_dense_col<1, 16>), dim3(grid_of((int64_t)nxc * nz, 65536)), dim3(64),
+                       0, st, nx, ny, nz, d_out, env, (int32_t)DINF);
+    hipLaunchKernelGGL((k_dense_col<2, 8>), dim3(grid_of((int64_t)nxc * ny, 65536)), dim3(64), 0,
+                       st, nx, ny, nz, d_out, env, cap);
+    if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
+    return EDT_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices];
+
+edt_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return EDT_ERR_HIP;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EDT_ERR_HIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return EDT_OK;
+}
+
 }  // namespace
 
 using namespace edt;
@@ -284,20 +332,18 @@ edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
         return EDT_ERR_ARG;
     if (((uintptr_t)d_ws & 7) != 0) return EDT_ERR_ARG;
     if (ws_bytes < edt_dense_workspace_bytes(nx, ny, nz)) return EDT_ERR_CAPACITY;
-    hipStream_t st = (hipStream_t)stream;
-    const int32_t cap = d_max > 0 ? d_max * d_max : DINF;
-    int2* env = (int2*)d_ws;
-    const int nxc = (nx + 63) / 64;
-    hipLaunchKernelGGL(k_dense_x, dim3(grid_of((int64_t)ny * nz, 65536)), dim3(64), 0, st, nx, ny,
-                       nz, d_occ, d_out);
-    // chunk lengths measured on a 1024x1024x128 extent: 16 for the long y
-    // columns, 8 for z (fewer registers, more resident waves)
-    hipLaunchKernelGGL((k_dense_col<1, 16>), dim3(grid_of((int64_t)nxc * nz, 65536)), dim3(64),
-                       0, st, nx, ny, nz, d_out, env, (int32_t)DINF);
-    hipLaunchKernelGGL((k_dense_col<2, 8>), dim3(grid_of((int64_t)nxc * ny, 65536)), dim3(64), 0,
-                       st, nx, ny, nz, d_out, env, cap);
-    if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
-    return EDT_OK;
+    return launch_dense(nx, ny, nz, d_max, d_occ, d_out, (int2*)d_ws, (hipStream_t)stream);
+}
+
+edt_status edt_dense_global_noalloc(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
+                                    const uint8_t* d_occ, int32_t* d_out, void* stream) {
+    if (!dense_ok(nx, ny, nz) || d_max < 0 || d_max > 46340 || !d_occ || !d_out)
+        return EDT_ERR_ARG;
+    if (edt_dense_workspace_bytes(nx, ny, nz) > EDT_DENSE_STATIC_BYTES) return EDT_ERR_CAPACITY;
+    void* env = nullptr;
+    const edt_status e = scratch_address(&env);
+    if (e != EDT_OK) return e;
+    return launch_dense(nx, ny, nz, d_max, d_occ, d_out, (int2*)env, (hipStream_t)stream);
 }
 
 }  // extern "C"
