@@ -45,6 +45,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("voxels/s global EDT + p50/p99 incremental update latency; "
           "clearance fwd+bwd pts/s")
 HBM_PEAK_GBS = 8000.0
+STEP_FLOOR_B = 4.3
 
 
 def log(*a):
@@ -85,6 +86,10 @@ def counter_record(kernel: str, kind: str, field: str):
 
 
 def bench_global(args, torch, np):
+    """The timed steps run with nothing recorded between their kernels.  The
+    per-phase split comes from a separate run with HIP events around every
+    phase, and the dominant kernel's duration from a third run of as many
+    steps with events around that kernel only."""
     import workloads
     from paper_2105_04419_amd import Field
     occ = workloads.tunnels(args.seed)
@@ -98,20 +103,29 @@ def bench_global(args, torch, np):
     torch.cuda.synchronize()
     st = f.stats()
     assert st["error"] == 0, st
-    f.timing_begin(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f.global_blocks(xyz_d, occ_d)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+
+    def timed(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            f.global_blocks(xyz_d, occ_d)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    ms = timed(args.steps)
+    f.timing_begin(min(args.steps, 20))
+    timed(min(args.steps, 20))
     ph = f.timing_read()
+    kern = max(("pass_x", "pass_y", "pass_z"), key=lambda k: ph[k])
+    f.timing_begin(args.steps, kern)
+    ms_armed = timed(args.steps)
+    dom_ms = f.timing_read()[kern]
     f.timing_begin(0)
-    ms = (t1 - t0) * 1e3 / args.steps
     n_ext = nx * ny * nz
     n_c = st["blocks"] * 512
-    return dict(f=f, occ=occ, st=st, ms=ms, phases=ph, n_ext=n_ext, n_c=n_c,
-                n_obst_blocks=len(bxyz), xyz_d=xyz_d, occ_d=occ_d)
+    return dict(f=f, occ=occ, st=st, ms=ms, phases=ph, dominant=kern, dominant_ms=dom_ms,
+                ms_armed=ms_armed, n_ext=n_ext, n_c=n_c, n_obst_blocks=len(bxyz), xyz_d=xyz_d,
+                occ_d=occ_d)
 
 
 def roofline(g, dmax):
@@ -127,7 +141,6 @@ def roofline(g, dmax):
               is D everywhere);
       pass_z  reads g2 and its minimum, writes s (uint16) and the int32 block
               maximum (2 + 2 B per voxel, 6 B per block)."""
-    ph = g["phases"]
     nb = g["st"]["blocks"]
     per_launch = {
         "pass_x": nb * (64 + 1024 + 2),
@@ -138,8 +151,8 @@ def roofline(g, dmax):
     names = ({"pass_x": f"k_pass_x_rows<{R}>", "pass_y": f"k_pass_win_tiles<{R},1>",
               "pass_z": f"k_pass_win_tiles<{R},2>"} if R <= 8 else
              {"pass_x": "k_pass_x", "pass_y": "k_pass_y", "pass_z": "k_pass_z"})
-    kern = max(per_launch, key=lambda k: ph[k])
-    ms = ph[kern]
+    kern = g["dominant"]
+    ms = g["dominant_ms"]
     achieved = per_launch[kern] / (ms * 1e-3) / 1e9
     tr = counter_record(kern, "traffic", "traffic_bytes_per_launch")
     valu = counter_record(kern, "traffic", "valu_insts_per_launch")
@@ -153,11 +166,23 @@ def roofline(g, dmax):
         "traffic": tr,
         "algorithmic_bytes_per_launch": per_launch[kern],
         "mean_ms": round(ms, 5),
+        "timing": "HIP events around this kernel only, on its launch stream, over "
+                  "a run of as many steps as the timed run",
         # share of the VALU issue cycles of all 1024 SIMDs at 2.4 GHz that the
         # kernel's counted VALU instructions fill (4 cycles per wave64 op)
         "valu_busy_frac": (round(valu * 4 / (1024 * 2.4e9 * ms * 1e-3), 3)
                            if valu is not None else None),
     }
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_cpu(g, args, np):
@@ -175,6 +200,7 @@ def bench_cpu(g, args, np):
         "value": g["n_ext"] * reps / t_total,
         "unit": "voxels/s",
         "cores": nthreads,
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": f"separable oracle on the full {occ.shape[2]}x{occ.shape[1]}x{occ.shape[0]} "
                   f"tunnel extent, d_max {args.dmax}, {reps} run(s), {t_total:.1f} s",
@@ -462,6 +488,40 @@ def bench_integrate(g, args, torch, np):
     }
 
 
+def bench_readback(g, args, torch, np):
+    """Dense readbacks of the tunnel map (edt_read_dense: int32 field of the
+    whole extent; edt_read_occupancy: uint8).  Algorithmic bytes: the output,
+    plus the stored uint16 field (64 B of bits for the occupancy) of every
+    region block."""
+    f = g["f"]
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    nz, ny, nx = g["occ"].shape
+    out = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+    occo = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    nb = g["st"]["blocks"]
+    res = {}
+    for name, fn, nbytes in (("field_int32", lambda: f.dense(out=out), 4 * g["n_ext"] + 1024 * nb),
+                             ("occupancy_u8", lambda: f.occupancy(out=occo), g["n_ext"] + 64 * nb)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        n = 20
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "algorithmic_bytes": nbytes, "GB_per_s": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    res["field_equals_oracle"] = g.get("parity_ref") is not None and bool(
+        np.array_equal(out.cpu().numpy(), g["parity_ref"]))
+    return res
+
+
 def bench_clearance(args, torch, np):
     import workloads
     from paper_2105_04419_amd import ClearanceCost, Field
@@ -484,7 +544,24 @@ def bench_clearance(args, torch, np):
         if r >= 5:
             times.append(e0.elapsed_time(e1))
     med = pct(times, 50)
-    return {"points": n, "median_ms": round(med, 4), "pts_per_s": n / (med * 1e-3)}
+    # the two kernels alone, without autograd's dispatch between them
+    from paper_2105_04419_amd import clearance_bwd, clearance_fwd
+    gc = torch.ones(wp.shape[0], device="cuda")
+    cost = torch.empty(wp.shape[0], dtype=torch.float32, device="cuda")
+    gwp = torch.empty_like(wp)
+    dev = []
+    for r in range(args.clear_reps + 5):
+        e0.record()
+        clearance_fwd(s, wp, 0.2, 1.0, out=cost)
+        clearance_bwd(s, wp, gc, 0.2, 1.0, out=gwp)
+        e1.record()
+        e1.synchronize()
+        if r >= 5:
+            dev.append(e0.elapsed_time(e1))
+    dmed = pct(dev, 50)
+    return {"points": n, "median_ms": round(med, 4), "pts_per_s": n / (med * 1e-3),
+            "timing": "HIP events around forward + backward through torch.autograd",
+            "kernels_median_ms": round(dmed, 4), "kernels_pts_per_s": n / (dmed * 1e-3)}
 
 
 def bench_batch(args, torch, np):
@@ -517,6 +594,8 @@ def bench_batch(args, torch, np):
         "search_space": {k: v for k, v in autotune.SPACE.items()},
         "trials": len(results),
         "fused_equals_per_map": bool(torch.equal(fused, per_map)),
+        # floor: 1 B of occupancy read and 4 B of int32 written per voxel
+        "fused_hbm_frac_floor": round(5 * nvox / (t_tuned * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
     }
 
 
@@ -639,9 +718,18 @@ def main():
             "region_blocks": g["st"]["blocks"],
             "region_voxels": g["n_c"],
             "extent_voxels": g["n_ext"],
+            "voxels_counted": "the whole extent: the field covers every voxel, the blocks "
+                              "outside the computed region hold D implicitly",
         },
         "region_voxels_per_s": g["n_c"] / (g["ms"] * 1e-3),
+        # the step against a floor of 4.3 B per region voxel (an int32 field
+        # write plus occupancy and block metadata), as if the step wrote int32
+        "step_floor_frac": round(STEP_FLOOR_B * g["n_c"] / (g["ms"] * 1e-3) /
+                                 (HBM_PEAK_GBS * 1e9), 4),
+        "step_floor_bytes_per_region_voxel": STEP_FLOOR_B,
         "phases_ms": {k: round(v, 5) for k, v in g["phases"].items() if k != "calls"},
+        "phases_timing": "separate run with HIP events around every phase",
+        "ms_per_step_dominant_kernel_bracketed": round(g["ms_armed"], 5),
         "roofline": rl,
     }
     if not args.no_cpu:
@@ -650,12 +738,15 @@ def main():
         out["cpu_baseline"] = cb
         got = g["f"].dense().cpu().numpy()
         out["parity_global_vs_oracle"] = bool(np.array_equal(got, ref))
+        g["parity_ref"] = ref
         if not args.no_extra:
             log("[bench] cpu oracle, one thread")
             out["cpu_single_thread"] = bench_cpu_single(g, args, np)
             log("[bench] the paper's Algorithm 1 on one cpu thread")
             out["paper_alg1_cpu"] = bench_paper_alg1(g, args, np)
     if not args.no_extra:
+        log("[bench] dense readbacks of the tunnel map")
+        out["readback"] = bench_readback(g, args, torch, np)
         log(f"[bench] incremental: {args.scans} scans")
         out["incremental"] = bench_incremental(g, args, torch, np)
         log(f"[bench] scan integration + incremental: {args.scans} scans")

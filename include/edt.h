@@ -243,6 +243,11 @@ edt_status edt_get_error(edt_ctx* ctx, void* stream);
  * on the stream the calls were made on. */
 edt_status edt_timing_begin(edt_ctx* ctx, int32_t n_calls);
 edt_status edt_timing_read(edt_ctx* ctx, float* ms, int32_t* n_recorded);
+/* As edt_timing_begin, but only phase `phase` (0 .. 5, in the order above; -1
+ * = all) is bracketed, two events per call, so the other phases run without
+ * event records between them; edt_timing_read then reports 0 for the other
+ * phases. */
+edt_status edt_timing_begin_phase(edt_ctx* ctx, int32_t n_calls, int32_t phase);
 
 /* ------------------------------------------------------------------------ */
 /* Batched global transform of many dense maps (same definition as edt_global

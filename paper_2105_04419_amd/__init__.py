@@ -19,7 +19,8 @@ import os
 
 import torch
 
-__all__ = ["Field", "ClearanceCost", "clearance_cost", "lib", "EdtError", "LIB_PATH",
+__all__ = ["Field", "ClearanceCost", "clearance_cost", "clearance_fwd", "clearance_bwd", "lib",
+           "EdtError", "LIB_PATH",
            "Batch", "batch_global", "FUSED", "PER_MAP"]
 
 LIB_PATH = os.environ.get("EDT_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -101,6 +102,7 @@ def lib():
         "edt_get_stats": ([vp, ctypes.POINTER(EdtStats), vp], ctypes.c_int),
         "edt_get_error": ([vp, vp], ctypes.c_int),
         "edt_timing_begin": ([vp, i32], ctypes.c_int),
+        "edt_timing_begin_phase": ([vp, i32, i32], ctypes.c_int),
         "edt_timing_read": ([vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)],
                             ctypes.c_int),
         "edt_batch_workspace_bytes": ([ctypes.POINTER(EdtBatchMap), i32, i32], i64),
@@ -274,9 +276,11 @@ class Field:
                                                           _stream(stream)))
         return out
 
-    def signed_dense(self, stream=None) -> torch.Tensor:
+    def signed_dense(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         nx, ny, nz = self.shape
-        out = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+        out = _dev_tensor(out, torch.int32, (nz, ny, nx))
         _check("edt_read_signed_dense", lib().edt_read_signed_dense(self._ctx, _ptr(out),
                                                                     _stream(stream)))
         return out
@@ -289,9 +293,11 @@ class Field:
         _check("edt_read_dense", lib().edt_read_dense(self._ctx, _ptr(out), _stream(stream)))
         return out
 
-    def occupancy(self, stream=None) -> torch.Tensor:
+    def occupancy(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         nx, ny, nz = self.shape
-        out = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+        out = _dev_tensor(out, torch.uint8, (nz, ny, nx))
         _check("edt_read_occupancy", lib().edt_read_occupancy(self._ctx, _ptr(out), _stream(stream)))
         return out
 
@@ -302,10 +308,13 @@ class Field:
 
     PHASES = ("ingest", "region", "items", "pass_x", "pass_y", "pass_z")
 
-    def timing_begin(self, n_calls: int):
+    def timing_begin(self, n_calls: int, phase: str | None = None):
         """Record HIP events around the phases of the next n_calls global
-        transforms (profiling)."""
-        _check("edt_timing_begin", lib().edt_timing_begin(self._ctx, int(n_calls)))
+        transforms (profiling); with `phase` (one of PHASES) only that phase
+        is bracketed."""
+        k = -1 if phase is None else self.PHASES.index(phase)
+        _check("edt_timing_begin_phase",
+               lib().edt_timing_begin_phase(self._ctx, int(n_calls), k))
 
     def timing_read(self) -> dict:
         """Mean phase durations (ms) over the recorded calls."""
@@ -383,17 +392,42 @@ def _clearance_args(s, wp):
     return s, wp, nx, ny, nz
 
 
+def clearance_fwd(s, wp, h: float, margin: float, out=None, stream=None):
+    """edt_clearance_fwd: per-trajectory cost (float32 [T]) of waypoints
+    wp (T, W, 3) on the int32 field s (nz, ny, nx), no autograd."""
+    s, wp, nx, ny, nz = _clearance_args(s, wp)
+    T, W = int(wp.shape[0]), int(wp.shape[1])
+    if out is None:
+        out = torch.empty(T, dtype=torch.float32, device=wp.device)
+    out = _dev_tensor(out, torch.float32, (T,))
+    _check("edt_clearance_fwd", lib().edt_clearance_fwd(
+        _ptr(s), nx, ny, nz, float(h), float(margin), _ptr(wp), T, W, _ptr(out), _stream(stream)))
+    return out
+
+
+def clearance_bwd(s, wp, gcost, h: float, margin: float, out=None, stream=None):
+    """edt_clearance_bwd: gcost[t] * d C[t] / d wp (float32 (T, W, 3))."""
+    s, wp, nx, ny, nz = _clearance_args(s, wp)
+    T, W = int(wp.shape[0]), int(wp.shape[1])
+    gcost = _dev_tensor(gcost.to(torch.float32), torch.float32, (T,))
+    if out is None:
+        out = torch.empty_like(wp)
+    out = _dev_tensor(out, torch.float32, tuple(wp.shape))
+    _check("edt_clearance_bwd", lib().edt_clearance_bwd(
+        _ptr(s), nx, ny, nz, float(h), float(margin), _ptr(wp), T, W, _ptr(gcost), _ptr(out),
+        _stream(stream)))
+    return out
+
+
 class ClearanceCost(torch.autograd.Function):
     """C[t] = sum_w max(0, margin - d(wp[t, w]))^2 with d the trilinear
     interpolant of h*sqrt(s); forward and backward are HIP kernels."""
 
     @staticmethod
     def forward(ctx, s, wp, h: float, margin: float):
-        s, wp, nx, ny, nz = _clearance_args(s, wp)
-        T, W = int(wp.shape[0]), int(wp.shape[1])
-        cost = torch.empty(T, dtype=torch.float32, device=wp.device)
-        _check("edt_clearance_fwd", lib().edt_clearance_fwd(
-            _ptr(s), nx, ny, nz, float(h), float(margin), _ptr(wp), T, W, _ptr(cost), _stream()))
+        s = _dev_tensor(s, torch.int32)
+        wp = _dev_tensor(wp, torch.float32)
+        cost = clearance_fwd(s, wp, h, margin)
         ctx.save_for_backward(s, wp)
         ctx.h, ctx.margin = float(h), float(margin)
         return cost
@@ -401,14 +435,7 @@ class ClearanceCost(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gcost):
         s, wp = ctx.saved_tensors
-        nz, ny, nx = s.shape
-        T, W = int(wp.shape[0]), int(wp.shape[1])
-        gcost = gcost.contiguous().to(torch.float32)
-        gwp = torch.empty_like(wp)
-        _check("edt_clearance_bwd", lib().edt_clearance_bwd(
-            _ptr(s), nx, ny, nz, ctx.h, ctx.margin, _ptr(wp), T, W, _ptr(gcost), _ptr(gwp),
-            _stream()))
-        return None, gwp, None, None
+        return None, clearance_bwd(s, wp, gcost.contiguous(), ctx.h, ctx.margin), None, None
 
 
 def clearance_cost(s, wp, h: float = 0.2, margin: float = 1.0):

@@ -25,6 +25,7 @@ struct edt_ctx {
     hipEvent_t* ev;     // timing events, (NPHASE + 1) per recorded call
     int ev_calls;       // calls to record
     int ev_used;        // calls recorded so far
+    int ev_phase;       // phase bracketed by the events, or -1 for all of them
     int cap;            // envelope ring capacity (entries per lane)
     size_t env_lds;     // dynamic LDS bytes of the envelope passes
     int64_t tcap;       // tile hash capacity
@@ -108,9 +109,16 @@ bool layout_of(const edt_config* c, Layout* L) {
 
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
+// Workgroups of the dense readbacks: strips of RB_BLOCKS blocks along x per
+// block row (at most the number of blocks, checked by the callers).
+inline int64_t read_strips(const Grid& g) {
+    return (int64_t)((g.nbx + RB_BLOCKS - 1) / RB_BLOCKS) * g.nby * g.nbz;
+}
+
 // Event k of the current timed call (no-op unless timing is armed).
 inline void mark(edt_ctx* c, int k, hipStream_t st) {
-    if (c->ev && c->ev_used < c->ev_calls)
+    if (c->ev && c->ev_used < c->ev_calls &&
+        (c->ev_phase < 0 || k == c->ev_phase || k == c->ev_phase + 1))
         (void)hipEventRecord(c->ev[c->ev_used * (NPHASE + 1) + k], st);
 }
 
@@ -343,8 +351,11 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
                        L.ucap, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt, (int64_t)64, 0);
+    // the block of D values that the window passes read for absent blocks of
+    // g1 / g2, in their representation (binary16 for small radii)
+    const uint32_t dw = win_f16(g.R) ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int32_t*)g.dblock, (int64_t)256,
-                       (int32_t)((uint32_t)g.D | ((uint32_t)g.D << 16)));
+                       (int32_t)(dw | (dw << 16)));
     if (hipGetLastError() != hipSuccess) {
         free(c);
         return EDT_ERR_HIP;
@@ -361,8 +372,14 @@ edt_status edt_destroy(edt_ctx* ctx) {
 }
 
 edt_status edt_timing_begin(edt_ctx* c, int32_t n_calls) {
-    if (!c || n_calls < 0 || n_calls > 100000) return EDT_ERR_ARG;
+    return edt_timing_begin_phase(c, n_calls, -1);
+}
+
+edt_status edt_timing_begin_phase(edt_ctx* c, int32_t n_calls, int32_t phase) {
+    if (!c || n_calls < 0 || n_calls > 100000 || phase < -1 || phase >= NPHASE)
+        return EDT_ERR_ARG;
     free_events(c);
+    c->ev_phase = phase;
     if (n_calls == 0) return EDT_OK;
     const int ne = n_calls * (NPHASE + 1);
     c->ev = (hipEvent_t*)calloc((size_t)ne, sizeof(hipEvent_t));
@@ -388,6 +405,7 @@ edt_status edt_timing_read(edt_ctx* c, float* ms, int32_t* n_recorded) {
         hipEvent_t* e = c->ev + i * (NPHASE + 1);
         if (hipEventSynchronize(e[NPHASE]) != hipSuccess) return EDT_ERR_HIP;
         for (int k = 0; k < NPHASE; ++k) {
+            if (c->ev_phase >= 0 && k != c->ev_phase) continue;
             float t = 0.0f;
             if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess) return EDT_ERR_HIP;
             ms[k] += t / (float)c->ev_used;
@@ -604,7 +622,8 @@ edt_status edt_read_signed_dense(edt_ctx* c, int32_t* d_out, void* stream) {
     const Grid& g = c->g;
     const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
     if (nblk > 0x7fffffff) return EDT_ERR_ARG;
-    hipLaunchKernelGGL(k_read_signed, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_out);
+    hipLaunchKernelGGL(k_read_strip<RB_SIGNED>, dim3((unsigned)read_strips(g)), dim3(256), 0, S(stream), g,
+                       (void*)d_out);
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -614,7 +633,8 @@ edt_status edt_read_dense(edt_ctx* c, int32_t* d_out, void* stream) {
     const Grid& g = c->g;
     const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
     if (nblk > 0x7fffffff) return EDT_ERR_ARG;
-    hipLaunchKernelGGL(k_read_dense, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_out);
+    hipLaunchKernelGGL(k_read_strip<RB_FIELD>, dim3((unsigned)read_strips(g)), dim3(256), 0, S(stream), g,
+                       (void*)d_out);
     LAUNCH_CHECK();
     return EDT_OK;
 }
@@ -624,7 +644,8 @@ edt_status edt_read_occupancy(edt_ctx* c, uint8_t* d_occ, void* stream) {
     const Grid& g = c->g;
     const int64_t nblk = (int64_t)g.nbx * g.nby * g.nbz;
     if (nblk > 0x7fffffff) return EDT_ERR_ARG;
-    hipLaunchKernelGGL(k_read_occ, dim3((unsigned)nblk), dim3(64), 0, S(stream), g, d_occ);
+    hipLaunchKernelGGL(k_read_strip<RB_OCC>, dim3((unsigned)read_strips(g)), dim3(256), 0, S(stream), g,
+                       (void*)d_occ);
     LAUNCH_CHECK();
     return EDT_OK;
 }

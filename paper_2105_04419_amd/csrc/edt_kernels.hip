@@ -678,7 +678,9 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                 for (int x = 7; x >= 0; --x) {
                     r = (r + 1u) & ~m[x];
                     const uint32_t v = min(min(d[x], r), dmax);
-                    d[x] = v * v;
+                    d[x] = win_f16(M) ? (uint32_t)__builtin_bit_cast(unsigned short,
+                                                                     (_Float16)(v * v))
+                                      : v * v;
                 }
                 const int32_t slot = sl[M + j];
                 if (lane == 0 && slot >= 0) g.bmin1[slot] = (uint16_t)bmin;
@@ -765,11 +767,12 @@ __device__ inline void pass_x_body(const Grid& g, const int32_t* list, int list_
         const int dmax = g.dmax;
         uint16_t* dst = g.g1 + (int64_t)slot * 512 + 64 * z + y;
         int mn = dmax;
+        const bool f16 = win_f16(R);
 #pragma unroll
         for (int x = 7; x >= 0; --x) {
             if ((c >> x) & 1u) q = x;
             const int d = min(min(dl[x], q - x), dmax);
-            dst[8 * x] = (uint16_t)(d * d);
+            dst[8 * x] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)(d * d)) : (uint16_t)(d * d);
             mn = min(mn, d);
         }
         mn = wave_min(mn);
@@ -1080,7 +1083,7 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
 // row o of two consecutive blocks (low half: slot0, high half: slot1; a
 // negative slot sends its half to the wave's dummy buffer).  Pass Y writes g2
 // (z-major rows); pass Z writes s and the block maxima.
-template <int AXIS>
+template <int AXIS, bool F16>
 __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, const u16x2* acc,
                                  int lane, uint32_t* dummy) {
     if (AXIS == 1) {
@@ -1103,7 +1106,10 @@ __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, co
             mn = __builtin_elementwise_min(mn, as_u16x2((uint32_t)__shfl_xor((int)as_u32(mn), o)));
         uint16_t* f0 = slot0 >= 0 ? g.bmin2 + slot0 : (uint16_t*)(dummy + 130);
         uint16_t* f1 = slot1 >= 0 ? g.bmin2 + slot1 : (uint16_t*)(dummy + 131);
-        if (lane == 0) { *f0 = mn.x; *f1 = mn.y; }
+        if (lane == 0) {
+            *f0 = F16 ? (uint16_t)f16_int(mn.x) : mn.x;
+            *f1 = F16 ? (uint16_t)f16_int(mn.y) : mn.y;
+        }
     } else {
         uint16_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (uint16_t*)dummy + lane;
         uint16_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (uint16_t*)dummy + 64 + lane;
@@ -1112,7 +1118,8 @@ __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, co
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const uint32_t v = as_u32(acc[o]);
-            const int v0 = (int)(v & 0xffffu), v1 = (int)(v >> 16);
+            const int v0 = F16 ? f16_int(v & 0xffffu) : (int)(v & 0xffffu);
+            const int v1 = F16 ? f16_int(v >> 16) : (int)(v >> 16);
             d0[s0 * o] = (uint16_t)v0;
             d1[s1 * o] = (uint16_t)v1;
             m0 = max(m0, v0);
@@ -1137,7 +1144,9 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
     const int64_t nit = g.cnt[item_counter];
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
     uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
-    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
+    constexpr bool F16 = win_f16(M);
+    const uint32_t Dw = F16 ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
+    const uint32_t Dp = Dw | (Dw << 16);      // D in the window's representation
     for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
         const int32_t s0 = items[it];
         int bx, by, bz;
@@ -1176,9 +1185,9 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
         auto emit = [&](int ob, const u16x2* acc, bool has1) {
             const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[base + ob]);
             const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
-            win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
+            win_store<AXIS, F16>(g, slot0, slot1, acc, lane, dummy);
         };
-        window_min<M>(hb, len, Dp, blk, emit, [](int) { return true; }, sk);
+        window_min<M, false, F16>(hb, len, Dp, blk, emit, [](int) { return true; }, sk);
         __syncthreads();
     }
 }
@@ -1195,7 +1204,10 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
     const int64_t ncol = (int64_t)g.cnt[C_NTILE] * 64;
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
     uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
-    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);
+    constexpr bool F16 = win_f16(M);
+    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);       // integer D (field s)
+    const uint32_t Dw = F16 ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
+    const uint32_t Dpw = Dw | (Dw << 16);     // D in the window's representation
     for (int64_t it = blockIdx.x; it < ncol; it += gridDim.x) {
         const int32_t* ti = g.tinfo + (it >> 6) * 8;
         const int ca = (int)(it & 7), cb = (int)((it >> 3) & 7);
@@ -1253,10 +1265,10 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
             auto emit = [&](int ob, const u16x2* acc, bool) {
                 const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[M + ob]);
                 const int32_t slot1 = __builtin_amdgcn_readfirstlane(sl[M + ob + 1]);
-                win_store<AXIS>(g, slot0, slot1, acc, lane, dummy);
+                win_store<AXIS, F16>(g, slot0, slot1, acc, lane, dummy);
             };
             auto need = [&](int ob) { return sl[M + ob] >= 0 || sl[M + ob + 1] >= 0; };
-            window_min<M>(0, 8, Dp, blk, emit, need, sk);
+            window_min<M, false, F16>(0, 8, Dpw, blk, emit, need, sk);
         }
         __syncthreads();
     }
@@ -1265,34 +1277,99 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
 // ---------------------------------------------------------------------------
 // readback and query
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_read_dense(Grid g, int32_t* __restrict__ out) {
-    const int lane = threadIdx.x;
-    int bx, by, bz;
-    block_of(g.nbx, g.nby, bx, by, bz);
-    const int32_t slot = find_block(g, bx, by, bz);
-    const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
-    if (y >= g.ny || z >= g.nz) return;
-    int32_t* row = out + ((int64_t)z * g.ny + y) * (int64_t)g.nx + 8 * bx;
-    const int nxr = min(8, g.nx - 8 * bx);
-    if (slot < 0) {
-        for (int k = 0; k < nxr; ++k) row[k] = g.D;
-        return;
-    }
-    const uint16_t* src = g.s + (int64_t)slot * 512 + 8 * lane;
-    for (int k = 0; k < nxr; ++k) row[k] = src[k];
-}
+// Dense readbacks: one workgroup of four waves per strip of RB_BLOCKS blocks
+// along x (256 voxels) at one block row (by, bz).  The strip's blocks are
+// first staged in LDS with coalesced loads (a block's 1 KiB of s as one
+// 16-byte load per lane), then each wave writes whole rows of the strip, four
+// consecutive voxels per lane: one store instruction covers 1 KiB of int32
+// output (256 bytes of occupancy), so every row of the output is written
+// contiguously.  Absent blocks read D (free for the occupancy).
+constexpr int RB_BLOCKS = 32;
+enum { RB_FIELD = 0, RB_SIGNED = 1, RB_OCC = 2 };
 
-__global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ out) {
-    const int lane = threadIdx.x;
-    int bx, by, bz;
-    block_of(g.nbx, g.nby, bx, by, bz);
-    const int32_t slot = find_block(g, bx, by, bz);
-    const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
-    if (y >= g.ny || z >= g.nz) return;
-    uint8_t* row = out + ((int64_t)z * g.ny + y) * (int64_t)g.nx + 8 * bx;
-    const int nxr = min(8, g.nx - 8 * bx);
-    const uint32_t b = slot < 0 ? 0u : ((const uint8_t*)g.occ)[(int64_t)slot * 64 + lane];
-    for (int k = 0; k < nxr; ++k) row[k] = (b >> k) & 1u;
+template <int KIND>
+__global__ void __launch_bounds__(256) k_read_strip(Grid g, void* __restrict__ out) {
+    constexpr int NV = KIND == RB_OCC ? 1 : RB_BLOCKS * 65;
+    __shared__ int32_t sl[RB_BLOCKS];
+    __shared__ uint4 val[NV];                  // block b, row r at b * 65 + r (8 values of s)
+    __shared__ uint8_t bits[RB_BLOCKS * 64];   // occupancy byte of block b, row r
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nsx = (g.nbx + RB_BLOCKS - 1) / RB_BLOCKS;
+    const int64_t wg = blockIdx.x;
+    const int bx0 = (int)(wg % nsx) * RB_BLOCKS;
+    const int by = (int)((wg / nsx) % g.nby), bz = (int)((wg / nsx) / g.nby);
+    const uint8_t* occ8 = (const uint8_t*)g.occ;
+    if (t < RB_BLOCKS) sl[t] = bx0 + t < g.nbx ? find_block(g, bx0 + t, by, bz) : -1;
+    __syncthreads();
+    // stage: wave w takes blocks w, w + 4, ...; lane = row (y + 8z)
+    for (int bb = w; bb < RB_BLOCKS; bb += 4) {
+        const int32_t slot = sl[bb];
+        if (slot < 0) continue;
+        const uint8_t ob = occ8[(int64_t)slot * 64 + lane];
+        if (KIND != RB_FIELD) bits[bb * 64 + lane] = ob;
+        if (KIND == RB_OCC) continue;
+        uint4 v = ((const uint4*)(g.s + (int64_t)slot * 512))[lane];
+        if (KIND == RB_SIGNED && __any(ob != 0u)) {
+            // occupied voxels take their interior value (D without storage)
+            const int32_t ii = g.iidx[slot];
+            const uint32_t dd = (uint32_t)g.D | ((uint32_t)g.D << 16);
+            const uint4 iv = ii >= 0 ? ((const uint4*)(g.ic1 + (int64_t)ii * 512))[lane]
+                                     : make_uint4(dd, dd, dd, dd);
+            uint32_t* vw = &v.x;
+            const uint32_t* iw = &iv.x;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = (ob >> (2 * q)) & 1u ? 0x0000ffffu : 0u;
+                const uint32_t hi = (ob >> (2 * q + 1)) & 1u ? 0xffff0000u : 0u;
+                vw[q] = (vw[q] & ~(lo | hi)) | (iw[q] & (lo | hi));
+            }
+        }
+        val[bb * 65 + lane] = v;
+    }
+    __syncthreads();
+    // write: wave w takes rows w, w + 4, ...
+    const int x = 8 * bx0 + 4 * lane;
+    const int bb = lane >> 1;
+    const int32_t slot = sl[bb];
+    if (x >= g.nx) return;
+    for (int r = w; r < 64; r += 4) {
+        const int y = 8 * by + (r & 7), z = 8 * bz + (r >> 3);
+        if (y >= g.ny || z >= g.nz) continue;
+        const int64_t off = ((int64_t)z * g.ny + y) * (int64_t)g.nx + x;
+        const uint32_t ob = slot >= 0 && KIND != RB_FIELD ? (bits[bb * 64 + r] >> (4 * (lane & 1))) & 15u
+                                                          : 0u;
+        if (KIND == RB_OCC) {
+            const uint32_t v = (ob & 1u) | ((ob & 2u) << 7) | ((ob & 4u) << 14) | ((ob & 8u) << 21);
+            uint8_t* o = (uint8_t*)out + off;
+            if (x + 4 <= g.nx && ((uintptr_t)o & 3) == 0) {
+                *(uint32_t*)o = v;
+            } else {
+                for (int k = 0; k < 4 && x + k < g.nx; ++k) o[k] = (uint8_t)(v >> (8 * k));
+            }
+        } else {
+            int32_t v[4];
+            if (slot < 0) {
+                v[0] = v[1] = v[2] = v[3] = g.D;
+            } else {
+                const uint2 h = ((const uint2*)&val[bb * 65 + r])[lane & 1];
+                v[0] = (int32_t)(h.x & 0xffffu);
+                v[1] = (int32_t)(h.x >> 16);
+                v[2] = (int32_t)(h.y & 0xffffu);
+                v[3] = (int32_t)(h.y >> 16);
+                if (KIND == RB_SIGNED) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if ((ob >> k) & 1u) v[k] = -v[k];
+                }
+            }
+            int32_t* o = (int32_t*)out + off;
+            if (x + 4 <= g.nx && ((uintptr_t)o & 15) == 0) {
+                *(int4*)o = make_int4(v[0], v[1], v[2], v[3]);
+            } else {
+                for (int k = 0; k < 4 && x + k < g.nx; ++k) o[k] = v[k];
+            }
+        }
+    }
 }
 
 // g1, g2 and s of voxel (x, y, z) inside the extent (absent block: D).  The
@@ -1301,12 +1378,14 @@ __global__ void __launch_bounds__(64) k_read_occ(Grid g, uint8_t* __restrict__ o
 __device__ inline int field_g1(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
     if (slot < 0 || (int)g.bmin1[slot] >= g.D) return g.D;
-    return g.g1[(int64_t)slot * 512 + (y & 7) + 8 * (x & 7) + 64 * (z & 7)];
+    const uint16_t v = g.g1[(int64_t)slot * 512 + (y & 7) + 8 * (x & 7) + 64 * (z & 7)];
+    return win_f16(g.R) ? f16_int(v) : (int)v;
 }
 __device__ inline int field_g2(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
     if (slot < 0 || (int)g.bmin2[slot] >= g.D) return g.D;
-    return g.g2[(int64_t)slot * 512 + (z & 7) + 8 * (x & 7) + 64 * (y & 7)];
+    const uint16_t v = g.g2[(int64_t)slot * 512 + (z & 7) + 8 * (x & 7) + 64 * (y & 7)];
+    return win_f16(g.R) ? f16_int(v) : (int)v;
 }
 __device__ inline bool field_occ(const Grid& g, int x, int y, int z) {
     const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
@@ -1428,6 +1507,9 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
     const int lane = __lane_id();
     const uint32_t d2 = (uint32_t)g.D | ((uint32_t)g.D << 16);
     const uint4 dd = make_uint4(d2, d2, d2, d2);
+    // g1 and g2 hold D in their own representation (binary16 for small radii)
+    const uint32_t dw = win_f16(g.R) ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
+    const uint4 dg = make_uint4(dw | (dw << 16), dw | (dw << 16), dw | (dw << 16), dw | (dw << 16));
     while (m) {
         const int src = __ffsll((long long)m) - 1;
         m &= m - 1ull;
@@ -1437,8 +1519,8 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
             g.chg_add[s * 16 + lane] = 0u;
             g.chg_rem[s * 16 + lane] = 0u;
         }
-        ((uint4*)(g.g1 + s * 512))[lane] = dd;
-        ((uint4*)(g.g2 + s * 512))[lane] = dd;
+        ((uint4*)(g.g1 + s * 512))[lane] = dg;
+        ((uint4*)(g.g2 + s * 512))[lane] = dg;
         ((uint4*)(g.s + s * 512))[lane] = dd;
         if (lane == 0) {
             g.bmax[s] = g.D;
@@ -2326,27 +2408,6 @@ __global__ void k_query_signed(Grid g, const int32_t* __restrict__ xyz, int64_t 
         const bool in = x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
         out[i] = in ? signed_at(g, x, y, z) : g.D;
     }
-}
-
-__global__ void __launch_bounds__(64) k_read_signed(Grid g, int32_t* __restrict__ out) {
-    const int lane = threadIdx.x;
-    int bx, by, bz;
-    block_of(g.nbx, g.nby, bx, by, bz);
-    const int32_t slot = find_block(g, bx, by, bz);
-    const int y = 8 * by + (lane & 7), z = 8 * bz + (lane >> 3);
-    if (y >= g.ny || z >= g.nz) return;
-    int32_t* row = out + ((int64_t)z * g.ny + y) * (int64_t)g.nx + 8 * bx;
-    const int nxr = min(8, g.nx - 8 * bx);
-    if (slot < 0) {
-        for (int k = 0; k < nxr; ++k) row[k] = g.D;
-        return;
-    }
-    const uint32_t b = ((const uint8_t*)g.occ)[(int64_t)slot * 64 + lane];
-    const int32_t ii = g.iidx[slot];
-    const uint16_t* sv = g.s + (int64_t)slot * 512 + 8 * lane;
-    const uint16_t* iv = ii >= 0 ? g.ic1 + (int64_t)ii * 512 + 8 * lane : nullptr;
-    for (int k = 0; k < nxr; ++k)
-        row[k] = ((b >> k) & 1u) ? -(iv ? (int32_t)iv[k] : g.D) : (int32_t)sv[k];
 }
 
 __global__ void k_clear_error(Grid g) { g.cnt[C_ERR] = 0; }

@@ -14,6 +14,18 @@
 // every load and store unconditional (absent blocks read a block of D values,
 // halo outputs go to a scratch row) so the loop issues a fixed sequence of
 // memory operations.
+//
+// Half-precision mode (F16, for d_max <= 40, so D <= 1600): the values are
+// held as IEEE binary16 instead of integers.  Every integer up to 2048 is
+// exact in binary16, so inputs (<= D), squares of offsets and every candidate
+// sum below 2048 are exact; a candidate whose exact sum is 2048 or more
+// rounds to a value >= 2048 > D, so it can never beat an output, which stays
+// <= D.  The results are therefore the same integers.  Non-negative binary16
+// values order like their bit patterns, so the mins of the two candidates of
+// an offset stay integer mins on the bits; the additions are binary16, and
+// the candidates of two offsets join an output with one three-way minimum
+// (v_pk_minimum3_f16), 2.5 instructions per offset and output pair instead of
+// 3.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,9 +33,26 @@
 namespace edt {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
 __device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 __device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline h16x2 as_h16x2(u16x2 v) { return __builtin_bit_cast(h16x2, v); }
+__device__ inline u16x2 as_u16x2(h16x2 v) { return __builtin_bit_cast(u16x2, v); }
+
+// Block radii whose intermediates (g1, g2) are stored as binary16.
+__host__ __device__ constexpr bool win_f16(int M) { return M <= 5; }
+
+// binary16 bit pattern of an integer 0 <= n <= 2048 (exact).
+__host__ __device__ constexpr uint32_t f16_bits(uint32_t n) {
+    uint32_t e = 0;
+    while ((2u << e) <= n) ++e;                // n in [2^e, 2^(e+1))
+    return n == 0 ? 0u : ((e + 15u) << 10) | ((n << (10u - e)) & 0x3ffu);
+}
+// Integer value of a binary16 bit pattern holding an integer <= 2048.
+__device__ inline int f16_int(uint32_t bits) {
+    return (int)(unsigned short)__builtin_bit_cast(_Float16, (unsigned short)bits);
+}
 __device__ inline uint32_t word_of(const uint4& v, int w) {
     return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
 }
@@ -53,15 +82,32 @@ struct WinSkip {
 // output) and skip the group when no lane can improve.  It pays on maps where
 // most groups are decided that way (dense maps), not where the block bounds
 // already skip them.
-template <int M, bool LB = false, class Blk, class Emit, class Need>
+// F16: values are binary16 bit patterns (see above); Dp then holds D as two
+// binary16 halves, and so do the outputs handed to emit.
+template <int M, bool LB = false, bool F16 = false, class Blk, class Emit, class Need>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit,
                                   Need&& need, const WinSkip& sk) {
     constexpr int NW = 2 * M + 2;        // window blocks
     constexpr int K = 8 * M - 1;         // largest offset
     constexpr int NP = 8 * (NW - 1);     // input pairs: positions p = -8M .. 8M + 7
-    uint4 W[NW];
+    // P[q]: (in(p), in(p + 8)) for p = q - 8M relative to the step's first
+    // output, packed.  The window slides by 16 positions per step, so all but
+    // the last 16 pairs of a step are the previous step's pairs moved down;
+    // only the newest input block (Wl) is kept besides P.
+    u16x2 P[NP];
+    uint4 Wl;
+    {
+        uint4 W[NW];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) W[w] = blk(first - M + w);
+        for (int w = 0; w < NW; ++w) W[w] = blk(first - M + w);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int b = q >> 3, z = q & 7;
+            const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
+            P[q] = as_u16x2(__builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
+        }
+        Wl = W[NW - 1];
+    }
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
         if (need(ob)) {
@@ -78,15 +124,6 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
 #pragma unroll
                 for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
             } else {
-                // P[q]: (in(p), in(p + 8)) for p = q - 8M, packed
-                u16x2 P[NP];
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const int b = q >> 3, z = q & 7;
-                    const uint32_t lo = word_of(W[b], z >> 1), hi = word_of(W[b + 1], z >> 1);
-                    P[q] = as_u16x2(
-                        __builtin_amdgcn_perm(hi, lo, (z & 1) ? 0x07060302u : 0x05040100u));
-                }
 #pragma unroll
                 for (int o = 0; o < 8; ++o) acc[o] = P[o + 8 * M];
                 // offsets outward in groups of 8: group G (k = 8G .. 8G + 7,
@@ -115,28 +152,63 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
 #pragma unroll
                         for (int q = 8 * M + 8 * G; q <= 8 * M + 8 * G + 14 && q < NP; ++q)
                             lb = __builtin_elementwise_min(lb, P[q]);
-                        const unsigned short g2 = (unsigned short)(64 * G * G);
-                        lb = lb + (u16x2){g2, g2};
+                        if (F16) {
+                            const _Float16 g2 = (_Float16)(64 * G * G);
+                            lb = as_u16x2(as_h16x2(lb) + (h16x2){g2, g2});
+                        } else {
+                            const unsigned short g2 = (unsigned short)(64 * G * G);
+                            lb = lb + (u16x2){g2, g2};
+                        }
                         if (!__any(lb.x < mx.x || lb.y < mx.y)) continue;
                     }
+                    const int k0 = G == 0 ? 1 : 8 * G, k1 = 8 * G + 7;
+                    if (F16) {
+                        // offsets in pairs: two candidates and the output meet
+                        // in one three-way minimum
 #pragma unroll
-                    for (int k = (G == 0 ? 1 : 8 * G); k <= 8 * G + 7; ++k) {
-                        const unsigned short kk = (unsigned short)(k * k);
-                        u16x2 m[8];
+                        for (int k = k0; k <= k1; k += 2) {
+                            const _Float16 ka = (_Float16)(k * k);
+                            const _Float16 kb = (_Float16)((k + 1) * (k + 1));
 #pragma unroll
-                        for (int o = 0; o < 8; ++o)
-                            m[o] = __builtin_elementwise_min(P[o + 8 * M - k], P[o + 8 * M + k]) +
-                                   (u16x2){kk, kk};
+                            for (int o = 0; o < 8; ++o) {
+                                const h16x2 ca = as_h16x2(__builtin_elementwise_min(
+                                                     P[o + 8 * M - k], P[o + 8 * M + k])) +
+                                                 (h16x2){ka, ka};
+                                h16x2 a = __builtin_elementwise_minimum(as_h16x2(acc[o]), ca);
+                                if (k + 1 <= k1) {
+                                    const h16x2 cb = as_h16x2(__builtin_elementwise_min(
+                                                         P[o + 8 * M - k - 1],
+                                                         P[o + 8 * M + k + 1])) +
+                                                     (h16x2){kb, kb};
+                                    a = __builtin_elementwise_minimum(a, cb);
+                                }
+                                acc[o] = as_u16x2(a);
+                            }
+                        }
+                    } else {
 #pragma unroll
-                        for (int o = 0; o < 8; ++o) acc[o] = __builtin_elementwise_min(acc[o], m[o]);
+                        for (int k = k0; k <= k1; ++k) {
+                            const unsigned short kk = (unsigned short)(k * k);
+                            u16x2 m[8];
+#pragma unroll
+                            for (int o = 0; o < 8; ++o)
+                                m[o] = __builtin_elementwise_min(P[o + 8 * M - k],
+                                                                 P[o + 8 * M + k]) +
+                                       (u16x2){kk, kk};
+#pragma unroll
+                            for (int o = 0; o < 8; ++o)
+                                acc[o] = __builtin_elementwise_min(acc[o], m[o]);
+                        }
                     }
                     // stop once no output of the wave can still drop, i.e. all
                     // are <= (8G + 8)^2, the least any further candidate adds
+                    // (binary16 patterns order like their values)
                     if (G + 1 < M) {
                         mx = __builtin_elementwise_max(acc[0], acc[1]);
 #pragma unroll
                         for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
-                        const int lim = (8 * G + 8) * (8 * G + 8);
+                        const uint32_t sq = (8 * G + 8) * (8 * G + 8);
+                        const int lim = F16 ? (int)f16_bits(sq) : (int)sq;
                         const bool more = (int)mx.x > lim || (int)mx.y > lim;
                         if (!__any(more)) break;
                     }
@@ -144,16 +216,25 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
             }
             emit(ob, acc, ob + 1 < first + count);
         }
+        // slide: pairs move down by 16 positions; the 16 new ones pair the
+        // old last block with N0 and N0 with N1
 #pragma unroll
-        for (int w = 0; w + 2 < NW; ++w) W[w] = W[w + 2];
-        W[NW - 2] = N0;
-        W[NW - 1] = N1;
+        for (int q = 0; q + 16 < NP; ++q) P[q] = P[q + 16];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            const uint32_t sel = (z & 1) ? 0x07060302u : 0x05040100u;
+            P[NP - 16 + z] = as_u16x2(__builtin_amdgcn_perm(word_of(N0, z >> 1),
+                                                            word_of(Wl, z >> 1), sel));
+            P[NP - 8 + z] = as_u16x2(__builtin_amdgcn_perm(word_of(N1, z >> 1),
+                                                           word_of(N0, z >> 1), sel));
+        }
+        Wl = N1;
     }
 }
 
-template <int M, bool LB = false, class Blk, class Emit>
+template <int M, bool LB = false, bool F16 = false, class Blk, class Emit>
 __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, Emit&& emit) {
-    window_min<M, LB>(first, count, Dp, blk, emit, [](int) { return true; }, WinSkip{});
+    window_min<M, LB, F16>(first, count, Dp, blk, emit, [](int) { return true; }, WinSkip{});
 }
 
 }  // namespace edt
