@@ -162,44 +162,53 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                         if (!__any(lb.x < mx.x || lb.y < mx.y)) continue;
                     }
                     const int k0 = G == 0 ? 1 : 8 * G, k1 = 8 * G + 7;
-                    if (F16) {
-                        // offsets in pairs: two candidates and the output meet
-                        // in one three-way minimum
+                    // one side of the group can be skipped on its own: the
+                    // candidates of offsets -k then come from the blocks
+                    // before the outputs only, those of +k from the blocks
+                    // after them only (side 0 both, 1 minus, 2 plus)
+                    const uint64_t CL = 7ull << (M - G - 1), CR = 7ull << (M + G);
+                    const bool skipL = ((sk.g[G] >> sh) & CL) == CL;
+                    const bool skipR = ((sk.g[G] >> sh) & CR) == CR;
+                    auto cand = [&](int o, int k, int side) -> u16x2 {
+                        return side == 1 ? P[o + 8 * M - k]
+                             : side == 2 ? P[o + 8 * M + k]
+                                         : __builtin_elementwise_min(P[o + 8 * M - k],
+                                                                     P[o + 8 * M + k]);
+                    };
+                    auto run = [&](int side) {
+                        if (F16) {
+                            // offsets in pairs: two candidates and the output
+                            // meet in one three-way minimum
 #pragma unroll
-                        for (int k = k0; k <= k1; k += 2) {
-                            const _Float16 ka = (_Float16)(k * k);
-                            const _Float16 kb = (_Float16)((k + 1) * (k + 1));
+                            for (int k = k0; k <= k1; k += 2) {
+                                const _Float16 ka = (_Float16)(k * k);
+                                const _Float16 kb = (_Float16)((k + 1) * (k + 1));
 #pragma unroll
-                            for (int o = 0; o < 8; ++o) {
-                                const h16x2 ca = as_h16x2(__builtin_elementwise_min(
-                                                     P[o + 8 * M - k], P[o + 8 * M + k])) +
-                                                 (h16x2){ka, ka};
-                                h16x2 a = __builtin_elementwise_minimum(as_h16x2(acc[o]), ca);
-                                if (k + 1 <= k1) {
-                                    const h16x2 cb = as_h16x2(__builtin_elementwise_min(
-                                                         P[o + 8 * M - k - 1],
-                                                         P[o + 8 * M + k + 1])) +
-                                                     (h16x2){kb, kb};
-                                    a = __builtin_elementwise_minimum(a, cb);
+                                for (int o = 0; o < 8; ++o) {
+                                    const h16x2 ca = as_h16x2(cand(o, k, side)) + (h16x2){ka, ka};
+                                    h16x2 a = __builtin_elementwise_minimum(as_h16x2(acc[o]), ca);
+                                    if (k + 1 <= k1) {
+                                        const h16x2 cb =
+                                            as_h16x2(cand(o, k + 1, side)) + (h16x2){kb, kb};
+                                        a = __builtin_elementwise_minimum(a, cb);
+                                    }
+                                    acc[o] = as_u16x2(a);
                                 }
-                                acc[o] = as_u16x2(a);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = k0; k <= k1; ++k) {
+                                const unsigned short kk = (unsigned short)(k * k);
+#pragma unroll
+                                for (int o = 0; o < 8; ++o)
+                                    acc[o] = __builtin_elementwise_min(
+                                        acc[o], cand(o, k, side) + (u16x2){kk, kk});
                             }
                         }
-                    } else {
-#pragma unroll
-                        for (int k = k0; k <= k1; ++k) {
-                            const unsigned short kk = (unsigned short)(k * k);
-                            u16x2 m[8];
-#pragma unroll
-                            for (int o = 0; o < 8; ++o)
-                                m[o] = __builtin_elementwise_min(P[o + 8 * M - k],
-                                                                 P[o + 8 * M + k]) +
-                                       (u16x2){kk, kk};
-#pragma unroll
-                            for (int o = 0; o < 8; ++o)
-                                acc[o] = __builtin_elementwise_min(acc[o], m[o]);
-                        }
-                    }
+                    };
+                    if (!skipL && !skipR) run(0);
+                    else if (!skipL) run(1);
+                    else run(2);
                     // stop once no output of the wave can still drop, i.e. all
                     // are <= (8G + 8)^2, the least any further candidate adds
                     // (binary16 patterns order like their values)
