@@ -512,8 +512,11 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
     hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
     hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
-    hipLaunchKernelGGL(k_seed_box, dim3(grid_for(n, 1, 4096)), dim3(64), 0, st, g);
-    hipLaunchKernelGGL(k_upd_mark, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
+    // fronts: one workgroup per seed block (at most one per change entry),
+    // wide enough for the seed's whole neighbourhood when it has at most 1024
+    // blocks
+    const int fwg = w3 <= 256 ? 256 : (w3 <= 512 ? 512 : 1024);
+    hipLaunchKernelGGL(k_upd_fronts, dim3(grid_for(n, 1, 4096)), dim3(fwg), 0, st, g);
     // short work items: the recompute sets are small, and short runs give
     // more waves to hide each item's latency
     Grid gu = g;
@@ -523,8 +526,6 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
                        0, st, gu, nxw);
     launch_pass(c, gu, 1, st, g.list_yi, (int)C_NYI, (uint32_t)F_YS);
     launch_pass(c, gu, 2, st, g.list_zi, (int)C_NZI, (uint32_t)F_DIRTY);
-    hipLaunchKernelGGL(k_upd_cleanup, dim3(grid_for(n > mb ? n : mb, 256, 4096)), dim3(256), 0, st,
-                       g, n, n_dev);
     LAUNCH_CHECK();
     return EDT_OK;
 }

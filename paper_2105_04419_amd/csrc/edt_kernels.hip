@@ -908,6 +908,19 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
     while (ha < R && sl[R + len + ha] >= 0) ++ha;
 }
 
+// An incremental pass is done with the run's own blocks (sl[R .. R + len))
+// once its outputs are stored: pass Y clears their g1 / g2 marks and the seed
+// mark, pass Z the front marks, so the next update starts with clean flags.
+// Runs of one pass never share a block, and a run only reads the membership
+// of its own blocks, so clearing cannot change another run.
+__device__ inline void finish_run(const Grid& g, const int32_t* sl, int len, int axis,
+                                  uint32_t runflag) {
+    if (runflag == 0u) return;                  // global transform: no marks
+    const uint32_t clear = axis == 1 ? (F_YS | F_XS | F_SEED) : (F_DIRTY | F_RAISE | F_LOWER);
+    const int lane = threadIdx.x;
+    if (lane < len) atomicAnd(&g.flags[sl[g.R + lane]], ~clear);
+}
+
 // The envelope passes walk the blocks of a work item two at a time with two
 // explicit input buffers (no register copies), and every step issues exactly
 // one global store (halo steps store to a per-wave scratch row), so the
@@ -992,6 +1005,7 @@ __global__ void __launch_bounds__(64) k_pass_y(Grid g, const int32_t* items, int
             P.block(B, j + 1);
             B = P.load(j + 3);
         }
+        finish_run(g, sl, len, 1, runflag);
         __syncthreads();
     }
 }
@@ -1072,6 +1086,7 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
             P.block(B, j + 1);
             B = P.load(j + 3);
         }
+        finish_run(g, sl, len, 2, runflag);
         __syncthreads();
     }
 }
@@ -1188,6 +1203,7 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
             win_store<AXIS, F16>(g, slot0, slot1, acc, lane, dummy);
         };
         window_min<M, false, F16>(hb, len, Dp, blk, emit, [](int) { return true; }, sk);
+        finish_run(g, sl, len, AXIS, runflag);
         __syncthreads();
     }
 }
@@ -1559,17 +1575,34 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
 }
 
 // Apply the winning entries: flip occupancy bits, record the changed voxels
-// per block (the wave centres) and list the blocks that hold them.
+// per block (the wave centres) and list the blocks that hold them.  The
+// voxel-keyed dedupe table is emptied here for the next call: each winner
+// clears its entry once it has read it (the entries that lose to it only
+// ever compare the stored index with their own), and a cancelled call clears
+// the entry of every input.
 __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
                             const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
                             int32_t gen) {
-    if (g.cnt[C_UABORT] == gen) return;
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    if (g.cnt[C_UABORT] == gen) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t h = g.upos[i];
+            if (h >= 0) {
+                g.ukeys[h] = KEY_EMPTY;
+                g.uvals[h] = -1;
+            }
+        }
+        return;
+    }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         bool add = false, rem = false, first_seed = false, new_dil = false;
         int32_t slot = -1;
         if (upd_winner(g, i)) {
+            const int32_t h = g.upos[i];
+            g.ukeys[h] = KEY_EMPTY;
+            g.uvals[h] = -1;
             const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
             slot = find_block(g, x >> 3, y >> 3, z >> 3);
             if (slot >= 0) {
@@ -1662,32 +1695,6 @@ __device__ inline int32_t row_box(uint32_t byte) {
     return xmn | (xmx << 4) | (ymn << 8) | (ymx << 12) | (zmn << 16) | (zmx << 20) | (1 << 24);
 }
 
-// One wave per seed block: the bounding boxes of its added and removed
-// voxels, its coordinates and, for d_max <= 64 (fronts reach at most one
-// tile beyond the seed's), the positions of the 27 tiles around its tile.
-__global__ void __launch_bounds__(64) k_seed_box(Grid g) {
-    const int64_t n = g.cnt[C_NSEED];
-    const int lane = threadIdx.x;
-    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
-        const int32_t slot = g.list_seed[s];
-        const uint32_t a = ((const uint8_t*)g.chg_add)[(int64_t)slot * 64 + lane];
-        const uint32_t r = ((const uint8_t*)g.chg_rem)[(int64_t)slot * 64 + lane];
-        int sx, sy, sz;
-        unpack_key(g.bkey[slot], sx, sy, sz);
-        const int32_t ba = row_box(a);
-        const int32_t br = row_box(r);
-        int32_t* rec = g.seed_box + s * 32;
-        if (lane == 0) *(int4*)rec = make_int4(ba, br, sx, sy);
-        if (lane == 1) *(int4*)(rec + 4) = make_int4(sz, 0, 0, 0);
-        if (g.R <= 8 && lane < 27) {
-            const int tx = (sx >> 3) + lane % 3 - 1, ty = (sy >> 3) + (lane / 3) % 3 - 1,
-                      tz = (sz >> 3) + lane / 9 - 1;
-            rec[5 + lane] = (tx < 0 || ty < 0 || tz < 0) ? -1
-                                                         : hpos(g.tkeys, g.tmask, pack_key(tx, ty, tz));
-        }
-    }
-}
-
 // squared distance between voxel boxes [a0,a1] and [b0,b1] per axis
 __device__ inline int box_gap2(int a0, int a1, int b0, int b1) {
     const int d = max(0, max(b0 - a1, a0 - b1));
@@ -1701,132 +1708,140 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
            box_gap2(zmn, zmx, 8 * bz, 8 * bz + 7);
 }
 
-// Raise / lower fronts around every seed and the g1/g2 recompute sets.
+// Raise / lower fronts around every seed and the g1/g2 recompute sets.  One
+// workgroup (up to 1024 threads: every block within R of the seed at once for
+// d_max <= 32) per seed block: its first wave takes the bounding boxes of the
+// seed's added and removed voxels (and, for d_max <= 64, the positions of the
+// 27 tiles around its tile, since the fronts reach at most one tile beyond
+// it), then every thread marks blocks within R of the seed:
 //   lower: some added voxel a has |box(B) - a|^2 < bmax(B)   (a value can drop)
 //   raise: some removed voxel r has |box(B) - r|^2 <= bmax(B) and < D
 //   xs:    blocks within R along x of a seed (their g1 can change)
 //   ys:    blocks within R in x and y of a seed (their g2 can change)
-__global__ void __launch_bounds__(256) k_upd_mark(Grid g) {
-    __shared__ int wcnt[4][5];      // per wave: dirty, ys, xs, raise, lower
-    __shared__ int bbase[3];        // the block's list positions
+// The seed's change masks are emptied for the next call once read, and the
+// call's cancel flag is cleared (no later kernel of the update tests it).
+__global__ void __launch_bounds__(1024) k_upd_fronts(Grid g) {
+    __shared__ int32_t rec[32];     // boxes, block coordinates, 27 tile positions
+    __shared__ int wcnt[16][5];     // per wave: dirty, ys, xs, raise, lower
+    __shared__ int bbase[3];        // the workgroup's list positions
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
-    const int64_t total = (int64_t)g.cnt[C_NSEED] * w3;
-    const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    for (int64_t b0 = blockIdx.x * (int64_t)blockDim.x; b0 < total;
-         b0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = b0 + threadIdx.x;
-        bool new_dirty = false, new_xs = false, new_ys = false, raise = false, lower = false;
-        int32_t slot = -1;
-        if (i < total) {
-            const int64_t si = i / w3;
-            const int o = (int)(i % w3);
-            const int32_t* rec = g.seed_box + si * 32;
-            const int4 r0 = *(const int4*)rec;
-            const int32_t pa = r0.x, pr = r0.y, sx = r0.z, sy = r0.w, sz = rec[4];
-            const int ox = o % w - R, oy = (o / w) % w - R, oz = o / (w * w) - R;
-            const int bx = sx + ox, by = sy + oy, bz = sz + oz;
-            // box distances need no loads: a block beyond D of both boxes can
-            // only join the g1 / g2 sets (its own x row or xy plane of the seed)
-            const int da = pa != 0 ? box_dist2(pa, sx, sy, sz, bx, by, bz) : 0x7fffffff;
-            const int dr = pr != 0 ? box_dist2(pr, sx, sy, sz, bx, by, bz) : 0x7fffffff;
-            const bool maybe = da < g.D || dr < g.D || oz == 0;
-            if (!maybe) {
-            } else if (R <= 8) {
-                // the block's tile among the 27 recorded around the seed's tile
-                if (bx >= 0 && by >= 0 && bz >= 0) {
-                    const int k = ((bx >> 3) - (sx >> 3) + 1) + 3 * ((by >> 3) - (sy >> 3) + 1) +
-                                  9 * ((bz >> 3) - (sz >> 3) + 1);
-                    const int32_t t = rec[5 + k];
-                    if (t >= 0) slot = g.tslots[(int64_t)t * 512 + block_local(bx, by, bz)];
-                }
-            } else {
-                slot = find_block(g, bx, by, bz);
-            }
-            if (slot >= 0) {
-                const int bm = g.bmax[slot];
-                const uint32_t seen = g.flags[slot];   // bits only get set in this kernel
-                lower = da < bm;
-                raise = dr <= bm && dr < g.D;
-                uint32_t want = 0;
-                if (lower) want |= F_LOWER | F_DIRTY;
-                if (raise) want |= F_RAISE | F_DIRTY;
-                if (oz == 0) want |= F_YS;
-                if (oz == 0 && oy == 0) want |= F_XS;
-                if (!(want & ~seen)) {
-                    raise = lower = false;              // already marked by another seed
-                } else {
-                    const uint32_t old = atomicOr(&g.flags[slot], want);
-                    new_dirty = (want & F_DIRTY) && !(old & F_DIRTY);
-                    new_ys = (want & F_YS) && !(old & F_YS);
-                    new_xs = (want & F_XS) && !(old & F_XS);
-                    raise = raise && !(old & F_RAISE);
-                    lower = lower && !(old & F_LOWER);
-                }
-            }
-        }
-        // list appends and statistics: one counter atomic per list and
-        // workgroup, positions from the waves' ballots
-        const unsigned long long md = __ballot(new_dirty), my = __ballot(new_ys),
-                                 mx = __ballot(new_xs), mr = __ballot(raise), ml = __ballot(lower);
-        if (lane == 0) {
-            wcnt[wid][0] = __popcll(md);
-            wcnt[wid][1] = __popcll(my);
-            wcnt[wid][2] = __popcll(mx);
-            wcnt[wid][3] = __popcll(mr);
-            wcnt[wid][4] = __popcll(ml);
-        }
-        __syncthreads();
-        if (threadIdx.x < 5) {
-            const int c = threadIdx.x;
-            const int sum = wcnt[0][c] + wcnt[1][c] + wcnt[2][c] + wcnt[3][c];
-            const int ctr = c == 0 ? C_NDIRTY : c == 1 ? C_NYS : c == 2 ? C_NXS
-                          : c == 3 ? C_NRAISE : C_NLOWER;
-            const int base = sum ? atomicAdd(&g.cnt[ctr], sum) : 0;
-            if (c < 3) bbase[c] = base;
-        }
-        __syncthreads();
-        int bd = bbase[0], by_ = bbase[1], bx_ = bbase[2];
-        for (int v = 0; v < wid; ++v) {
-            bd += wcnt[v][0];
-            by_ += wcnt[v][1];
-            bx_ += wcnt[v][2];
-        }
-        const unsigned long long below = (1ull << lane) - 1ull;
-        if (new_dirty) g.list_dirty[bd + __popcll(md & below)] = slot;
-        if (new_ys) g.list_ys[by_ + __popcll(my & below)] = slot;
-        if (new_xs) g.list_xs[bx_ + __popcll(mx & below)] = slot;
-        __syncthreads();
-    }
-}
-
-// Clear per-update state: dedupe table entries, change masks and flags.
-__global__ void k_upd_cleanup(Grid g, int64_t n0, const int32_t* n_dev) {
-    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
-    // no other workgroup of this kernel touches the cancel flag: one thread
-    // clears it, so a replayed copy of the update (a captured graph, whose
-    // call number is fixed) starts uncancelled too
-    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_UABORT] = 0;
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < n; i += stride) {
-        const int32_t h = g.upos[i];
-        if (h >= 0) {
-            g.ukeys[h] = KEY_EMPTY;
-            g.uvals[h] = -1;
-        }
-    }
     const int64_t ns = g.cnt[C_NSEED];
-    for (int64_t i = tid; i < ns * 16; i += stride) {
-        const int32_t slot = g.list_seed[i / 16];
-        g.chg_add[(int64_t)slot * 16 + (i % 16)] = 0u;
-        g.chg_rem[(int64_t)slot * 16 + (i % 16)] = 0u;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_UABORT] = 0;
+    for (int64_t si = blockIdx.x; si < ns; si += gridDim.x) {
+        if (wid == 0) {
+            const int32_t seed = g.list_seed[si];
+            const uint32_t a = ((const uint8_t*)g.chg_add)[(int64_t)seed * 64 + lane];
+            const uint32_t r = ((const uint8_t*)g.chg_rem)[(int64_t)seed * 64 + lane];
+            int sx, sy, sz;
+            unpack_key(g.bkey[seed], sx, sy, sz);
+            const int32_t ba = row_box(a);
+            const int32_t br = row_box(r);
+            if (lane < 16) {
+                g.chg_add[(int64_t)seed * 16 + lane] = 0u;
+                g.chg_rem[(int64_t)seed * 16 + lane] = 0u;
+            }
+            if (lane == 0) {
+                rec[0] = ba;
+                rec[1] = br;
+                rec[2] = sx;
+                rec[3] = sy;
+                rec[4] = sz;
+            }
+            if (R <= 8 && lane < 27) {
+                const int tx = (sx >> 3) + lane % 3 - 1, ty = (sy >> 3) + (lane / 3) % 3 - 1,
+                          tz = (sz >> 3) + lane / 9 - 1;
+                rec[5 + lane] = (tx < 0 || ty < 0 || tz < 0)
+                                    ? -1
+                                    : hpos(g.tkeys, g.tmask, pack_key(tx, ty, tz));
+            }
+        }
+        __syncthreads();
+        const int32_t pa = rec[0], pr = rec[1], sx = rec[2], sy = rec[3], sz = rec[4];
+        for (int o0 = 0; o0 < w3; o0 += blockDim.x) {
+            const int o = o0 + (int)threadIdx.x;
+            bool new_dirty = false, new_xs = false, new_ys = false, raise = false, lower = false;
+            int32_t slot = -1;
+            if (o < w3) {
+                const int ox = o % w - R, oy = (o / w) % w - R, oz = o / (w * w) - R;
+                const int bx = sx + ox, by = sy + oy, bz = sz + oz;
+                // box distances need no loads: a block beyond D of both boxes
+                // can only join the g1 / g2 sets (its own x row or xy plane of
+                // the seed)
+                const int da = pa != 0 ? box_dist2(pa, sx, sy, sz, bx, by, bz) : 0x7fffffff;
+                const int dr = pr != 0 ? box_dist2(pr, sx, sy, sz, bx, by, bz) : 0x7fffffff;
+                const bool maybe = da < g.D || dr < g.D || oz == 0;
+                if (!maybe) {
+                } else if (R <= 8) {
+                    // the block's tile among the 27 recorded around the seed's tile
+                    if (bx >= 0 && by >= 0 && bz >= 0) {
+                        const int k = ((bx >> 3) - (sx >> 3) + 1) + 3 * ((by >> 3) - (sy >> 3) + 1) +
+                                      9 * ((bz >> 3) - (sz >> 3) + 1);
+                        const int32_t t = rec[5 + k];
+                        if (t >= 0) slot = g.tslots[(int64_t)t * 512 + block_local(bx, by, bz)];
+                    }
+                } else {
+                    slot = find_block(g, bx, by, bz);
+                }
+                if (slot >= 0) {
+                    const int bm = g.bmax[slot];
+                    const uint32_t seen = g.flags[slot];   // bits only get set in this kernel
+                    lower = da < bm;
+                    raise = dr <= bm && dr < g.D;
+                    uint32_t want = 0;
+                    if (lower) want |= F_LOWER | F_DIRTY;
+                    if (raise) want |= F_RAISE | F_DIRTY;
+                    if (oz == 0) want |= F_YS;
+                    if (oz == 0 && oy == 0) want |= F_XS;
+                    if (!(want & ~seen)) {
+                        raise = lower = false;              // already marked by another seed
+                    } else {
+                        const uint32_t old = atomicOr(&g.flags[slot], want);
+                        new_dirty = (want & F_DIRTY) && !(old & F_DIRTY);
+                        new_ys = (want & F_YS) && !(old & F_YS);
+                        new_xs = (want & F_XS) && !(old & F_XS);
+                        raise = raise && !(old & F_RAISE);
+                        lower = lower && !(old & F_LOWER);
+                    }
+                }
+            }
+            // list appends and statistics: one counter atomic per list and
+            // workgroup, positions from the waves' ballots
+            const unsigned long long md = __ballot(new_dirty), my = __ballot(new_ys),
+                                     mx = __ballot(new_xs), mr = __ballot(raise),
+                                     ml = __ballot(lower);
+            if (lane == 0) {
+                wcnt[wid][0] = __popcll(md);
+                wcnt[wid][1] = __popcll(my);
+                wcnt[wid][2] = __popcll(mx);
+                wcnt[wid][3] = __popcll(mr);
+                wcnt[wid][4] = __popcll(ml);
+            }
+            __syncthreads();
+            const int nw = (int)(blockDim.x >> 6);
+            if (threadIdx.x < 5) {
+                const int c = threadIdx.x;
+                int sum = 0;
+                for (int v = 0; v < nw; ++v) sum += wcnt[v][c];
+                const int ctr = c == 0 ? C_NDIRTY : c == 1 ? C_NYS : c == 2 ? C_NXS
+                              : c == 3 ? C_NRAISE : C_NLOWER;
+                const int base = sum ? atomicAdd(&g.cnt[ctr], sum) : 0;
+                if (c < 3) bbase[c] = base;
+            }
+            __syncthreads();
+            int bd = bbase[0], by_ = bbase[1], bx_ = bbase[2];
+            for (int v = 0; v < wid; ++v) {
+                bd += wcnt[v][0];
+                by_ += wcnt[v][1];
+                bx_ += wcnt[v][2];
+            }
+            const unsigned long long below = (1ull << lane) - 1ull;
+            if (new_dirty) g.list_dirty[bd + __popcll(md & below)] = slot;
+            if (new_ys) g.list_ys[by_ + __popcll(my & below)] = slot;
+            if (new_xs) g.list_xs[bx_ + __popcll(mx & below)] = slot;
+            __syncthreads();
+        }
     }
-    const uint32_t clear = ~(F_SEED | F_DIRTY | F_XS | F_YS | F_RAISE | F_LOWER);
-    for (int64_t i = tid; i < ns; i += stride) atomicAnd(&g.flags[g.list_seed[i]], clear);
-    const int64_t nd = g.cnt[C_NDIRTY];
-    for (int64_t i = tid; i < nd; i += stride) atomicAnd(&g.flags[g.list_dirty[i]], clear);
-    const int64_t ny = g.cnt[C_NYS];
-    for (int64_t i = tid; i < ny; i += stride) atomicAnd(&g.flags[g.list_ys[i]], clear);
 }
 
 // ---------------------------------------------------------------------------
