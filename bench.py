@@ -226,8 +226,9 @@ def bench_paper_alg1(g, args, np):
     """The paper's own procedure (Algorithm 1, one CPU thread, oracle.Alg1):
     a global build of a 256 x 256 x 128 corner of the tunnel map and its
     deviation from the exact field, then 30 range scans on the 64 x 64 x 32
-    boxes map (d_max 20) with per-scan time and lowered / raised cells, the
-    counts of the paper's Table II."""
+    boxes map (d_max 20) with per-scan time and lowered / raised fronts, the
+    counts of the paper's Table II, in the paper's transform-status schedule
+    and in the conventional one."""
     import oracle
     import workloads
     from workloads.scans import ScanSim, ellipse_path
@@ -246,26 +247,31 @@ def bench_paper_alg1(g, args, np):
                       "lowered": lowered, "voxels_differing_from_exact": int((f != ref).sum()),
                       "max_overestimate": int((f - ref).max())}}
     occ = workloads.dense_boxes(0)
-    sim = ScanSim(occ, ellipse_path(64, 64, 32), seed=0)
-    b = oracle.Alg1((64, 64, 32), 20)
-    b.set_map(occ)
-    b.transform()
-    ms, lo, ra, ch = [], [], [], []
-    for _ in range(30):
-        xyz, st, _ = sim.step()
-        t0 = time.perf_counter()
-        b.apply(xyz, st)
-        l, r = b.transform()
-        ms.append((time.perf_counter() - t0) * 1e3)
-        lo.append(l)
-        ra.append(r)
-        ch.append(len(xyz))
-    exact = bool(np.array_equal(b.field(), oracle.edt_separable(sim.map, 20)))
-    b.close()
-    out["incremental"] = {"workload": "30 range scans on the 64x64x32 boxes map, d_max 20",
-                          "p50_ms": round(pct(ms, 50), 3), "changed_mean": float(np.mean(ch)),
-                          "lowered_mean": float(np.mean(lo)), "raised_mean": float(np.mean(ra)),
-                          "equals_exact": exact}
+    # the paper's transform-status schedule and the conventional one on the
+    # same 30 scans: per-scan time and the lowered / raised fronts (Table II)
+    for schedule, key in (("transform_status", "incremental"),
+                          ("conventional", "incremental_conventional")):
+        sim = ScanSim(occ, ellipse_path(64, 64, 32), seed=0)
+        b = oracle.Alg1((64, 64, 32), 20, schedule)
+        b.set_map(occ)
+        b.transform()
+        ms, lo, ra, ch = [], [], [], []
+        for _ in range(30):
+            xyz, st, _ = sim.step()
+            t0 = time.perf_counter()
+            b.apply(xyz, st)
+            l, r = b.transform()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            lo.append(l)
+            ra.append(r)
+            ch.append(len(xyz))
+        exact = bool(np.array_equal(b.field(), oracle.edt_separable(sim.map, 20)))
+        b.close()
+        out[key] = {"workload": "30 range scans on the 64x64x32 boxes map, d_max 20",
+                    "schedule": schedule,
+                    "p50_ms": round(pct(ms, 50), 3), "changed_mean": float(np.mean(ch)),
+                    "lowered_mean": float(np.mean(lo)), "raised_mean": float(np.mean(ra)),
+                    "equals_exact": exact}
     out["cores"] = 1
     return out
 

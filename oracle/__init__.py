@@ -75,7 +75,7 @@ def lib():
         L.oracle_integrate_scan.argtypes = [u8p, ci, ci, ci, i32p, i32p, u8p, ctypes.c_int64]
         L.oracle_integrate_scan.restype = ctypes.c_int64
         vp = ctypes.c_void_p
-        L.alg1_create.argtypes = [ci, ci, ci, ci]
+        L.alg1_create.argtypes = [ci, ci, ci, ci, ci]
         L.alg1_create.restype = vp
         L.alg1_destroy.argtypes = [vp]
         L.alg1_destroy.restype = None
@@ -220,14 +220,21 @@ def integrate_scan(occ: np.ndarray, origin, ends: np.ndarray, hits: np.ndarray):
 
 class Alg1:
     """The paper's Algorithm 1 on the CPU (``alg1.c``): SetObstacle /
-    RemoveObstacle, then DistanceTransform with Raise and Lower over the
-    26-neighbourhood.  Not an oracle: it is the paper's own procedure, whose
-    result the tests compare with the exact field."""
+    RemoveObstacle, then DistanceTransform with raising and lowering waves
+    over the 26-neighbourhood.  schedule "transform_status" is the paper's
+    method (section IV-B: the raise key is the transform radius, and a
+    lowering wave may take over a raising front); "conventional" is the
+    scheme it improves on (a raise flag, raising fronts are never taken
+    over).  Not an oracle: it is the paper's own procedure, whose result the
+    tests compare with the exact field."""
 
-    def __init__(self, shape, dmax: int):
+    SCHEDULES = {"conventional": 0, "transform_status": 1}
+
+    def __init__(self, shape, dmax: int, schedule: str = "transform_status"):
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
-        self._h = lib().alg1_create(nx, ny, nz, int(dmax))
+        self.schedule = schedule
+        self._h = lib().alg1_create(nx, ny, nz, int(dmax), self.SCHEDULES[schedule])
         if not self._h:
             raise ValueError("alg1_create failed")
 
@@ -251,7 +258,7 @@ class Alg1:
         return self.apply(xyz, np.ones(len(xyz), np.uint8))
 
     def transform(self):
-        """DistanceTransform; returns (cells lowered, cells raised)."""
+        """DistanceTransform; returns (fronts lowered, fronts raised)."""
         c = (ctypes.c_int64 * 2)()
         lib().alg1_transform(self._h, c)
         return int(c[0]), int(c[1])

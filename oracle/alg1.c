@@ -1,248 +1,265 @@
 /*
- * oracle/alg1.c -- the paper's own method on the CPU: the incremental
- * Euclidean distance transform of Algorithm 1 (SetObstacle, RemoveObstacle,
- * DistanceTransform with Raise and Lower over the 26-neighbourhood, a priority
- * queue ordered by squared distance, one nearest-obstacle pointer per cell).
- * TEST INFRASTRUCTURE ONLY: the tests and the benchmark's CPU leg use it to
- * show what the paper's procedure computes on the same inputs (its
- * deviation from the exact field, its lowered / raised cell counts as in
- * Table II) and how long it takes on this CPU.  It is not the oracle (the
- * exact field comes from edt_oracle.c) and shares no code with the HIP path.
+ * oracle/alg1.c -- the paper's own incremental method on the CPU (section
+ * IV-B, Algorithm 1), in two schedules, for comparison only.
  *
- * Readings: distances are squared and capped at D = d_max^2 (R1); the raise
- * field holds -1 when a cell is not raising and the old distance otherwise
- * (the key of the raise wave); the queue is a bucket queue over the integer
- * keys 0..D, first in first out within a key (the paper leaves the order of
- * equal keys open); a cell is processed when popped while still marked
- * queued, so stale duplicates are dropped.  Storage is dense arrays rather
- * than a VDB tree: the procedure, not the memory layout, is what is measured.
+ * TEST INFRASTRUCTURE ONLY: the tests and the benchmark's CPU leg use it to
+ * show what the paper's wave procedure computes on the same inputs (its
+ * deviation from the exact field, the lowered / raised counts of Table II)
+ * and what it costs on this CPU.  It is not the oracle (the exact field comes
+ * from edt_oracle.c) and shares no code with the HIP path.
+ *
+ * What the method does (section IV-B):
+ *   - every cell keeps the obstacle it points at, its squared distance to it
+ *     (capped at D = d_max^2, reading R1) and a raise key; changed cells are
+ *     the wave centres;
+ *   - a removed obstacle starts a raising wave: cells that point at an
+ *     obstacle that is gone forget it (back to D) and pass the raise on;
+ *     cells that still point at a valid obstacle are where the raising wave
+ *     stops, and they are queued to lower the cleared area again;
+ *   - an added obstacle (and every boundary cell) starts a lowering wave: a
+ *     cell offers its obstacle to its 26 neighbours, which take it when it
+ *     is nearer than what they hold (or as near, when theirs is gone);
+ *   - all fronts are popped in order of their key, the transform radius, so
+ *     waves spread at the same speed (a bucket queue over 0..D, first in
+ *     first out within a key: reading R22); stale duplicates are skipped.
+ * Schedules:
+ *   TRANSFORM_STATUS (the paper's "-Ex"): the raise key of a raising cell is
+ *     its old transform radius, so a lowering wave that reaches a raising
+ *     cell with a candidate no larger than that key takes the cell over at
+ *     once and turns it into a lowering front;
+ *   CONVENTIONAL (the scheme the paper improves on): the raise key is only a
+ *     flag, raising cells are never touched by a lowering wave, and they are
+ *     lowered again only after their raise has been processed.
+ * Storage is dense arrays rather than a VDB tree: the procedure, not the
+ * memory layout, is what is measured.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-enum { NOT_QUEUED = 0, QUEUED = 1 };
+enum { SCHED_CONVENTIONAL = 0, SCHED_TRANSFORM_STATUS = 1 };
+enum { SETTLED = -1 };          /* raise key of a cell that is not raising */
+
+/* ---- bucket queue keyed by transform radius ---------------------------- */
+typedef struct {
+    int64_t* cell;
+    int64_t len, cap, head;
+} bucket;
 
 typedef struct {
-    int nx, ny, nz, dmax;
-    int32_t D;
-    int64_t n;
-    uint8_t* occ;
-    int64_t* obst;     /* index of the nearest obstacle, -1 for none */
-    int32_t* dist;
-    int32_t* raise;    /* -1: not raising; else the key of the raise */
-    uint8_t* state;
-    /* bucket queue: per key a growable array of cell indices */
-    int64_t** bucket;
-    int64_t* blen;     /* entries pushed into each key */
-    int64_t* bcap;
-    int64_t* qhead;    /* entries already popped from each key */
-    int32_t cur;       /* smallest key that may be non-empty */
-    int64_t size;
-    int64_t lowered, raised;
-} alg1;
+    bucket* b;
+    int32_t kmax;     /* keys 0 .. kmax */
+    int32_t low;      /* no bucket below this key holds an unread entry */
+} wave_queue;
 
-static int qpush(alg1* a, int64_t cell, int32_t key) {
-    if (key < 0) key = 0;
-    if (key > a->D) key = a->D;
-    if (a->blen[key] == a->bcap[key]) {
-        int64_t c = a->bcap[key] ? 2 * a->bcap[key] : 16;
-        int64_t* p = (int64_t*)realloc(a->bucket[key], (size_t)c * sizeof(int64_t));
+static int wq_init(wave_queue* q, int32_t kmax) {
+    q->b = (bucket*)calloc((size_t)kmax + 1, sizeof(bucket));
+    q->kmax = kmax;
+    q->low = kmax + 1;
+    return q->b ? 0 : -1;
+}
+
+static void wq_free(wave_queue* q) {
+    if (!q->b) return;
+    for (int32_t k = 0; k <= q->kmax; ++k) free(q->b[k].cell);
+    free(q->b);
+    q->b = NULL;
+}
+
+static int wq_push(wave_queue* q, int64_t c, int32_t key) {
+    key = key < 0 ? 0 : (key > q->kmax ? q->kmax : key);
+    bucket* b = &q->b[key];
+    if (b->len == b->cap) {
+        const int64_t cap = b->cap ? 2 * b->cap : 16;
+        int64_t* p = (int64_t*)realloc(b->cell, (size_t)cap * sizeof(int64_t));
         if (!p) return -1;
-        a->bucket[key] = p;
-        a->bcap[key] = c;
+        b->cell = p;
+        b->cap = cap;
     }
-    a->bucket[key][a->blen[key]++] = cell;
-    if (key < a->cur) a->cur = key;
-    a->size++;
+    b->cell[b->len++] = c;
+    if (key < q->low) q->low = key;
     return 0;
 }
 
-/* next cell of the smallest key, first in first out within a key */
-static int64_t qpop(alg1* a) {
-    while (a->cur <= a->D) {
-        const int32_t k = a->cur;
-        if (a->qhead[k] < a->blen[k]) {
-            a->size--;
-            return a->bucket[k][a->qhead[k]++];
-        }
-        a->blen[k] = 0;
-        a->qhead[k] = 0;
-        a->cur++;
+/* next entry of the smallest key (-1 when empty); drained buckets are reset */
+static int64_t wq_pop(wave_queue* q) {
+    for (; q->low <= q->kmax; ++q->low) {
+        bucket* b = &q->b[q->low];
+        if (b->head < b->len) return b->cell[b->head++];
+        b->head = b->len = 0;
     }
     return -1;
 }
 
-void alg1_destroy(alg1* a);
-
-alg1* alg1_create(int nx, int ny, int nz, int dmax) {
-    if (nx < 1 || ny < 1 || nz < 1 || dmax < 1 || dmax > 4095) return NULL;
-    alg1* a = (alg1*)calloc(1, sizeof(alg1));
-    if (!a) return NULL;
-    a->nx = nx; a->ny = ny; a->nz = nz; a->dmax = dmax;
-    a->D = dmax * dmax;
-    a->n = (int64_t)nx * ny * nz;
-    a->occ = (uint8_t*)calloc((size_t)a->n, 1);
-    a->obst = (int64_t*)malloc((size_t)a->n * sizeof(int64_t));
-    a->dist = (int32_t*)malloc((size_t)a->n * sizeof(int32_t));
-    a->raise = (int32_t*)malloc((size_t)a->n * sizeof(int32_t));
-    a->state = (uint8_t*)calloc((size_t)a->n, 1);
-    a->bucket = (int64_t**)calloc((size_t)a->D + 1, sizeof(int64_t*));
-    a->blen = (int64_t*)calloc((size_t)a->D + 1, sizeof(int64_t));
-    a->bcap = (int64_t*)calloc((size_t)a->D + 1, sizeof(int64_t));
-    a->qhead = (int64_t*)calloc((size_t)a->D + 1, sizeof(int64_t));
-    if (!a->occ || !a->obst || !a->dist || !a->raise || !a->state || !a->bucket || !a->blen ||
-        !a->bcap || !a->qhead) {
-        alg1_destroy(a);
-        return NULL;
-    }
-    /* Initialize: no obstacle, distance at the cap, not raising, not queued */
-    for (int64_t i = 0; i < a->n; ++i) {
-        a->obst[i] = -1;
-        a->dist[i] = a->D;
-        a->raise[i] = -1;
-    }
-    a->cur = a->D + 1;
-    return a;
-}
+/* ---- the distance field and its waves ----------------------------------- */
+typedef struct alg1 {
+    int nx, ny, nz, sched;
+    int32_t D;
+    int64_t n;
+    uint8_t* occ;
+    uint8_t* queued;    /* waiting in the queue */
+    int64_t* obst;      /* obstacle the cell points at, -1 for none */
+    int32_t* dist;      /* squared distance to it, capped at D */
+    int32_t* rkey;      /* SETTLED, or the raise key of a raising cell */
+    wave_queue q;
+    int64_t lowered, raised;
+} alg1;
 
 void alg1_destroy(alg1* a) {
     if (!a) return;
-    if (a->bucket)
-        for (int64_t k = 0; k <= a->D; ++k) free(a->bucket[k]);
-    free(a->bucket); free(a->blen); free(a->bcap); free(a->qhead);
-    free(a->occ); free(a->obst); free(a->dist); free(a->raise); free(a->state);
+    wq_free(&a->q);
+    free(a->occ);
+    free(a->queued);
+    free(a->obst);
+    free(a->dist);
+    free(a->rkey);
     free(a);
 }
 
-static int64_t idx(const alg1* a, int x, int y, int z) {
-    return x + (int64_t)a->nx * (y + (int64_t)a->ny * z);
+/* Initialize: no obstacle anywhere, every cell at the cap and settled */
+alg1* alg1_create(int nx, int ny, int nz, int dmax, int sched) {
+    if (nx < 1 || ny < 1 || nz < 1 || dmax < 1 || dmax > 4095) return NULL;
+    if (sched != SCHED_CONVENTIONAL && sched != SCHED_TRANSFORM_STATUS) return NULL;
+    alg1* a = (alg1*)calloc(1, sizeof(alg1));
+    if (!a) return NULL;
+    a->nx = nx;
+    a->ny = ny;
+    a->nz = nz;
+    a->sched = sched;
+    a->D = dmax * dmax;
+    a->n = (int64_t)nx * ny * nz;
+    a->occ = (uint8_t*)calloc((size_t)a->n, 1);
+    a->queued = (uint8_t*)calloc((size_t)a->n, 1);
+    a->obst = (int64_t*)malloc((size_t)a->n * sizeof(int64_t));
+    a->dist = (int32_t*)malloc((size_t)a->n * sizeof(int32_t));
+    a->rkey = (int32_t*)malloc((size_t)a->n * sizeof(int32_t));
+    if (!a->occ || !a->queued || !a->obst || !a->dist || !a->rkey || wq_init(&a->q, a->D)) {
+        alg1_destroy(a);
+        return NULL;
+    }
+    for (int64_t c = 0; c < a->n; ++c) {
+        a->obst[c] = -1;
+        a->dist[c] = a->D;
+        a->rkey[c] = SETTLED;
+    }
+    return a;
 }
 
-/* SetObstacle: a free cell that is not waiting in the queue becomes its own
-   nearest obstacle at distance 0 and starts a lower wave */
-void alg1_set_obstacle(alg1* a, int x, int y, int z) {
-    const int64_t s = idx(a, x, y, z);
-    if (a->occ[s] || a->state[s] == QUEUED) return;
-    a->occ[s] = 1;
-    a->obst[s] = s;
-    a->dist[s] = 0;
-    a->raise[s] = -1;
-    a->state[s] = QUEUED;
-    qpush(a, s, 0);
+static void enqueue(alg1* a, int64_t c, int32_t key) {
+    a->queued[c] = 1;
+    wq_push(&a->q, c, key);
 }
 
-/* RemoveObstacle: an obstacle that is not waiting in the queue loses its
-   distance and starts a raise wave */
-void alg1_remove_obstacle(alg1* a, int x, int y, int z) {
-    const int64_t s = idx(a, x, y, z);
-    if (!a->occ[s] || a->state[s] == QUEUED) return;
-    a->occ[s] = 0;
-    a->obst[s] = -1;
-    a->dist[s] = a->D;
-    a->raise[s] = 0;
-    a->state[s] = QUEUED;
-    qpush(a, s, 0);
-}
-
-static int32_t sqdist(const alg1* a, int64_t p, int64_t q) {
+static int32_t capped_sqdist(const alg1* a, int64_t p, int64_t c) {
     const int64_t nxy = (int64_t)a->nx * a->ny;
-    const int64_t dx = p % a->nx - q % a->nx;
-    const int64_t dy = (p / a->nx) % a->ny - (q / a->nx) % a->ny;
-    const int64_t dz = p / nxy - q / nxy;
+    const int64_t dx = p % a->nx - c % a->nx;
+    const int64_t dy = (p / a->nx) % a->ny - (c / a->nx) % a->ny;
+    const int64_t dz = p / nxy - c / nxy;
     const int64_t d = dx * dx + dy * dy + dz * dz;
     return d > a->D ? a->D : (int32_t)d;
 }
 
-/* the 26 neighbours of cell s inside the grid */
-static int neighbours(const alg1* a, int64_t s, int64_t* out) {
-    const int x = (int)(s % a->nx), y = (int)((s / a->nx) % a->ny),
-              z = (int)(s / ((int64_t)a->nx * a->ny));
-    int k = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy && !dz) continue;
-                const int u = x + dx, v = y + dy, w = z + dz;
-                if (u < 0 || v < 0 || w < 0 || u >= a->nx || v >= a->ny || w >= a->nz) continue;
-                out[k++] = idx(a, u, v, w);
-            }
-    return k;
-}
-
-/* Raise: neighbours whose nearest obstacle is gone start raising (their old
-   distance is the key) and lose their distance; neighbours with a valid
-   obstacle are queued so that they lower the raised area again */
-static void raise_cell(alg1* a, int64_t s) {
-    int64_t nb[26];
-    const int m = neighbours(a, s, nb);
-    a->raised++;
-    for (int i = 0; i < m; ++i) {
-        const int64_t n = nb[i];
-        if (a->obst[n] < 0) continue;
-        if (!a->occ[a->obst[n]]) {
-            a->raise[n] = a->dist[n];
-            a->state[n] = QUEUED;
-            qpush(a, n, a->dist[n]);
-            a->obst[n] = -1;
-            a->dist[n] = a->D;
-        } else if (a->state[n] != QUEUED) {
-            a->state[n] = QUEUED;
-            qpush(a, n, a->dist[n]);
-        }
+/* a raising wave reaches cell c */
+static void spread_raise(alg1* a, int64_t c) {
+    const int64_t o = a->obst[c];
+    if (o < 0) return;                     /* already cleared, nothing to pass on */
+    if (a->occ[o]) {
+        /* c still points at a valid obstacle: the raise stops here, and c
+           will lower the cleared cells around it */
+        if (!a->queued[c]) enqueue(a, c, a->dist[c]);
+        return;
     }
-    a->raise[s] = -1;
-    a->state[s] = NOT_QUEUED;
+    /* c pointed at a removed obstacle: it raises too, keyed by its old radius
+       (transform status) or merely flagged (conventional), and forgets it */
+    a->rkey[c] = a->sched == SCHED_TRANSFORM_STATUS ? a->dist[c] : 0;
+    enqueue(a, c, a->dist[c]);
+    a->obst[c] = -1;
+    a->dist[c] = a->D;
 }
 
-/* Lower: offer the cell's obstacle to each neighbour; a raising neighbour
-   whose raise key is no smaller takes it outright, a settled neighbour
-   takes it when it is nearer (or equally near while its own obstacle is
-   gone) */
-static void lower_cell(alg1* a, int64_t s) {
-    int64_t nb[26];
-    const int m = neighbours(a, s, nb);
-    a->lowered++;
-    const int64_t ob = a->obst[s];
-    if (ob >= 0) {
-        for (int i = 0; i < m; ++i) {
-            const int64_t n = nb[i];
-            const int32_t dn = sqdist(a, ob, n);
-            if (a->raise[n] >= dn) {
-                a->obst[n] = ob;
-                a->dist[n] = dn;
-                a->raise[n] = -1;
-                a->state[n] = QUEUED;
-                qpush(a, n, dn);
-            } else if (a->raise[n] < 0) {
-                const int gone = a->obst[n] < 0 || !a->occ[a->obst[n]];
-                if (dn < a->dist[n] || (dn == a->dist[n] && gone)) {
-                    a->obst[n] = ob;
-                    a->dist[n] = dn;
-                    a->raise[n] = -1;
-                    if (dn < a->D) {
-                        a->state[n] = QUEUED;
-                        qpush(a, n, dn);
-                    }
+/* a lowering wave offers obstacle o to cell c */
+static void offer(alg1* a, int64_t c, int64_t o) {
+    const int32_t d = capped_sqdist(a, o, c);
+    if (a->rkey[c] != SETTLED) {
+        /* a raising cell: only the transform-status schedule may take it over,
+           when the offer is no farther than the radius it raises from */
+        if (a->sched == SCHED_TRANSFORM_STATUS && a->rkey[c] >= d) {
+            a->obst[c] = o;
+            a->dist[c] = d;
+            a->rkey[c] = SETTLED;
+            enqueue(a, c, d);
+        }
+        return;
+    }
+    const int64_t held = a->obst[c];
+    const int held_gone = held < 0 || !a->occ[held];
+    if (d < a->dist[c] || (d == a->dist[c] && held_gone)) {
+        a->obst[c] = o;
+        a->dist[c] = d;
+        if (d < a->D) enqueue(a, c, d);
+    }
+}
+
+/* one popped front: pass its raise, or its obstacle, to the 26 neighbours,
+   then the cell is settled and out of the queue */
+static void relax(alg1* a, int64_t s) {
+    const int raising = a->rkey[s] != SETTLED;
+    const int64_t o = a->obst[s];
+    if (raising) a->raised++;
+    else a->lowered++;
+    if (raising || o >= 0) {
+        const int x = (int)(s % a->nx), y = (int)((s / a->nx) % a->ny),
+                  z = (int)(s / ((int64_t)a->nx * a->ny));
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int w = z + dz;
+            if (w < 0 || w >= a->nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int v = y + dy;
+                if (v < 0 || v >= a->ny) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int u = x + dx;
+                    if (u < 0 || u >= a->nx || (!dx && !dy && !dz)) continue;
+                    const int64_t c = u + (int64_t)a->nx * (v + (int64_t)a->ny * w);
+                    if (raising) spread_raise(a, c);
+                    else offer(a, c, o);
                 }
             }
         }
     }
-    a->raise[s] = -1;
-    a->state[s] = NOT_QUEUED;
+    a->rkey[s] = SETTLED;
+    a->queued[s] = 0;
 }
 
-/* DistanceTransform: process the queue in key order; counts[0] and
-   counts[1] receive the cells lowered and raised by this call */
+/* SetObstacle / RemoveObstacle: a cell already in the target state, or
+   already waiting in the queue, is left alone (the guards of the paper's
+   procedures); a new obstacle points at itself at distance 0 and starts a
+   lowering wave, a removed one forgets its distance and starts a raising
+   wave (raise key 0) */
+static void change(alg1* a, int64_t c, int occupied) {
+    if (!a->occ[c] == !occupied || a->queued[c]) return;
+    a->occ[c] = occupied ? 1 : 0;
+    a->obst[c] = occupied ? c : -1;
+    a->dist[c] = occupied ? 0 : a->D;
+    a->rkey[c] = occupied ? SETTLED : 0;
+    enqueue(a, c, 0);
+}
+
+/* the changes of n entries (x, y, z) with target states, in order; entries
+   outside the grid are ignored */
+void alg1_apply(alg1* a, const int32_t* xyz, const uint8_t* state, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= a->nx || y >= a->ny || z >= a->nz) continue;
+        change(a, x + (int64_t)a->nx * (y + (int64_t)a->ny * z), state[i] != 0);
+    }
+}
+
+/* DistanceTransform: pop fronts in key order until the queue is empty;
+   counts[0] and counts[1] receive the fronts lowered and raised */
 void alg1_transform(alg1* a, int64_t* counts) {
     a->lowered = a->raised = 0;
-    for (;;) {
-        const int64_t s = qpop(a);
-        if (s < 0) break;
-        if (a->state[s] != QUEUED) continue;
-        if (a->raise[s] >= 0) raise_cell(a, s);
-        else lower_cell(a, s);
-    }
+    for (int64_t s; (s = wq_pop(&a->q)) >= 0;)
+        if (a->queued[s]) relax(a, s);
     if (counts) {
         counts[0] = a->lowered;
         counts[1] = a->raised;
@@ -252,15 +269,4 @@ void alg1_transform(alg1* a, int64_t* counts) {
 /* the distance field (squared, capped at D), x fastest */
 void alg1_read(const alg1* a, int32_t* out) {
     memcpy(out, a->dist, (size_t)a->n * sizeof(int32_t));
-}
-
-/* SetObstacle / RemoveObstacle for n entries (x, y, z) with target states,
-   in order; entries outside the grid are ignored */
-void alg1_apply(alg1* a, const int32_t* xyz, const uint8_t* state, int64_t n) {
-    for (int64_t i = 0; i < n; ++i) {
-        const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        if (x < 0 || y < 0 || z < 0 || x >= a->nx || y >= a->ny || z >= a->nz) continue;
-        if (state[i]) alg1_set_obstacle(a, x, y, z);
-        else alg1_remove_obstacle(a, x, y, z);
-    }
 }
