@@ -123,9 +123,11 @@ edt_status edt_global(edt_ctx* ctx, const edt_map* map, void* stream);
  * order).  Afterwards s equals edt_global of the new occupancy, bit for bit.
  * n == 0 is a no-op.  n > max_changes returns EDT_ERR_CAPACITY with nothing
  * enqueued.  Entries outside the extent make the whole call a no-op and set
- * the device error word to EDT_ERR_RANGE.  If the block pool fills up the
- * error word becomes EDT_ERR_CAPACITY and the field must be rebuilt with
- * edt_global. */
+ * the device error word to EDT_ERR_RANGE.  Every block the call needs is
+ * created before any occupancy changes: if the block pool fills up, the call
+ * is cancelled with the map unchanged (blocks it created hold the background
+ * value, which is their correct field) and the error word becomes
+ * EDT_ERR_CAPACITY; edt_grow then makes room and the call can be repeated. */
 edt_status edt_update(edt_ctx* ctx, const int32_t* d_xyz, const uint8_t* d_state,
                       int64_t n, void* stream);
 
@@ -159,6 +161,22 @@ edt_status edt_integrate_scan(edt_ctx* ctx, const int32_t* d_origin, const int32
  * tree, section IV-A), so the pool follows the map again.  s is unchanged;
  * pool slots are renumbered. */
 edt_status edt_compact(edt_ctx* ctx, void* stream);
+
+/* Growth of the block pool (section IV-A: the tree grows as cells are
+ * transformed, memory is allocated only where the field is computed).  Moves
+ * the context onto the caller's new workspace d_ws (256-byte aligned, at
+ * least edt_workspace_bytes of the context's configuration with max_blocks
+ * replaced by the new max_blocks, which must not be smaller than the current
+ * capacity).  The map is carried over: the blocks holding an obstacle are
+ * gathered from the old pool and the pool and field are rebuilt in the new
+ * workspace, so s, the occupancy and every later result are those the old
+ * context would give (interior distances must be recomputed).  The old
+ * workspace is read by work enqueued on `stream` and may be released once
+ * that work has completed.  An update cancelled because the pool was full
+ * (edt_get_error returns EDT_ERR_CAPACITY) leaves the map unchanged, so it
+ * can be issued again after edt_grow. */
+edt_status edt_grow(edt_ctx* ctx, int64_t max_blocks, void* d_ws, int64_t ws_bytes,
+                    void* stream);
 
 /* s at n voxel coordinates d_xyz (int32[n][3]) into d_out (int32[n]);
  * out-of-extent coordinates and voxels of blocks that hold no field read D

@@ -93,6 +93,7 @@ def lib():
         "edt_query": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_query_nearest": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "edt_compact": ([vp, vp], ctypes.c_int),
+        "edt_grow": ([vp, i64, vp, i64, vp], ctypes.c_int),
         "edt_integrate_scan": ([vp, vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_interior": ([vp, vp], ctypes.c_int),
         "edt_query_signed": ([vp, vp, i64, vp, vp], ctypes.c_int),
@@ -167,6 +168,9 @@ class Field:
             raise EdtError("edt_workspace_bytes", int(nbytes))
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        nb = ((nx + 7) // 8) * ((ny + 7) // 8) * ((nz + 7) // 8)
+        self.extent_blocks = nb
+        self.max_blocks = min(int(max_blocks), nb) if max_blocks else nb
         ctx = ctypes.c_void_p()
         _check("edt_create", L.edt_create(ctypes.byref(self.cfg), _ptr(self.workspace),
                                           int(nbytes), _stream(stream), ctypes.byref(ctx)))
@@ -184,37 +188,75 @@ class Field:
             pass
 
     # -- transforms ---------------------------------------------------------
-    def global_(self, occ: torch.Tensor, stream=None):
-        """Global transform of a dense occupancy grid (nz, ny, nx) uint8."""
+    def _grown(self, call, grow: bool, stream):
+        """Run call(); with grow, wait for it and, while the device reports a
+        full pool (the call was cancelled with the map unchanged, or a global
+        transform ran out of room), double the pool and run it again."""
+        call()
+        while grow:
+            err = self.error(stream)
+            if err != EDT_ERR_CAPACITY or self.max_blocks >= self.extent_blocks:
+                if err != EDT_OK:
+                    raise EdtError("device error", err)
+                break
+            self.grow(min(2 * self.max_blocks, self.extent_blocks), stream)
+            call()
+        return self
+
+    def global_(self, occ: torch.Tensor, stream=None, grow: bool = False):
+        """Global transform of a dense occupancy grid (nz, ny, nx) uint8.
+        grow: enlarge the pool until the map fits (waits for the GPU)."""
         nx, ny, nz = self.shape
         occ = _dev_tensor(occ, torch.uint8, (nz, ny, nx))
         m = EdtMap(0, occ.data_ptr(), None, None, 0)
-        _check("edt_global", lib().edt_global(self._ctx, ctypes.byref(m), _stream(stream)))
         self._keep = occ
-        return self
+        return self._grown(lambda: _check("edt_global", lib().edt_global(
+            self._ctx, ctypes.byref(m), _stream(stream))), grow, stream)
 
-    def global_blocks(self, block_xyz: torch.Tensor, block_occ: torch.Tensor, stream=None):
+    def global_blocks(self, block_xyz: torch.Tensor, block_occ: torch.Tensor, stream=None,
+                      grow: bool = False):
         """Global transform of a leaf-block list: block_xyz int32 (n, 3) as
         (bx, by, bz), block_occ uint8 (n, 512) with in-block index x+8y+64z."""
         n = int(block_xyz.shape[0])
         xyz = _dev_tensor(block_xyz, torch.int32, (n, 3))
         data = _dev_tensor(block_occ, torch.uint8, (n, 512))
         m = EdtMap(1, None, xyz.data_ptr() if n else None, data.data_ptr() if n else None, n)
-        _check("edt_global", lib().edt_global(self._ctx, ctypes.byref(m), _stream(stream)))
         self._keep = (xyz, data)
-        return self
+        return self._grown(lambda: _check("edt_global", lib().edt_global(
+            self._ctx, ctypes.byref(m), _stream(stream))), grow, stream)
 
-    def update(self, xyz: torch.Tensor, state: torch.Tensor, stream=None):
+    def update(self, xyz: torch.Tensor, state: torch.Tensor, stream=None, grow: bool = False):
         """Incremental transform: set voxels xyz (int32 (n, 3)) to the
-        absolute occupancy `state` (uint8 (n,)); the last entry wins."""
+        absolute occupancy `state` (uint8 (n,)); the last entry wins.
+        grow: if the pool is full, enlarge it and repeat the (cancelled)
+        update (waits for the GPU)."""
         n = int(xyz.shape[0])
         if n == 0:
             return self
         xyz = _dev_tensor(xyz, torch.int32, (n, 3))
         state = _dev_tensor(state, torch.uint8, (n,))
-        _check("edt_update", lib().edt_update(self._ctx, _ptr(xyz), _ptr(state), n,
-                                              _stream(stream)))
         self._keep = (xyz, state)
+        return self._grown(lambda: _check("edt_update", lib().edt_update(
+            self._ctx, _ptr(xyz), _ptr(state), n, _stream(stream))), grow, stream)
+
+    def grow(self, max_blocks: int | None = None, stream=None):
+        """Move the field onto a larger block pool (edt_grow): max_blocks
+        slots (default: twice the current pool, at most one per block of the
+        extent).  The map and field carry over unchanged."""
+        new = int(max_blocks) if max_blocks else min(2 * self.max_blocks, self.extent_blocks)
+        new = min(new, self.extent_blocks)
+        cfg = EdtConfig(self.cfg.nx, self.cfg.ny, self.cfg.nz, self.cfg.d_max, new,
+                        self.cfg.max_changes, self.cfg.max_interior_blocks)
+        L = lib()
+        nbytes = L.edt_workspace_bytes(ctypes.byref(cfg))
+        if nbytes < 0:
+            raise EdtError("edt_workspace_bytes", int(nbytes))
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        _check("edt_grow", L.edt_grow(self._ctx, new, _ptr(ws), int(nbytes), _stream(stream)))
+        if stream is not None:
+            # the old workspace is read by the work just enqueued on `stream`
+            self.workspace.record_stream(stream)
+        self.workspace, self.cfg, self.max_blocks = ws, cfg, new
         return self
 
     def integrate_scan(self, origin: torch.Tensor, ends: torch.Tensor, hits: torch.Tensor,
@@ -473,6 +515,9 @@ class Batch:
             raise EdtError("edt_batch_workspace_bytes", int(nbytes))
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        nb = ((nx + 7) // 8) * ((ny + 7) // 8) * ((nz + 7) // 8)
+        self.extent_blocks = nb
+        self.max_blocks = min(int(max_blocks), nb) if max_blocks else nb
         h = ctypes.c_void_p()
         _check("edt_batch_create", L.edt_batch_create(self._maps, n, self.d_max, _ptr(self.workspace),
                                                       int(nbytes), _stream(stream), ctypes.byref(h)))

@@ -233,40 +233,11 @@ edt_status dilate_region(edt_ctx* c, hipStream_t st) {
 
 }  // namespace
 
-extern "C" {
-
-const char* edt_status_str(int s) {
-    switch (s) {
-        case EDT_OK: return "EDT_OK";
-        case EDT_ERR_ARG: return "EDT_ERR_ARG";
-        case EDT_ERR_RANGE: return "EDT_ERR_RANGE";
-        case EDT_ERR_CAPACITY: return "EDT_ERR_CAPACITY";
-        case EDT_ERR_HIP: return "EDT_ERR_HIP";
-        case EDT_ERR_STATE: return "EDT_ERR_STATE";
-        default: return "EDT_UNKNOWN";
-    }
-}
-
-int64_t edt_workspace_bytes(const edt_config* cfg) {
-    Layout L;
-    if (!layout_of(cfg, &L)) return EDT_ERR_ARG;
-    return L.total;
-}
-
-edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void* stream,
-                      edt_ctx** out) {
-    if (!out) return EDT_ERR_ARG;
-    *out = nullptr;
-    Layout L;
-    if (!layout_of(cfg, &L) || !d_ws) return EDT_ERR_ARG;
-    if (((uintptr_t)d_ws & 255) != 0) return EDT_ERR_ARG;
-    if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
-    edt_ctx* c = (edt_ctx*)calloc(1, sizeof(edt_ctx));
-    if (!c) return EDT_ERR_CAPACITY;
+// Points the context's grid at the regions of workspace b for layout L.
+static void bind_workspace(edt_ctx* c, const edt_config* cfg, const Layout& L, char* b) {
     c->cfg = *cfg;
     c->tcap = L.tcap;
     c->ucap = L.ucap;
-    char* b = (char*)d_ws;
     Grid& g = c->g;
     g.nx = cfg->nx; g.ny = cfg->ny; g.nz = cfg->nz;
     g.nbx = (cfg->nx + 7) / 8; g.nby = (cfg->ny + 7) / 8; g.nbz = (cfg->nz + 7) / 8;
@@ -319,6 +290,83 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
     c->scan_cnt = (int32_t*)(b + L.off[O_SCANCNT]);
     c->scan_off = (int64_t*)(b + L.off[O_SCANOFF]);
     c->scan_blk = (int64_t*)(b + L.off[O_SCANBLK]);
+}
+
+// Enqueues the initial state of a freshly bound workspace: empty tile and
+// dedupe tables, zero counters, the block of D values.
+static edt_status init_workspace(edt_ctx* c, const Layout& L, hipStream_t st) {
+    const Grid& g = c->g;
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(L.tcap * 128, 256, 4096)), dim3(256), 0, st,
+                       g, L.tcap);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.ukeys,
+                       L.ucap, KEY_EMPTY);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
+                       L.ucap, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt, (int64_t)64, 0);
+    // the block of D values that the window passes read for absent blocks of
+    // g1 / g2, in their representation (binary16 for small radii)
+    const uint32_t dw = win_f16(g.R) ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int32_t*)g.dblock, (int64_t)256,
+                       (int32_t)(dw | (dw << 16)));
+    return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_HIP;
+}
+
+// Rebuilds the pool of c from a device list of blocks holding an obstacle
+// (int32 coordinates and 64 bytes of occupancy bits each; *count entries, at
+// most nmax) and recomputes the field: the global transform of that map.
+static edt_status rebuild_from_list(edt_ctx* c, const int32_t* count, const int32_t* lxyz,
+                                    const uint8_t* lbits, int64_t nmax, hipStream_t st) {
+    Grid& g = c->g;
+    c->interior_valid = false;
+    mark(c, 0, st);
+    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
+                       g, c->tcap);
+    const int grid = grid_for((nmax + 7) / 8, 1, 16384);
+    hipLaunchKernelGGL(k_ingest_blocks_mark<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
+                       (int64_t)0, count);
+    mark(c, 1, st);
+    edt_status r = dilate_region(c, st);
+    if (r) return r;
+    hipLaunchKernelGGL(k_ingest_blocks_write<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
+                       (int64_t)0, count);
+    mark(c, 2, st);
+    LAUNCH_CHECK();
+    return run_passes_global(c, st);
+}
+
+extern "C" {
+
+const char* edt_status_str(int s) {
+    switch (s) {
+        case EDT_OK: return "EDT_OK";
+        case EDT_ERR_ARG: return "EDT_ERR_ARG";
+        case EDT_ERR_RANGE: return "EDT_ERR_RANGE";
+        case EDT_ERR_CAPACITY: return "EDT_ERR_CAPACITY";
+        case EDT_ERR_HIP: return "EDT_ERR_HIP";
+        case EDT_ERR_STATE: return "EDT_ERR_STATE";
+        default: return "EDT_UNKNOWN";
+    }
+}
+
+int64_t edt_workspace_bytes(const edt_config* cfg) {
+    Layout L;
+    if (!layout_of(cfg, &L)) return EDT_ERR_ARG;
+    return L.total;
+}
+
+edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void* stream,
+                      edt_ctx** out) {
+    if (!out) return EDT_ERR_ARG;
+    *out = nullptr;
+    Layout L;
+    if (!layout_of(cfg, &L) || !d_ws) return EDT_ERR_ARG;
+    if (((uintptr_t)d_ws & 255) != 0) return EDT_ERR_ARG;
+    if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
+    edt_ctx* c = (edt_ctx*)calloc(1, sizeof(edt_ctx));
+    if (!c) return EDT_ERR_CAPACITY;
+    char* b = (char*)d_ws;
+    bind_workspace(c, cfg, L, b);
+    Grid& g = c->g;
     c->cap = 2 * g.dmax + 4;   // live envelope sites never exceed 2 * d_max + 2
     c->env_lds = (96 + 24) * 4 + (size_t)c->cap * 64 * 4;
     // the envelope ring must fit the device's LDS per workgroup
@@ -343,22 +391,10 @@ edt_status edt_create(const edt_config* cfg, void* d_ws, int64_t ws_bytes, void*
         }
     }
 
-    hipStream_t st = S(stream);
-    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(L.tcap * 128, 256, 4096)), dim3(256), 0, st,
-                       g, L.tcap);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.ukeys,
-                       L.ucap, KEY_EMPTY);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.ucap, 256, 4096)), dim3(256), 0, st, g.uvals,
-                       L.ucap, -1);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, g.cnt, (int64_t)64, 0);
-    // the block of D values that the window passes read for absent blocks of
-    // g1 / g2, in their representation (binary16 for small radii)
-    const uint32_t dw = win_f16(g.R) ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int32_t*)g.dblock, (int64_t)256,
-                       (int32_t)(dw | (dw << 16)));
-    if (hipGetLastError() != hipSuccess) {
+    const edt_status e = init_workspace(c, L, S(stream));
+    if (e != EDT_OK) {
         free(c);
-        return EDT_ERR_HIP;
+        return e;
     }
     *out = c;
     return EDT_OK;
@@ -468,7 +504,6 @@ edt_status edt_compact(edt_ctx* c, void* stream) {
     if (!c) return EDT_ERR_ARG;
     Grid& g = c->g;
     hipStream_t st = S(stream);
-    c->interior_valid = false;
     // the list lives in the g1 storage (rewritten by the passes that follow):
     // 12 bytes of coordinates and 64 bytes of occupancy per block; the count
     // in the first word of g2 (rewritten by the passes too)
@@ -479,20 +514,35 @@ edt_status edt_compact(edt_ctx* c, void* stream) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, count, (int64_t)1, 0);
     hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb, 256, 16384)), dim3(64), 0, st, g, count,
                        lxyz, (uint32_t*)lbits);
-    mark(c, 0, st);
-    hipLaunchKernelGGL(k_begin_global, dim3(grid_for(c->tcap * 128, 256, 4096)), dim3(256), 0, st,
-                       g, c->tcap);
-    const int grid = grid_for((mb + 7) / 8, 1, 16384);
-    hipLaunchKernelGGL(k_ingest_blocks_mark<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
-                       (int64_t)0, (const int32_t*)count);
-    mark(c, 1, st);
-    edt_status r = dilate_region(c, st);
-    if (r) return r;
-    hipLaunchKernelGGL(k_ingest_blocks_write<true>, dim3(grid), dim3(64), 0, st, g, lxyz, lbits,
-                       (int64_t)0, (const int32_t*)count);
-    mark(c, 2, st);
+    return rebuild_from_list(c, count, lxyz, lbits, mb, st);
+}
+
+edt_status edt_grow(edt_ctx* c, int64_t max_blocks, void* d_ws, int64_t ws_bytes, void* stream) {
+    if (!c || !d_ws || ((uintptr_t)d_ws & 255) != 0) return EDT_ERR_ARG;
+    edt_config cfg = c->cfg;
+    cfg.max_blocks = max_blocks;
+    Layout L;
+    if (!layout_of(&cfg, &L)) return EDT_ERR_ARG;
+    if (L.max_blocks < c->g.max_blocks) return EDT_ERR_ARG;   // the pool never shrinks here
+    if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
+    hipStream_t st = S(stream);
+    const Grid old = c->g;
+    edt_ctx n = *c;              // timing events, call number, envelope sizes carry over
+    bind_workspace(&n, &cfg, L, (char*)d_ws);
+    const edt_status e = init_workspace(&n, L, st);
+    if (e != EDT_OK) return e;
+    // the old pool's blocks holding an obstacle, gathered into the new
+    // workspace's g1 storage (76 bytes per block, within its 1 KiB per slot)
+    const int64_t mb_old = old.max_blocks;
+    int32_t* count = (int32_t*)n.g.g2;
+    int32_t* lxyz = (int32_t*)n.g.g1;
+    uint8_t* lbits = (uint8_t*)n.g.g1 + ((12 * mb_old + 255) & ~(int64_t)255);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, count, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb_old, 256, 16384)), dim3(64), 0, st, old,
+                       count, lxyz, (uint32_t*)lbits);
     LAUNCH_CHECK();
-    return run_passes_global(c, st);
+    *c = n;                      // from here on the context lives in the new workspace
+    return rebuild_from_list(c, count, lxyz, lbits, mb_old, st);
 }
 
 // The incremental transform over n change entries; n_dev, when given, holds
@@ -509,9 +559,11 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     c->upd_gen = c->upd_gen >= 0x7ffffffe ? 1 : c->upd_gen + 1;
     const int32_t gen = c->upd_gen;
     hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev, gen);
+    // every block the call needs exists before any occupancy changes
     hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
+    hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g,
+                       gen);
     hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
-    hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g);
     // fronts: one workgroup per seed block (at most one per change entry),
     // wide enough for the seed's whole neighbourhood when it has at most 1024
     // blocks

@@ -42,6 +42,7 @@ enum : uint32_t {
     F_YS = 16u,      // g2 recomputed in the current update
     F_RAISE = 32u,   // marked by the raise front
     F_LOWER = 64u,   // marked by the lower front
+    F_NEWDIL = 128u, // gains its first obstacle in the current update (listed for dilation)
 };
 
 // device counters (int32 slots of the counter array).  C_ABORT: the global

@@ -1547,7 +1547,12 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
 }
 
 // New blocks for voxels that become occupied (initialised to background by
-// the claiming wave).
+// the claiming wave), and the list of blocks that gain their first obstacle:
+// their R-neighbourhood joins the pool in the next kernel, before any
+// occupancy changes, so that a full pool cancels the whole call and leaves
+// the map as it was.  A block created here has no obstacle yet; an existing
+// one without F_DILATED never had one.  A block may be listed twice (two
+// entries race on a fresh slot); growing its neighbourhood twice is harmless.
 __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
                             const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
                             int32_t gen) {
@@ -1571,6 +1576,19 @@ __global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
         const int32_t sl = claim_slots(g, created, e, key, 0u);
         if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
         init_slots(g, sl);
+        bool newdil = created && sl >= 0;
+        int32_t dslot = sl;
+        if (!created && e >= 0) {
+            const int32_t s2 = __hip_atomic_load(&g.tslots[e], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (s2 >= 0 && !(g.flags[s2] & (F_DILATED | F_NEWDIL))) {
+                const uint32_t o = atomicOr(&g.flags[s2], F_NEWDIL);
+                newdil = !(o & (F_DILATED | F_NEWDIL));
+                dslot = s2;
+            }
+        }
+        const int j = wave_append(newdil, &g.cnt[C_NNEWDIL]);
+        if (newdil) g.list_newdil[j] = dslot;
     }
 }
 
@@ -1584,6 +1602,14 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
                             const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
                             int32_t gen) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    {
+        // the blocks listed for dilation have been dilated (or the call is
+        // cancelled): their listing mark goes
+        const int64_t nd = g.cnt[C_NNEWDIL];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nd;
+             i += (int64_t)gridDim.x * blockDim.x)
+            atomicAnd(&g.flags[g.list_newdil[i]], ~F_NEWDIL);
+    }
     if (g.cnt[C_UABORT] == gen) {
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
              i += (int64_t)gridDim.x * blockDim.x) {
@@ -1634,18 +1660,16 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
             atomicAdd(&g.cnt[C_NADD], __popcll(ma));
             atomicAdd(&g.cnt[C_NREM], __popcll(mr));
         }
-        int j = wave_append(first_seed, &g.cnt[C_NSEED]);
+        const int j = wave_append(first_seed, &g.cnt[C_NSEED]);
         if (first_seed) g.list_seed[j] = slot;
-        j = wave_append(new_dil, &g.cnt[C_NNEWDIL]);
-        if (new_dil) {
-            g.list_newdil[j] = slot;
-            atomicAdd(&g.cnt[C_NDIL], 1);
-        }
+        if (new_dil) atomicAdd(&g.cnt[C_NDIL], 1);   // obstacle blocks (statistics)
     }
 }
 
-// Blocks that just became obstacle blocks bring their R-neighbourhood in.
-__global__ void k_upd_dilate(Grid g) {
+// Blocks that gain their first obstacle bring their R-neighbourhood in
+// (before the occupancy changes; a full pool cancels the call).
+__global__ void k_upd_dilate(Grid g, int32_t gen) {
+    if (g.cnt[C_UABORT] == gen) return;
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NNEWDIL] * w3;
     const int lane = __lane_id();
@@ -1665,10 +1689,15 @@ __global__ void k_upd_dilate(Grid g) {
             key = pack_key(bx, by, bz);
             if (bx >= 0 && by >= 0 && bz >= 0 && bx < g.nbx && by < g.nby && bz < g.nbz) {
                 e = insert_block(g, bx, by, bz, &created);
-                if (e < 0) set_error(g, -3);
+                if (e < 0) {
+                    set_error(g, -3);
+                    g.cnt[C_UABORT] = gen;
+                }
             }
         }
-        init_slots(g, claim_slots(g, created, e, key, 0u));
+        const int32_t sl = claim_slots(g, created, e, key, 0u);
+        if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
+        init_slots(g, sl);
     }
 }
 
