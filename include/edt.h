@@ -285,9 +285,11 @@ typedef struct {
  *   waves_per_cu  waves resident per compute unit (0 = default, <= 64)
  *   chunk         work items taken per queue atomic (1 .. 1024)
  *   schedule      0 = dynamic queue, 1 = static stride
- *   wg_waves      waves per workgroup: 1, 2 or 4 (0 = 4); each wave takes
- *                 its own work items, the workgroup size only changes how
- *                 the waves are dispatched and share a compute unit      */
+ *   wg_waves      waves per workgroup: 1, 2, 4 or 8 (0 = 4); each wave
+ *                 takes its own work items, the workgroup size only changes
+ *                 how the waves are dispatched and share a compute unit, and
+ *                 how many workgroups meet at the fused launch's grid-wide
+ *                 barriers (fewer is cheaper)                             */
 typedef struct {
     int32_t lrun;
     int32_t waves_per_cu;

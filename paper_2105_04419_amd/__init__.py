@@ -515,9 +515,6 @@ class Batch:
             raise EdtError("edt_batch_workspace_bytes", int(nbytes))
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-        nb = ((nx + 7) // 8) * ((ny + 7) // 8) * ((nz + 7) // 8)
-        self.extent_blocks = nb
-        self.max_blocks = min(int(max_blocks), nb) if max_blocks else nb
         h = ctypes.c_void_p()
         _check("edt_batch_create", L.edt_batch_create(self._maps, n, self.d_max, _ptr(self.workspace),
                                                       int(nbytes), _stream(stream), ctypes.byref(h)))

@@ -27,7 +27,7 @@ SPACE = {
     "chunk": [1, 4, 16],
     "waves_per_cu": [4, 8, 16],
     "schedule": [0, 1],
-    "wg_waves": [1, 2, 4],
+    "wg_waves": [1, 2, 4, 8],
 }
 
 

@@ -175,7 +175,9 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
         for (int x = 7; x >= 0; --x) {
             rr = (rr + 1u) & ~mk[x];
             const uint32_t v = min(min(d[x], rr), dmax);
-            buf[j * LS + rofs + 8 * x] = (uint16_t)(v * v);
+            // g1 in the window's representation (binary16 for small radii)
+            buf[j * LS + rofs + 8 * x] = win_f16(M)
+                ? __builtin_bit_cast(uint16_t, (_Float16)(v * v)) : (uint16_t)(v * v);
         }
     }
     // block j: lane writes g1 elements 8 lane .. 8 lane + 7 (16 bytes)
@@ -216,7 +218,7 @@ __device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
             d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
         }
     };
-    window_min<M, true>(by0, len, Dp, blk, emit);
+    window_min<M, true, win_f16(M)>(by0, len, Dp, blk, emit);
 }
 
 // phase 2: windowed minimum along z, g2 -> dense int32 field.  An item is a
@@ -253,11 +255,11 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
             const int z0 = 8 * ob + o, z1 = 8 * ob + 8 + o;
             int32_t* p0 = (col_ok && z0 < m.nz) ? col + z0 * zstride : dummy + lane;
             int32_t* p1 = (col_ok && has1 && z1 < m.nz) ? col + z1 * zstride : dummy + lane;
-            *p0 = (int)(v & 0xffffu);
-            *p1 = (int)(v >> 16);
+            *p0 = win_f16(M) ? f16_int(v & 0xffffu) : (int)(v & 0xffffu);
+            *p1 = win_f16(M) ? f16_int(v >> 16) : (int)(v >> 16);
         }
     };
-    window_min<M, true>(bz0, len, Dp, blk, emit);
+    window_min<M, true, win_f16(M)>(bz0, len, Dp, blk, emit);
 }
 
 template <int M>
@@ -280,7 +282,8 @@ __device__ void run_phase(const BArgs& a, int phase, int lo, int hi, int cidx) {
     const int wpb = blockDim.x >> 6;
     const int wid = blockIdx.x * wpb + (threadIdx.x >> 6);
     const int nwaves = gridDim.x * wpb;
-    const uint32_t Dp = (uint32_t)a.D | ((uint32_t)a.D << 16);
+    const uint32_t Dw = win_f16(M) ? f16_bits((uint32_t)a.D) : (uint32_t)a.D;
+    const uint32_t Dp = Dw | (Dw << 16);        // D in the window's representation
     if (a.schedule == 0) {
         for (;;) {
             int base = 0;
@@ -297,7 +300,7 @@ __device__ void run_phase(const BArgs& a, int phase, int lo, int hi, int cidx) {
 
 // FUSED: phases 0..2 of all maps, grid barrier between phases.
 template <int M>
-__global__ void __launch_bounds__(256) k_batch_fused(BArgs a) {
+__global__ void __launch_bounds__(512) k_batch_fused(BArgs a) {
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
     const int n = a.n_maps;
@@ -310,24 +313,56 @@ __global__ void __launch_bounds__(256) k_batch_fused(BArgs a) {
 
 // PER_MAP: one phase of one map.
 template <int M>
-__global__ void __launch_bounds__(256) k_batch_phase(BArgs a, int phase, int map) {
+__global__ void __launch_bounds__(512) k_batch_phase(BArgs a, int phase, int map) {
     const int* pref = a.pref + phase * (a.n_maps + 1);
     run_phase<M>(a, phase, pref[map], pref[map + 1], phase * (a.n_maps + 1) + map);
 }
 
-__global__ void k_batch_prefix(const MapDev* maps, int n, int lrun, int32_t* pref, int32_t* queues) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int acc[3] = {0, 0, 0};
-        for (int i = 0; i <= n; ++i) {
-            for (int p = 0; p < 3; ++p) pref[p * (n + 1) + i] = acc[p];
-            if (i == n) break;
+// Item prefix sums of the three phases over the maps (processing order), one
+// workgroup of 1024 threads: every thread counts one map's items, a scan
+// across the workgroup gives the offsets, chunks of 1024 maps carry on.
+__global__ void __launch_bounds__(1024) k_batch_prefix(const MapDev* maps, int n, int lrun,
+                                                       int32_t* pref) {
+    __shared__ int wsum[16][3];
+    __shared__ int carry[3];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t < 3) carry[t] = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < n; i0 += 1024) {
+        const int i = i0 + t;
+        int c[3] = {0, 0, 0};
+        if (i < n) {
             const MapDev m = maps[i];
-            acc[0] += m.nxr * m.nby * m.nbz;
-            acc[1] += m.nbx * m.nbz * ((m.nby + lrun - 1) / lrun);
-            acc[2] += m.nxr * m.ny * ((m.nbz + lrun - 1) / lrun);
+            c[0] = m.nxr * m.nby * m.nbz;
+            c[1] = m.nbx * m.nbz * ((m.nby + lrun - 1) / lrun);
+            c[2] = m.nxr * m.ny * ((m.nbz + lrun - 1) / lrun);
         }
+        int incl[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            incl[p] = c[p];
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl[p], o);
+                if (lane >= o) incl[p] += v;
+            }
+            if (lane == 63) wsum[w][p] = incl[p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            int before = carry[p];
+            for (int v = 0; v < w; ++v) before += wsum[v][p];
+            if (i < n) pref[p * (n + 1) + i] = before + incl[p] - c[p];
+            if (i == n - 1) pref[p * (n + 1) + n] = before + incl[p];
+        }
+        __syncthreads();
+        if (t < 3) {
+            int tot = 0;
+            for (int v = 0; v < 16; ++v) tot += wsum[v][t];
+            carry[t] += tot;
+        }
+        __syncthreads();
     }
-    for (int i = threadIdx.x; i < 3 * (n + 1); i += blockDim.x) queues[i] = 0;
 }
 
 // The map of every work item of every phase (one workgroup per map), so an
@@ -419,8 +454,9 @@ edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<M>, bs, lds) !=
             hipSuccess)
             return EDT_ERR_HIP;
-        const int wgs_per_cu =
+        int wgs_per_cu =
             waves_per_cu > 0 ? (waves_per_cu + wg_waves - 1) / wg_waves : 8 / wg_waves;
+        if (wgs_per_cu < 1) wgs_per_cu = 1;
         const int g = b->cus * (wgs_per_cu < per_cu ? wgs_per_cu : per_cu);
         if (g < 1) return EDT_ERR_HIP;
         void* args[] = {(void*)&a};
@@ -519,7 +555,10 @@ edt_status edt_batch_create(const edt_batch_map* maps, int32_t n_maps, int32_t d
         free(b);
         return EDT_ERR_HIP;
     }
-    const uint32_t D = (uint32_t)(d_max * d_max);
+    // the block of D values read for blocks beyond a map, in the window's
+    // representation (binary16 for small radii)
+    const uint32_t D = win_f16(b->M) ? f16_bits((uint32_t)(d_max * d_max))
+                                     : (uint32_t)(d_max * d_max);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (uint32_t*)(b->ws + L.off_dblock),
                        (int64_t)256, D | (D << 16));
     if (hipStreamSynchronize(st) != hipSuccess) {   // the host map table may go away now
@@ -548,7 +587,7 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
     if (t.wg_waves == 0) t.wg_waves = 4;
     if (t.lrun < 1 || t.lrun > 64 || t.chunk < 1 || t.chunk > 1024 || t.waves_per_cu < 0 ||
         t.waves_per_cu > 64 || (t.schedule != 0 && t.schedule != 1) ||
-        (t.wg_waves != 1 && t.wg_waves != 2 && t.wg_waves != 4))
+        (t.wg_waves != 1 && t.wg_waves != 2 && t.wg_waves != 4 && t.wg_waves != 8))
         return EDT_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     const BLayout& L = b->L;
@@ -570,10 +609,19 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
     a.schedule = t.schedule;
     a.itemmap = (const int32_t*)(b->ws + L.off_itemmap);
     a.icap = L.icap;
-    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(256), 0, st, a.maps, b->n, t.lrun,
-                       (int32_t*)a.pref, a.queues);
-    hipLaunchKernelGGL(k_batch_itemmap, dim3(b->n), dim3(256), 0, st, a.pref, b->n,
-                       (int32_t*)a.itemmap, a.icap);
+    // item offsets and the item -> map table depend on the run length only:
+    // rebuilt when it changes; the dynamic schedule's grab counters start at
+    // zero on every run
+    if (t.lrun != b->last_lrun) {
+        hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(1024), 0, st, a.maps, b->n, t.lrun,
+                           (int32_t*)a.pref);
+        hipLaunchKernelGGL(k_batch_itemmap, dim3(b->n), dim3(256), 0, st, a.pref, b->n,
+                           (int32_t*)a.itemmap, a.icap);
+        b->last_lrun = t.lrun;
+    }
+    if (t.schedule == 0)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (uint32_t*)a.queues,
+                           (int64_t)3 * (b->n + 1), 0u);
     if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
     switch (b->M) {
         case 1: return launch_batch<1>(b, a, mode, t.waves_per_cu, t.wg_waves, st);

@@ -56,6 +56,8 @@ def test_small_batch_all_modes(dmax):
     {"lrun": 16, "chunk": 64, "schedule": 1, "waves_per_cu": 8, "wg_waves": 4},
     {"lrun": 64, "chunk": 2, "schedule": 1, "waves_per_cu": 1, "wg_waves": 1},
     {"lrun": 8, "chunk": 4, "schedule": 0, "waves_per_cu": 5, "wg_waves": 2},
+    {"lrun": 4, "chunk": 1, "schedule": 1, "waves_per_cu": 16, "wg_waves": 8},
+    {"lrun": 2, "chunk": 16, "schedule": 0, "waves_per_cu": 4, "wg_waves": 8},
 ])
 def test_schedules_are_bit_identical(tune):
     maps = small_maps(11, 9, 8, 90)
@@ -71,7 +73,7 @@ def test_rejects_bad_schedule():
     from paper_2105_04419_amd import EdtError
     b = Batch([(8, 8, 8)], 4)
     occ = b.pack([np.zeros((8, 8, 8), np.uint8)])
-    for bad in ({"wg_waves": 3}, {"wg_waves": 8}, {"lrun": 0}, {"chunk": 2000},
+    for bad in ({"wg_waves": 3}, {"wg_waves": 16}, {"lrun": 0}, {"chunk": 2000},
                 {"schedule": 2}, {"waves_per_cu": 65}):
         t = {"lrun": 8, "chunk": 4, "schedule": 0, "waves_per_cu": 8, "wg_waves": 4}
         t.update(bad)
@@ -119,3 +121,15 @@ def test_degenerate_and_extreme_maps():
     m = (rng.random((5, 17, 33)) < 0.05).astype(np.uint8)
     out = single.run(single.pack([m]), mode=FUSED)
     check(single, [m], out, 24, "one map")
+
+
+def test_run_length_changes_between_runs():
+    # item offsets are kept for the last run length: switching back and forth
+    # must rebuild them every time
+    maps = small_maps(12, 7, 8, 80)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
+    occ = b.pack(maps)
+    ref = b.run(occ, mode=PER_MAP)
+    for lrun in (2, 16, 2, 8, 16):
+        t = {"lrun": lrun, "chunk": 4, "schedule": 1, "waves_per_cu": 8, "wg_waves": 4}
+        assert torch.equal(b.run(occ, mode=FUSED, tune=t), ref), lrun
