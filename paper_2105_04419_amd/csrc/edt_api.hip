@@ -58,7 +58,7 @@ struct Layout {
 
 enum {
     O_TKEYS, O_TSLOTS, O_BKEY, O_OCC, O_G1, O_G2, O_S, O_BMAX, O_FLAGS, O_CNT,
-    O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR, O_SEEDBOX,
+    O_YI, O_ZI, O_SEED, O_DIRTY, O_XS, O_YS, O_NEWDIL, O_CHGA, O_CHGR,
     O_UKEYS, O_UVALS, O_UPOS, O_DUMMY, O_DBLOCK, O_TOBST, O_TLIST, O_BMIN, O_TINFO, O_TFLAG, O_IIDX, O_ILIST, O_IC1, O_IC2, O_SCANXYZ, O_SCANST, O_SCANCNT, O_SCANOFF, O_SCANBLK, O_N
 };
 
@@ -94,7 +94,7 @@ bool layout_of(const edt_config* c, Layout* L) {
     const int64_t sz[O_N] = {
         L->tcap * 8, L->tcap * 2048, mb * 8, mb * 64, mb * 1024, mb * 1024, mb * 1024, mb * 4,
         mb * 4, 64 * 4,
-        mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64, mb * 128,
+        mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 4, mb * 64, mb * 64,
         L->ucap * 8, L->ucap * 4, mc * 4, 256 * 256 * 4 + 1024, 1024,
         L->tcap * 64, L->tcap * 4, mb * 4, L->tcap * 32, L->tcap * 4,
         mi ? mb * 4 : 0, mi * 4, mi * 1024, mi * 1024, mc * 12, mc, 256, mc * 8, (mc / 1024 + 1) * 16};
@@ -268,7 +268,6 @@ static void bind_workspace(edt_ctx* c, const edt_config* cfg, const Layout& L, c
     g.list_newdil = (int32_t*)(b + L.off[O_NEWDIL]);
     g.chg_add = (uint32_t*)(b + L.off[O_CHGA]);
     g.chg_rem = (uint32_t*)(b + L.off[O_CHGR]);
-    g.seed_box = (int32_t*)(b + L.off[O_SEEDBOX]);
     g.ukeys = (unsigned long long*)(b + L.off[O_UKEYS]);
     g.uvals = (int32_t*)(b + L.off[O_UVALS]);
     g.upos = (int32_t*)(b + L.off[O_UPOS]);

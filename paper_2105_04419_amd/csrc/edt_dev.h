@@ -89,9 +89,6 @@ struct Grid {
     int32_t* list_newdil;    // update: blocks that became obstacle blocks
     uint32_t* chg_add;       // [slot][16] voxels added in this update
     uint32_t* chg_rem;       // [slot][16] voxels removed in this update
-    int32_t* seed_box;       // [seed][32]: packed boxes of the added and removed voxels,
-                             // block coordinates, then (d_max <= 64) the 27 tiles
-                             // around the seed's tile
     unsigned long long* ukeys;
     int32_t* uvals;
     int32_t* upos;
