@@ -218,4 +218,27 @@ __device__ inline int wave_min(int v) {
     return v;
 }
 
+// Wave-wide max / min of two packed unsigned 16-bit halves (each half on its
+// own), returned to every lane as a uniform value.  Every lane of the wave
+// must be active.  Data moves between lanes with DPP: swaps inside quads, the
+// half-row and row mirrors make each row of 16 lanes uniform, the row
+// broadcasts of lanes 15 and 31 fold the four rows into lane 63.
+template <bool MAX>
+__device__ inline uint32_t wave_reduce_pk_u16(uint32_t v) {
+    typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+    auto op = [](uint32_t a, uint32_t b) -> uint32_t {
+        const u2 x = __builtin_bit_cast(u2, a), y = __builtin_bit_cast(u2, b);
+        return __builtin_bit_cast(uint32_t, MAX ? __builtin_elementwise_max(x, y)
+                                                : __builtin_elementwise_min(x, y));
+    };
+    v = op(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));  // lane ^ 1
+    v = op(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));  // lane ^ 2
+    v = op(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false)); // half-row mirror
+    v = op(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false)); // row mirror
+    // rows 1 and 3 take lane 15 / 47 of the row before; then rows 2 and 3 take lane 31
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 }  // namespace edt

@@ -1096,55 +1096,50 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
 // ---------------------------------------------------------------------------
 // Stores the results of one step of the windowed minimum: acc[o] holds output
 // row o of two consecutive blocks (low half: slot0, high half: slot1; a
-// negative slot sends its half to the wave's dummy buffer).  Pass Y writes g2
-// (z-major rows); pass Z writes s and the block maxima.
+// negative slot has no storage and its half is dropped).  Pass Y writes g2
+// (z-major rows) and the block minima; pass Z writes s and the block maxima.
+// The slots are wave-uniform, so the branches are scalar and each store
+// takes its block's base from scalar registers and the row from an
+// immediate offset.  The block extrema are reduced on the packed values,
+// both blocks at once (binary16 patterns of non-negative values order like
+// the values).
 template <int AXIS, bool F16>
 __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, const u16x2* acc,
-                                 int lane, uint32_t* dummy) {
+                                 int lane) {
     if (AXIS == 1) {
         const int out_lane = (lane & 7) * 8 + (lane >> 3);
-        uint16_t* d0 = slot0 >= 0 ? g.g2 + (int64_t)slot0 * 512 + out_lane : (uint16_t*)dummy + lane;
-        uint16_t* d1 = slot1 >= 0 ? g.g2 + (int64_t)slot1 * 512 + out_lane
-                                  : (uint16_t*)dummy + 64 + lane;
-        const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
-        u16x2 mn = acc[0];
+        if (slot0 >= 0) {
+            uint16_t* d0 = g.g2 + (int64_t)slot0 * 512 + out_lane;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const uint32_t v = as_u32(acc[o]);
-            d0[s0 * o] = (uint16_t)(v & 0xffffu);
-            d1[s1 * o] = (uint16_t)(v >> 16);
-            mn = __builtin_elementwise_min(mn, acc[o]);
+            for (int o = 0; o < 8; ++o) d0[64 * o] = acc[o].x;
+        }
+        if (slot1 >= 0) {
+            uint16_t* d1 = g.g2 + (int64_t)slot1 * 512 + out_lane;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) d1[64 * o] = acc[o].y;
         }
         // least output of each block, for the skip bounds of pass Z
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            mn = __builtin_elementwise_min(mn, as_u16x2((uint32_t)__shfl_xor((int)as_u32(mn), o)));
-        uint16_t* f0 = slot0 >= 0 ? g.bmin2 + slot0 : (uint16_t*)(dummy + 130);
-        uint16_t* f1 = slot1 >= 0 ? g.bmin2 + slot1 : (uint16_t*)(dummy + 131);
+        const uint32_t m = wave_reduce_pk_u16<false>(as_u32(min8<F16>(acc)));
         if (lane == 0) {
-            *f0 = F16 ? (uint16_t)f16_int(mn.x) : mn.x;
-            *f1 = F16 ? (uint16_t)f16_int(mn.y) : mn.y;
+            if (slot0 >= 0) g.bmin2[slot0] = F16 ? (uint16_t)f16_int(m & 0xffffu) : (uint16_t)m;
+            if (slot1 >= 0) g.bmin2[slot1] = F16 ? (uint16_t)f16_int(m >> 16) : (uint16_t)(m >> 16);
         }
     } else {
-        uint16_t* d0 = slot0 >= 0 ? g.s + (int64_t)slot0 * 512 + lane : (uint16_t*)dummy + lane;
-        uint16_t* d1 = slot1 >= 0 ? g.s + (int64_t)slot1 * 512 + lane : (uint16_t*)dummy + 64 + lane;
-        const int s0 = slot0 >= 0 ? 64 : 0, s1 = slot1 >= 0 ? 64 : 0;
-        int m0 = 0, m1 = 0;
+        const uint32_t m = wave_reduce_pk_u16<true>(as_u32(max8<F16>(acc)));
+        if (slot0 >= 0) {
+            uint16_t* d0 = g.s + (int64_t)slot0 * 512 + lane;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const uint32_t v = as_u32(acc[o]);
-            const int v0 = F16 ? f16_int(v & 0xffffu) : (int)(v & 0xffffu);
-            const int v1 = F16 ? f16_int(v >> 16) : (int)(v >> 16);
-            d0[s0 * o] = (uint16_t)v0;
-            d1[s1 * o] = (uint16_t)v1;
-            m0 = max(m0, v0);
-            m1 = max(m1, v1);
+            for (int o = 0; o < 8; ++o)
+                d0[64 * o] = F16 ? (uint16_t)f16_int(acc[o].x) : acc[o].x;
+            if (lane == 0) g.bmax[slot0] = F16 ? f16_int(m & 0xffffu) : (int)(m & 0xffffu);
         }
-        m0 = wave_max(m0);
-        m1 = wave_max(m1);
-        int32_t* b0 = slot0 >= 0 ? g.bmax + slot0 : (int32_t*)dummy + 128;
-        int32_t* b1 = slot1 >= 0 ? g.bmax + slot1 : (int32_t*)dummy + 129;
-        if (lane == 0) { *b0 = m0; *b1 = m1; }
+        if (slot1 >= 0) {
+            uint16_t* d1 = g.s + (int64_t)slot1 * 512 + lane;
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                d1[64 * o] = F16 ? (uint16_t)f16_int(acc[o].y) : acc[o].y;
+            if (lane == 0) g.bmax[slot1] = F16 ? f16_int(m >> 16) : (int)(m >> 16);
+        }
     }
 }
 
@@ -1158,7 +1153,6 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
     const int lane = threadIdx.x;
     const int64_t nit = g.cnt[item_counter];
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
-    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
     constexpr bool F16 = win_f16(M);
     const uint32_t Dw = F16 ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
     const uint32_t Dp = Dw | (Dw << 16);      // D in the window's representation
@@ -1200,7 +1194,7 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
         auto emit = [&](int ob, const u16x2* acc, bool has1) {
             const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[base + ob]);
             const int32_t slot1 = __builtin_amdgcn_readfirstlane(has1 ? sl[base + ob + 1] : -1);
-            win_store<AXIS, F16>(g, slot0, slot1, acc, lane, dummy);
+            win_store<AXIS, F16>(g, slot0, slot1, acc, lane);
         };
         window_min<M, false, F16>(hb, len, Dp, blk, emit, [](int) { return true; }, sk);
         finish_run(g, sl, len, AXIS, runflag);
@@ -1219,7 +1213,6 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
     const int lane = threadIdx.x;
     const int64_t ncol = (int64_t)g.cnt[C_NTILE] * 64;
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
-    uint32_t* dummy = g.dummy + (blockIdx.x & 255) * 256;
     constexpr bool F16 = win_f16(M);
     const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);       // integer D (field s)
     const uint32_t Dw = F16 ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
@@ -1281,7 +1274,7 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
             auto emit = [&](int ob, const u16x2* acc, bool) {
                 const int32_t slot0 = __builtin_amdgcn_readfirstlane(sl[M + ob]);
                 const int32_t slot1 = __builtin_amdgcn_readfirstlane(sl[M + ob + 1]);
-                win_store<AXIS, F16>(g, slot0, slot1, acc, lane, dummy);
+                win_store<AXIS, F16>(g, slot0, slot1, acc, lane);
             };
             auto need = [&](int ob) { return sl[M + ob] >= 0 || sl[M + ob + 1] >= 0; };
             window_min<M, false, F16>(0, 8, Dpw, blk, emit, need, sk);

@@ -11,9 +11,9 @@
 // outward from 0, and the wave stops early once every output is already no
 // larger than the square of the next offset.  The 2M + 2 input blocks of the
 // window stay in registers and slide by two blocks per step.  Callers make
-// every load and store unconditional (absent blocks read a block of D values,
-// halo outputs go to a scratch row) so the loop issues a fixed sequence of
-// memory operations.
+// every load unconditional (absent blocks read a block of D values) and
+// guard stores only by wave-uniform conditions, so the loop issues a fixed
+// sequence of loads.
 //
 // Half-precision mode (F16, for d_max <= 40, so D <= 1600): the values are
 // held as IEEE binary16 instead of integers.  Every integer up to 2048 is
@@ -55,6 +55,40 @@ __device__ inline int f16_int(uint32_t bits) {
 }
 __device__ inline uint32_t word_of(const uint4& v, int w) {
     return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+// Largest / least of the 8 packed output pairs, per half.  Binary16 values
+// here are non-negative, so the float extrema (three-way packed
+// instructions) equal the extrema of the bit patterns.
+template <bool F16>
+__device__ inline u16x2 max8(const u16x2* a) {
+    if (F16) {
+        const h16x2 x = __builtin_elementwise_maximum(
+            __builtin_elementwise_maximum(as_h16x2(a[0]), as_h16x2(a[1])), as_h16x2(a[2]));
+        const h16x2 y = __builtin_elementwise_maximum(
+            __builtin_elementwise_maximum(as_h16x2(a[3]), as_h16x2(a[4])), as_h16x2(a[5]));
+        const h16x2 z = __builtin_elementwise_maximum(as_h16x2(a[6]), as_h16x2(a[7]));
+        return as_u16x2(__builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+    }
+    u16x2 m = __builtin_elementwise_max(a[0], a[1]);
+#pragma unroll
+    for (int o = 2; o < 8; ++o) m = __builtin_elementwise_max(m, a[o]);
+    return m;
+}
+template <bool F16>
+__device__ inline u16x2 min8(const u16x2* a) {
+    if (F16) {
+        const h16x2 x = __builtin_elementwise_minimum(
+            __builtin_elementwise_minimum(as_h16x2(a[0]), as_h16x2(a[1])), as_h16x2(a[2]));
+        const h16x2 y = __builtin_elementwise_minimum(
+            __builtin_elementwise_minimum(as_h16x2(a[3]), as_h16x2(a[4])), as_h16x2(a[5]));
+        const h16x2 z = __builtin_elementwise_minimum(as_h16x2(a[6]), as_h16x2(a[7]));
+        return as_u16x2(__builtin_elementwise_minimum(__builtin_elementwise_minimum(x, y), z));
+    }
+    u16x2 m = __builtin_elementwise_min(a[0], a[1]);
+#pragma unroll
+    for (int o = 2; o < 8; ++o) m = __builtin_elementwise_min(m, a[o]);
+    return m;
 }
 
 // Output blocks first .. first + count - 1 (indices in the caller's run).
@@ -110,6 +144,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
     }
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
+        u16x2 acc[8];
         if (need(ob)) {
             // bit j of the shifted masks: block ob - M + j
             const int sh = ob - first;
@@ -119,7 +154,6 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                 const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
                 flat = flat && ((sk.g[G] >> sh) & CG) == CG;
             }
-            u16x2 acc[8];
             if (flat) {
 #pragma unroll
                 for (int o = 0; o < 8; ++o) acc[o] = as_u16x2(Dp);
@@ -133,9 +167,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                 // per-lane bound: group G offers candidates no smaller than the
                 // least input in its two position ranges plus (8G)^2; mx is the
                 // lane's largest output so far (both halves)
-                u16x2 mx = acc[0];
-#pragma unroll
-                for (int o = 1; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
+                u16x2 mx = LB ? max8<F16>(acc) : acc[0];
 #pragma unroll
                 for (int G = 0; G < M; ++G) {
                     const uint64_t CG = (7ull << (M - G - 1)) | (7ull << (M + G));
@@ -213,9 +245,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                     // are <= (8G + 8)^2, the least any further candidate adds
                     // (binary16 patterns order like their values)
                     if (G + 1 < M) {
-                        mx = __builtin_elementwise_max(acc[0], acc[1]);
-#pragma unroll
-                        for (int o = 2; o < 8; ++o) mx = __builtin_elementwise_max(mx, acc[o]);
+                        mx = max8<F16>(acc);
                         const uint32_t sq = (8 * G + 8) * (8 * G + 8);
                         const int lim = F16 ? (int)f16_bits(sq) : (int)sq;
                         const bool more = (int)mx.x > lim || (int)mx.y > lim;
@@ -223,10 +253,11 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                     }
                 }
             }
-            emit(ob, acc, ob + 1 < first + count);
         }
         // slide: pairs move down by 16 positions; the 16 new ones pair the
-        // old last block with N0 and N0 with N1
+        // old last block with N0 and N0 with N1.  This waits for the loads of
+        // N0 and N1 (and the stores before them), so it comes before this
+        // step's stores, which then stay in flight during the next step.
 #pragma unroll
         for (int q = 0; q + 16 < NP; ++q) P[q] = P[q + 16];
 #pragma unroll
@@ -238,6 +269,7 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
                                                            word_of(N0, z >> 1), sel));
         }
         Wl = N1;
+        if (need(ob)) emit(ob, acc, ob + 1 < first + count);
     }
 }
 
