@@ -167,12 +167,13 @@ edt_status edt_compact(edt_ctx* ctx, void* stream);
  * the context onto the caller's new workspace d_ws (256-byte aligned, at
  * least edt_workspace_bytes of the context's configuration with max_blocks
  * replaced by the new max_blocks, which must not be smaller than the current
- * capacity).  The map is carried over: the blocks holding an obstacle are
- * gathered from the old pool and the pool and field are rebuilt in the new
- * workspace, so s, the occupancy and every later result are those the old
- * context would give (interior distances must be recomputed).  The old
- * workspace is read by work enqueued on `stream` and may be released once
- * that work has completed.  An update cancelled because the pool was full
+ * capacity).  The map is carried over without recomputation: every pool
+ * block (occupancy, intermediates, field, per-block state) keeps its slot
+ * number and is copied, and the tile index is rehashed into the new table,
+ * so s, the occupancy and every later result are those the old context
+ * would give (interior distances must be recomputed).  The old workspace is
+ * read by work enqueued on `stream` and may be released once that work has
+ * completed.  An update cancelled because the pool was full
  * (edt_get_error returns EDT_ERR_CAPACITY) leaves the map unchanged, so it
  * can be issued again after edt_grow. */
 edt_status edt_grow(edt_ctx* ctx, int64_t max_blocks, void* d_ws, int64_t ws_bytes,

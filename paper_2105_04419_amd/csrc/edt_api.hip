@@ -525,23 +525,37 @@ edt_status edt_grow(edt_ctx* c, int64_t max_blocks, void* d_ws, int64_t ws_bytes
     if (L.max_blocks < c->g.max_blocks) return EDT_ERR_ARG;   // the pool never shrinks here
     if (ws_bytes < L.total) return EDT_ERR_CAPACITY;
     hipStream_t st = S(stream);
-    const Grid old = c->g;
+    const Grid o = c->g;
     edt_ctx n = *c;              // timing events, call number, envelope sizes carry over
     bind_workspace(&n, &cfg, L, (char*)d_ws);
-    const edt_status e = init_workspace(&n, L, st);
+    edt_status e = init_workspace(&n, L, st);
     if (e != EDT_OK) return e;
-    // the old pool's blocks holding an obstacle, gathered into the new
-    // workspace's g1 storage (76 bytes per block, within its 1 KiB per slot)
-    const int64_t mb_old = old.max_blocks;
-    int32_t* count = (int32_t*)n.g.g2;
-    int32_t* lxyz = (int32_t*)n.g.g1;
-    uint8_t* lbits = (uint8_t*)n.g.g1 + ((12 * mb_old + 255) & ~(int64_t)255);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, count, (int64_t)1, 0);
-    hipLaunchKernelGGL(k_compact_gather, dim3(grid_for(mb_old, 256, 16384)), dim3(64), 0, st, old,
-                       count, lxyz, (uint32_t*)lbits);
+    const Grid& g = n.g;
+    // tile tables: rehashed into the new capacity; the position map lives in
+    // the new g1 storage until g1 is copied below (stream order)
+    int32_t* map = (int32_t*)g.g1;
+    hipLaunchKernelGGL(k_tile_rehash, dim3(grid_for(c->tcap, 1, 8192)), dim3(64), 0, st, o, g, map);
+    hipLaunchKernelGGL(k_tile_remap, dim3(grid_for(c->tcap, 256, 1024)), dim3(256), 0, st, o, g,
+                       (const int32_t*)map);
+    // per-slot state of the old pool's slots: the same slot numbers
+    const int64_t mb = o.max_blocks;
+    struct { void* dst; const void* src; int64_t bytes; } cp[] = {
+        {g.bkey, o.bkey, mb * 8},       {g.occ, o.occ, mb * 64},
+        {g.g1, o.g1, mb * 1024},        {g.g2, o.g2, mb * 1024},
+        {g.s, o.s, mb * 1024},          {g.bmax, o.bmax, mb * 4},
+        {g.flags, o.flags, mb * 4},     {g.chg_add, o.chg_add, mb * 64},
+        {g.chg_rem, o.chg_rem, mb * 64}, {g.bmin1, o.bmin1, mb * 2},
+        {g.bmin2, o.bmin2, mb * 2},     {g.cnt, o.cnt, (int64_t)C_N * 4},
+    };
+    for (const auto& x : cp)
+        if (hipMemcpyAsync(x.dst, x.src, (size_t)x.bytes, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return EDT_ERR_HIP;
+    hipLaunchKernelGGL(k_grow_counts, dim3(1), dim3(1), 0, st, g, (int32_t)mb);
     LAUNCH_CHECK();
+    n.interior_valid = false;
     *c = n;                      // from here on the context lives in the new workspace
-    return rebuild_from_list(c, count, lxyz, lbits, mb_old, st);
+    return EDT_OK;
 }
 
 // The incremental transform over n change entries; n_dev, when given, holds

@@ -660,14 +660,29 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                 const uint32_t bj = b[M + j];
                 R = bj ? (uint32_t)(__ffs(bj) - 1) : R + 8u;
             }
+            // least g1 of each block: 0 on a row holding an obstacle, else set
+            // by the end voxels (voxel 0 is nearest the left obstacle, voxel 7
+            // the right one).  lc: distance from the voxel before block j to
+            // the nearest obstacle at or before it.  The squares (<= 64^2) are
+            // reduced over the wave two blocks at a time, packed.
+            uint32_t bmins[4];
+            {
+                uint32_t lc = L, nsq[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t bj = b[M + j];
+                    const uint32_t near = bj ? 0u : min(min(lc + 1u, rc[j] + 1u), dmax);
+                    nsq[j] = near * near;
+                    lc = bj ? (uint32_t)__clz(bj) - 24u : lc + 8u;
+                }
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    bmins[h] = wave_reduce_pk_u16<false>(nsq[2 * h] | (nsq[2 * h + 1] << 16));
+            }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const uint32_t bj = b[M + j];
-                // least g1 of the block: 0 on a row holding an obstacle, else
-                // set by the end voxels (voxel 0 is nearest the left obstacle,
-                // voxel 7 the right one)
-                const uint32_t near = bj ? 0u : min(min(L + 1u, rc[j] + 1u), dmax);
-                const int bmin = wave_min((int)(near * near));
+                const int bmin = (int)((bmins[j >> 1] >> (16 * (j & 1))) & 0xffffu);
                 uint32_t m[8], d[8];
 #pragma unroll
                 for (int x = 0; x < 8; ++x) m[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
@@ -775,8 +790,8 @@ __device__ inline void pass_x_body(const Grid& g, const int32_t* list, int list_
             dst[8 * x] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)(d * d)) : (uint16_t)(d * d);
             mn = min(mn, d);
         }
-        mn = wave_min(mn);
-        if (lane == 0) g.bmin1[slot] = (uint16_t)(mn * mn);
+        mn = (int)(wave_reduce_pk_u16<false>((uint32_t)(mn * mn)) & 0xffffu);
+        if (lane == 0) g.bmin1[slot] = (uint16_t)mn;
         __syncthreads();
     }
 }
@@ -2202,6 +2217,60 @@ __device__ inline void scan_chunk(const Grid& g, int64_t c0, int64_t n, int32_t*
 // pool; blocks that no longer hold an obstacle and lie beyond R blocks of
 // every obstacle block drop out.
 // ---------------------------------------------------------------------------
+// Pool growth (the context moves onto a larger workspace; the blocks and
+// their field are copied, nothing is recomputed).  Tile positions depend on
+// the hash capacity, so the tile tables are rebuilt: k_tile_rehash, one wave
+// per old table position, inserts the tile's key into the new hash, records
+// the new position in map[old position] (-1 for an empty position) and
+// copies the tile's slot table, obstacle mask and flag.
+__global__ void __launch_bounds__(64) k_tile_rehash(Grid o, Grid n, int32_t* map) {
+    const int lane = threadIdx.x;
+    for (int64_t p = blockIdx.x; p <= (int64_t)o.tmask; p += gridDim.x) {
+        const unsigned long long key = o.tkeys[p];
+        int32_t q = -1;
+        if (key != KEY_EMPTY && lane == 0) {
+            bool created;
+            q = hinsert(n.tkeys, n.tmask, key, &created);
+            if (q < 0) set_error(n, -3 /* EDT_ERR_CAPACITY */);
+        }
+        q = __shfl(q, 0);
+        if (lane == 0) map[p] = q;
+        if (q < 0) continue;
+        const int4* src = (const int4*)(o.tslots + p * 512);
+        int4* dst = (int4*)(n.tslots + (int64_t)q * 512);
+        dst[lane] = src[lane];
+        dst[lane + 64] = src[lane + 64];
+        if (lane < 16) n.tobst[(int64_t)q * 16 + lane] = o.tobst[p * 16 + lane];
+        if (lane == 0) n.tflag[q] = o.tflag[p];
+    }
+}
+
+// Second step of the growth: the tile list and the face-neighbour records
+// hold table positions; translate them through map.  Entries that do not
+// name a position of the old table (face records are only written for
+// d_max <= 64) become -1.
+__global__ void k_tile_remap(Grid o, Grid n, const int32_t* map) {
+    const int64_t nt = o.cnt[C_NTILE];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = o.tlist[i];
+        n.tlist[i] = (t >= 0 && t <= (int64_t)o.tmask) ? map[t] : -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t v = o.tinfo[i * 8 + k];
+            n.tinfo[i * 8 + k] = (v >= 0 && v <= (int64_t)o.tmask) ? map[v] : -1;
+        }
+    }
+}
+
+// Last step of the growth: a call that ran out of pool advanced the block
+// counter past the old capacity without writing those slots; only the slots
+// below it were claimed.  The pool abort flag no longer applies.
+__global__ void k_grow_counts(Grid n, int32_t old_max_blocks) {
+    if (n.cnt[C_NBLK] > old_max_blocks) n.cnt[C_NBLK] = old_max_blocks;
+    n.cnt[C_ABORT] = 0;
+}
+
 __global__ void __launch_bounds__(64) k_compact_gather(Grid g, int32_t* count, int32_t* xyz,
                                                        uint32_t* bits) {
     const int lane = threadIdx.x;

@@ -1,7 +1,8 @@
 """A block pool that grows (edt_grow; section IV-A: memory is allocated as
 the transformed region grows).  An update that does not fit the pool is
-cancelled with the map unchanged; after the pool grows, the same update
-gives the oracle's field, and a grown field keeps its map, field and
+cancelled with the map unchanged; after the pool grows (a copy of the pool
+into a larger workspace, tile index rehashed), the same update gives the
+oracle's field, and a grown field keeps its map, field, block count and
 nearest obstacles exactly."""
 import numpy as np
 import pytest
@@ -74,6 +75,10 @@ def test_updates_grow_the_pool_on_demand(dmax):
     g = Field((nx, ny, nz), dmax)
     g.global_(cu(occ))
     assert torch.equal(f.dense(), g.dense())
+    # a grown field runs the global transform like a fresh one
+    f.global_(cu(occ))
+    assert torch.equal(f.dense(), g.dense())
+    assert torch.equal(f.occupancy(), g.occupancy())
 
 
 def test_grow_keeps_map_field_and_nearest_obstacles():
@@ -89,10 +94,12 @@ def test_grow_keeps_map_field_and_nearest_obstacles():
     for (x, y, z), v in zip(xyz, st):
         occ[z, y, x] = v
     before = f.dense()
+    blocks = f.stats()["blocks"]
     f.grow(256)                                  # same capacity: a move, not a resize
     f.grow()                                     # capped at the extent's blocks
     assert f.error() == 0
     assert torch.equal(f.dense(), before)
+    assert f.stats()["blocks"] == blocks         # the pool is copied, not rebuilt
     ref = oracle.edt_separable(occ, 20)
     assert np.array_equal(before.cpu().numpy(), ref)
     q = all_voxels(nx, ny, nz)
