@@ -204,18 +204,18 @@ __device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     const int by0 = seg * a.lrun;
     const int len = min(a.lrun, m.nby - by0);
     const int out_lane = (lane & 7) * 8 + (lane >> 3);
-    uint16_t* dummy = (uint16_t*)(a.dummy + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 255) * 64);
     auto blk = [&](int b) -> uint4 { return *blk_ptr(a.g1, m, bx, b, bz, a.dblock, lane); };
+    // the block bases are uniform (scalar branch, scalar base, immediate row
+    // offsets)
     auto emit = [&](int ob, const u16x2* acc, bool has1) {
         const int64_t b0 = m.blk_off + ((int64_t)bz * m.nby + ob) * m.nbx + bx;
-        uint16_t* d0 = a.g2 + b0 * 512;
-        uint16_t* d1 = has1 ? a.g2 + (b0 + m.nbx) * 512 : dummy;
-        const int ol = has1 ? out_lane : lane;
+        uint16_t* d0 = a.g2 + b0 * 512 + out_lane;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const uint32_t v = as_u32(acc[o]);
-            d0[out_lane + 64 * o] = (uint16_t)(v & 0xffffu);
-            d1[(has1 ? 64 * o : 0) + ol] = (uint16_t)(v >> 16);
+        for (int o = 0; o < 8; ++o) d0[64 * o] = acc[o].x;
+        if (has1) {
+            uint16_t* d1 = a.g2 + (b0 + m.nbx) * 512 + out_lane;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) d1[64 * o] = acc[o].y;
         }
     };
     window_min<M, true, win_f16(M)>(by0, len, Dp, blk, emit);
@@ -245,19 +245,21 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
                             : (const uint4*)a.dblock + lane;
         return *p;
     };
-    int32_t* dummy = (int32_t*)(a.dummy + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 255) * 64);
-    int32_t* col = a.out + m.out_off + (int64_t)Y * m.nx + X;
+    // the strip's row at z = 0 (uniform base; lane l writes x = 8 bx0 + l)
+    int32_t* row0 = a.out + m.out_off + (int64_t)Y * m.nx + 8 * bx0;
     const int64_t zstride = (int64_t)m.nx * m.ny;
     auto emit = [&](int ob, const u16x2* acc, bool has1) {
+        if (!col_ok) return;
+        const int nz0 = min(8, m.nz - 8 * ob);                       // rows of block ob
+        const int nz1 = has1 ? min(8, m.nz - 8 * ob - 8) : 0;        // rows of block ob + 1
+        int32_t* p0 = row0 + (int64_t)(8 * ob) * zstride;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const uint32_t v = as_u32(acc[o]);
-            const int z0 = 8 * ob + o, z1 = 8 * ob + 8 + o;
-            int32_t* p0 = (col_ok && z0 < m.nz) ? col + z0 * zstride : dummy + lane;
-            int32_t* p1 = (col_ok && has1 && z1 < m.nz) ? col + z1 * zstride : dummy + lane;
-            *p0 = win_f16(M) ? f16_int(v & 0xffffu) : (int)(v & 0xffffu);
-            *p1 = win_f16(M) ? f16_int(v >> 16) : (int)(v >> 16);
-        }
+        for (int o = 0; o < 8; ++o)
+            if (o < nz0) p0[o * zstride + lane] = win_f16(M) ? f16_int(acc[o].x) : (int)acc[o].x;
+        int32_t* p1 = p0 + 8 * zstride;
+#pragma unroll
+        for (int o = 0; o < 8; ++o)
+            if (o < nz1) p1[o * zstride + lane] = win_f16(M) ? f16_int(acc[o].y) : (int)acc[o].y;
     };
     window_min<M, true, win_f16(M)>(bz0, len, Dp, blk, emit);
 }
