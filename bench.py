@@ -24,7 +24,8 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
                  returns): occupancy integration on the GPU plus the
                  incremental transform, p50 / p99 per scan;
   uncapped       the full transform without a radius (int32) of the tunnel
-                 map's dense extent, the paper's dataset setting;
+                 map's dense extent, the paper's dataset setting, and the
+                 same range scans applied to it incrementally;
   paper_alg1_cpu the paper's own Algorithm 1 on one CPU thread: a global
                  build of a tunnel-map corner (and its deviation from the
                  exact field) and range scans on the 64x64x32 map.
@@ -324,10 +325,11 @@ def bench_tunnel_x4(args, torch, np):
     }
 
 
-def bench_incremental(g, args, torch, np):
+def scan_lists(g, args, np):
+    """The change lists of the simulated range scans along the tunnels (and
+    the map after the last scan), generated once and cached."""
     import workloads
     from workloads.scans import ScanSim, tunnel_path
-    from paper_2105_04419_amd import Field
     cache = os.path.join(workloads.cache_dir(), f"scans_tunnel_s{args.seed}_{args.scans}.npz")
     if os.path.exists(cache):
         z = np.load(cache)
@@ -344,6 +346,12 @@ def bench_incremental(g, args, torch, np):
                  **{f"x{i}": x for i, (x, _) in enumerate(lists)},
                  **{f"s{i}": s for i, (_, s) in enumerate(lists)})
         os.replace(cache + ".tmp.npz", cache)
+    return lists, final
+
+
+def bench_incremental(g, args, torch, np):
+    from paper_2105_04419_amd import Field
+    lists, final = scan_lists(g, args, np)
     f = g["f"]
     f.global_blocks(g["xyz_d"], g["occ_d"])
     dev = [(torch.from_numpy(x).cuda(), torch.from_numpy(s).cuda()) for x, s in lists]
@@ -672,9 +680,38 @@ def bench_uncapped(g, args, torch, np):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / n
     vox = nx * ny * nz
-    return {"workload": f"tunnel map {nx}x{ny}x{nz}, dense input, no radius, int32 output",
-            "ms": round(ms, 4), "voxels_per_s": vox / (ms * 1e-3),
-            "max_squared_distance": int(out.max().item())}
+    res = {"workload": f"tunnel map {nx}x{ny}x{nz}, dense input, no radius, int32 output",
+           "ms": round(ms, 4), "voxels_per_s": vox / (ms * 1e-3),
+           "max_squared_distance": int(out.max().item())}
+    del ws, out
+    res["incremental"] = bench_uncapped_incremental(g, args, torch, np)
+    return res
+
+
+def bench_uncapped_incremental(g, args, torch, np):
+    """The range scans applied to the uncapped field of the whole extent
+    (edt_dense_ctx_update): p50 / p99 device latency per scan, and the field
+    after the last scan against the global transform of the final map."""
+    from paper_2105_04419_amd import DenseField, dense_global
+    lists, final = scan_lists(g, args, np)
+    nz, ny, nx = g["occ"].shape
+    f = DenseField((nx, ny, nz), 0, max_changes=max(1, max(len(x) for x, _ in lists)))
+    f.global_(torch.from_numpy(g["occ"]).cuda())
+    dev = [(torch.from_numpy(x).cuda(), torch.from_numpy(s).cuda()) for x, s in lists]
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for i, (x, s) in enumerate(dev):
+        e0.record()
+        f.update(x, s)
+        e1.record()
+        e1.synchronize()
+        if i >= args.scan_warmup:
+            ms.append(e0.elapsed_time(e1))
+    same = bool(torch.equal(f.field(), dense_global(torch.from_numpy(final).cuda())))
+    return {"scans": len(ms), "p50_ms": round(pct(ms, 50), 4), "p99_ms": round(pct(ms, 99), 4),
+            "incremental_equals_global": same, "error": f.error()}
 
 
 def main():

@@ -333,7 +333,7 @@ edt_status edt_batch_destroy(edt_batch* batch);
  * satisfy nx^2 + ny^2 + nz^2 < 2^31 (every squared distance fits in int32),
  * else EDT_ERR_ARG.  The caller's workspace (8-byte aligned,
  * edt_dense_workspace_bytes) holds the per-column parabola envelopes.
- * Global only: there is no incremental form of the uncapped transform. */
+ * The incremental form is the dense context below. */
 #define EDT_DENSE_INF 0x7fffffff
 int64_t edt_dense_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
 edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
@@ -355,6 +355,52 @@ edt_status edt_dense_global(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
 #define EDT_DENSE_STATIC_BYTES (64ll << 20)
 edt_status edt_dense_global_noalloc(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
                                     const uint8_t* d_occ, int32_t* d_out, void* stream);
+
+/* Dense context: the uncapped (or large-radius) field of a dense grid kept
+ * current under occupancy changes, the incremental counterpart of
+ * edt_dense_global (paper section IV-B, Algorithm 1's SetObstacle /
+ * RemoveObstacle followed by DistanceTransform, with d_max = infinity as in
+ * its section V-B runs).  The context holds the occupancy (uint8 per voxel),
+ * both int32 intermediates and the int32 field in the caller's workspace
+ * (256-byte aligned, edt_dense_ctx_bytes bytes; about 21 bytes per voxel);
+ * it is owned by the caller and must outlive the context.  d_max: 0 = no
+ * limit (voxels of a map without obstacles read EDT_DENSE_INF), else
+ * 1 ..  46340 (values clamped to d_max^2).  max_changes: the most entries
+ * one update may carry.  Extent: as edt_dense_global.  Errors: EDT_ERR_ARG
+ * for invalid sizes or pointers, EDT_ERR_CAPACITY for a short workspace.
+ * create enqueues the field of the empty map on `stream`. */
+typedef struct edt_dense_ctx edt_dense_ctx;
+int64_t edt_dense_ctx_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t max_changes);
+edt_status edt_dense_ctx_create(int32_t nx, int32_t ny, int32_t nz, int32_t d_max,
+                                int64_t max_changes, void* d_ws, int64_t ws_bytes, void* stream,
+                                edt_dense_ctx** out);
+edt_status edt_dense_ctx_destroy(edt_dense_ctx* ctx);
+
+/* Replaces the context's occupancy with d_occ (uint8[nz][ny][nx], nonzero =
+ * occupied; copied) and recomputes everything: edt_dense_global's result. */
+edt_status edt_dense_ctx_global(edt_dense_ctx* ctx, const uint8_t* d_occ, void* stream);
+
+/* Incremental transform: n entries (int32[n][3] voxel coordinates and
+ * uint8[n] absolute target states), same rules as edt_update (an entry equal
+ * to the current occupancy is a no-op; for a voxel listed several times the
+ * last entry wins; entries outside the extent make the call a no-op and set
+ * the device error word to EDT_ERR_RANGE; n > max_changes returns
+ * EDT_ERR_CAPACITY with nothing enqueued).  Rows holding a changed voxel are
+ * recomputed along x, then every column along y whose input changed, then
+ * every column along z whose input changed, each over its whole length, so
+ * afterwards the field equals edt_dense_global of the new occupancy bit for
+ * bit. */
+edt_status edt_dense_ctx_update(edt_dense_ctx* ctx, const int32_t* d_xyz,
+                                const uint8_t* d_state, int64_t n, void* stream);
+
+/* Device address of the field (int32[nz][ny][nx], inside the workspace):
+ * read it after the work enqueued before has completed; valid until the
+ * context is destroyed.  NULL for a NULL context. */
+const int32_t* edt_dense_ctx_field(const edt_dense_ctx* ctx);
+
+/* Device error word of the context (EDT_OK or the first error of the updates
+ * since the last read); reading clears it.  Waits for `stream`. */
+edt_status edt_dense_ctx_get_error(edt_dense_ctx* ctx, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Clearance cost on a dense field (paper section III, Eq. 2, clearance

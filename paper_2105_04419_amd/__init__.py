@@ -21,7 +21,7 @@ import torch
 
 __all__ = ["Field", "ClearanceCost", "clearance_cost", "clearance_fwd", "clearance_bwd", "lib",
            "EdtError", "LIB_PATH",
-           "Batch", "batch_global", "FUSED", "PER_MAP"]
+           "Batch", "batch_global", "FUSED", "PER_MAP", "DenseField", "dense_global"]
 
 LIB_PATH = os.environ.get("EDT_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                        "libedt.so")
@@ -114,6 +114,14 @@ def lib():
         "edt_dense_workspace_bytes": ([i32, i32, i32], i64),
         "edt_dense_global": ([i32, i32, i32, i32, vp, vp, vp, i64, vp], ctypes.c_int),
         "edt_dense_global_noalloc": ([i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
+        "edt_dense_ctx_bytes": ([i32, i32, i32, i64], i64),
+        "edt_dense_ctx_create": ([i32, i32, i32, i32, i64, vp, i64, vp, ctypes.POINTER(vp)],
+                                 ctypes.c_int),
+        "edt_dense_ctx_destroy": ([vp], ctypes.c_int),
+        "edt_dense_ctx_global": ([vp, vp, vp], ctypes.c_int),
+        "edt_dense_ctx_update": ([vp, vp, vp, i64, vp], ctypes.c_int),
+        "edt_dense_ctx_field": ([vp], vp),
+        "edt_dense_ctx_get_error": ([vp, vp], ctypes.c_int),
         "edt_clearance_fwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp], ctypes.c_int),
         "edt_clearance_bwd": ([vp, i32, i32, i32, f64, f32, vp, i64, i32, vp, vp, vp],
                               ctypes.c_int),
@@ -401,6 +409,72 @@ def dense_global(occ: torch.Tensor, d_max: int = 0, out: torch.Tensor | None = N
 
 
 DENSE_STATIC_BYTES = 64 << 20
+
+
+class DenseField:
+    """Uncapped (d_max = 0) or large-radius field of a dense grid kept
+    current under occupancy changes (edt_dense_ctx_*): global transform,
+    incremental updates, and the int32 field as a view of the workspace."""
+
+    def __init__(self, shape, d_max: int = 0, max_changes: int = 1 << 20, device=None,
+                 stream=None):
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self.d_max = int(d_max)
+        L = lib()
+        nbytes = int(L.edt_dense_ctx_bytes(nx, ny, nz, int(max_changes)))
+        if nbytes < 0:
+            raise EdtError("edt_dense_ctx_bytes", nbytes)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check("edt_dense_ctx_create", L.edt_dense_ctx_create(
+            nx, ny, nz, self.d_max, int(max_changes), _ptr(self.workspace), nbytes,
+            _stream(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        off = int(L.edt_dense_ctx_field(ctx)) - self.workspace.data_ptr()
+        n = nx * ny * nz
+        self._field = self.workspace[off:off + 4 * n].view(torch.int32).view(nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().edt_dense_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def global_(self, occ: torch.Tensor, stream=None):
+        nx, ny, nz = self.shape
+        occ = _dev_tensor(occ, torch.uint8, (nz, ny, nx))
+        _check("edt_dense_ctx_global", lib().edt_dense_ctx_global(self._ctx, _ptr(occ),
+                                                                   _stream(stream)))
+        self._keep = occ
+        return self
+
+    def update(self, xyz: torch.Tensor, state: torch.Tensor, stream=None):
+        """Set voxels xyz (int32 (n, 3)) to the absolute occupancy `state`
+        (uint8 (n,)); the last entry of a voxel wins."""
+        n = int(xyz.shape[0])
+        if n == 0:
+            return self
+        xyz = _dev_tensor(xyz, torch.int32, (n, 3))
+        state = _dev_tensor(state, torch.uint8, (n,))
+        _check("edt_dense_ctx_update", lib().edt_dense_ctx_update(
+            self._ctx, _ptr(xyz), _ptr(state), n, _stream(stream)))
+        self._keep = (xyz, state)
+        return self
+
+    def field(self) -> torch.Tensor:
+        """The int32 field (nz, ny, nx): a view of the workspace, current once
+        the work enqueued before has completed."""
+        return self._field
+
+    def error(self, stream=None) -> int:
+        return int(lib().edt_dense_ctx_get_error(self._ctx, _stream(stream)))
 
 
 def dense_global_noalloc(occ: torch.Tensor, d_max: int = 0, out: torch.Tensor | None = None,
