@@ -571,9 +571,10 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
     c->upd_gen = c->upd_gen >= 0x7ffffffe ? 1 : c->upd_gen + 1;
     const int32_t gen = c->upd_gen;
-    hipLaunchKernelGGL(k_upd_dedupe, dim3(tn), dim3(256), 0, st, g, d_xyz, n, n_dev, gen);
-    // every block the call needs exists before any occupancy changes
-    hipLaunchKernelGGL(k_upd_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
+    // dedupe, and every block the call needs exists before any occupancy
+    // changes
+    hipLaunchKernelGGL(k_upd_dedupe_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev,
+                       gen);
     hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g,
                        gen);
     hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);

@@ -1486,38 +1486,6 @@ __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int3
 // incremental update
 // ---------------------------------------------------------------------------
 
-// Range check (any entry outside the extent cancels the whole call) and
-// last-entry-wins dedupe through a voxel-keyed hash (value = max entry index).
-// Also zeroes the update's counters (no other workgroup of this kernel uses
-// them).  A cancelled update writes its number `gen` (never 0) into
-// C_UABORT; the update's last kernel clears it again.
-__global__ void k_upd_dedupe(Grid g, const int32_t* __restrict__ xyz, int64_t n0,
-                             const int32_t* n_dev, int32_t gen) {
-    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
-    if (blockIdx.x == 0 && threadIdx.x >= C_NYI && threadIdx.x < C_N) g.cnt[threadIdx.x] = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        g.upos[i] = -1;
-        if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz) {
-            set_error(g, -2);
-            g.cnt[C_UABORT] = gen;
-            continue;
-        }
-        const unsigned long long key = (unsigned long long)x +
-            (unsigned long long)g.nx * ((unsigned long long)y + (unsigned long long)g.ny * z);
-        bool created;
-        const int32_t h = hinsert(g.ukeys, g.umask, key, &created);
-        if (h < 0) {
-            set_error(g, -3);
-            g.cnt[C_UABORT] = gen;
-            continue;
-        }
-        g.upos[i] = h;
-        atomicMax(&g.uvals[h], (int32_t)i);
-    }
-}
-
 __device__ inline bool upd_winner(const Grid& g, int64_t i) {
     const int32_t h = g.upos[i];
     return h >= 0 && g.uvals[h] == (int32_t)i;
@@ -1554,26 +1522,57 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
     }
 }
 
-// New blocks for voxels that become occupied (initialised to background by
-// the claiming wave), and the list of blocks that gain their first obstacle:
-// their R-neighbourhood joins the pool in the next kernel, before any
-// occupancy changes, so that a full pool cancels the whole call and leaves
-// the map as it was.  A block created here has no obstacle yet; an existing
-// one without F_DILATED never had one.  A block may be listed twice (two
-// entries race on a fresh slot); growing its neighbourhood twice is harmless.
-__global__ void k_upd_alloc(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
-                            int32_t gen) {
-    if (g.cnt[C_UABORT] == gen) return;
+// First kernel of an update: range check (any entry outside the extent
+// cancels the whole call), last-entry-wins dedupe through a voxel-keyed hash
+// (value = max entry index), and the blocks the call needs.  Every entry that
+// sets a voxel gets its block (fresh slots hold background values), not only
+// the winning ones: a block made for an entry that loses to a later one is
+// harmless (background values are its field, and the region may be larger
+// than needed), and the allocation need not wait for the dedupe.  A block
+// that holds no obstacle yet and is not listed is listed for dilation (its
+// creator appends it; for an existing block the listing flag decides).  The
+// update's counters are zeroed here by the first workgroup, except the
+// dilation list's (zeroed by the previous call's fronts kernel), to which
+// every workgroup of this kernel appends.  A cancelled update writes its
+// number `gen` (never 0) into C_UABORT; the fronts kernel clears it again.
+__global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
+                                   const uint8_t* __restrict__ state, int64_t n0,
+                                   const int32_t* n_dev, int32_t gen) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    if (blockIdx.x == 0 && threadIdx.x >= C_NYI && threadIdx.x < C_N &&
+        threadIdx.x != C_NNEWDIL)
+        g.cnt[threadIdx.x] = 0;
     const int lane = __lane_id();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        bool want = false;
+        int bx = 0, by = 0, bz = 0;
+        if (i < n) {
+            const int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+            g.upos[i] = -1;
+            if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz) {
+                set_error(g, -2);
+                g.cnt[C_UABORT] = gen;
+            } else {
+                const unsigned long long key = (unsigned long long)x +
+                    (unsigned long long)g.nx * ((unsigned long long)y + (unsigned long long)g.ny * z);
+                bool created;
+                const int32_t h = hinsert(g.ukeys, g.umask, key, &created);
+                if (h < 0) {
+                    set_error(g, -3);
+                    g.cnt[C_UABORT] = gen;
+                } else {
+                    g.upos[i] = h;
+                    atomicMax(&g.uvals[h], (int32_t)i);
+                    want = state[i] != 0;
+                    bx = x >> 3; by = y >> 3; bz = z >> 3;
+                }
+            }
+        }
         bool created = false;
         int64_t e = -1;
         unsigned long long key = 0;
-        if (i < n && state[i] && upd_winner(g, i)) {
-            const int bx = xyz[3 * i] >> 3, by = xyz[3 * i + 1] >> 3, bz = xyz[3 * i + 2] >> 3;
+        if (want) {
             key = pack_key(bx, by, bz);
             e = insert_block(g, bx, by, bz, &created);
             if (e < 0) {
@@ -1756,7 +1755,8 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
 //   xs:    blocks within R along x of a seed (their g1 can change)
 //   ys:    blocks within R in x and y of a seed (their g2 can change)
 // The seed's change masks are emptied for the next call once read, and the
-// call's cancel flag is cleared (no later kernel of the update tests it).
+// call's cancel flag and dilation-list count are cleared (no later kernel of
+// the update reads them; the next call's first kernel appends to that list).
 __global__ void __launch_bounds__(1024) k_upd_fronts(Grid g) {
     __shared__ int32_t rec[32];     // boxes, block coordinates, 27 tile positions
     __shared__ int wcnt[16][5];     // per wave: dirty, ys, xs, raise, lower
@@ -1764,7 +1764,10 @@ __global__ void __launch_bounds__(1024) k_upd_fronts(Grid g) {
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t ns = g.cnt[C_NSEED];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_UABORT] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.cnt[C_UABORT] = 0;
+        g.cnt[C_NNEWDIL] = 0;
+    }
     for (int64_t si = blockIdx.x; si < ns; si += gridDim.x) {
         if (wid == 0) {
             const int32_t seed = g.list_seed[si];
