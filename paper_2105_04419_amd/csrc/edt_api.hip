@@ -226,7 +226,15 @@ edt_status dilate_region(edt_ctx* c, hipStream_t st) {
     const int TR = (g.R + 7) / 8, w = 2 * TR + 1;
     const int E = 8 + 2 * g.R;
     const size_t lds = (size_t)w * w * w * 64 + E * E + E * 8 + 64;
-    hipLaunchKernelGGL(k_tile_dilate, dim3(grid_for(c->tcap, 1, 4096)), dim3(64), lds, st, g);
+    const dim3 grid(grid_for(c->tcap, 1, 4096));
+    switch (g.R) {
+#define EDT_DIL_CASE(r) \
+    case r: hipLaunchKernelGGL(k_tile_dilate<r>, grid, dim3(64), lds, st, g); break;
+        EDT_DIL_CASE(1) EDT_DIL_CASE(2) EDT_DIL_CASE(3) EDT_DIL_CASE(4)
+        EDT_DIL_CASE(5) EDT_DIL_CASE(6) EDT_DIL_CASE(7) EDT_DIL_CASE(8)
+#undef EDT_DIL_CASE
+        default: hipLaunchKernelGGL(k_tile_dilate<0>, grid, dim3(64), lds, st, g); break;
+    }
     LAUNCH_CHECK();
     return EDT_OK;
 }

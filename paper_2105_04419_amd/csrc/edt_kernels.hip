@@ -343,10 +343,14 @@ __global__ void __launch_bounds__(64) k_ingest_blocks_write(Grid g, const int32_
 // ---------------------------------------------------------------------------
 // One workgroup per tile: OR the obstacle masks of the tile neighbourhood
 // shifted by -R..R along x, then y, then z (separable Chebyshev dilation on
-// bit rows in LDS) and create the missing blocks of the dilated mask.
+// bit rows in LDS) and create the missing blocks of the dilated mask.  RT:
+// the block radius R as a constant (1 .. 8, one tile of neighbourhood, loops
+// unrolled), or 0 for any R read from the grid.
+template <int RT>
 __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
     extern __shared__ uint32_t sm[];
-    const int R = g.R, TR = (R + 7) >> 3, w = 2 * TR + 1, NN = w * w * w;
+    const int R = RT > 0 ? RT : g.R, TR = RT > 0 ? 1 : (R + 7) >> 3, w = 2 * TR + 1,
+              NN = w * w * w;
     const int E = 8 + 2 * R;                 // rows of the dilation window per axis
     uint32_t* nmask = sm;                    // [NN][16] neighbour obstacle masks
     uint8_t* s1 = (uint8_t*)(sm + NN * 16);  // [E][E]  x-dilated rows (y', z')
@@ -383,6 +387,22 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
             // position X + 8 TR for X = -8 TR .. 8 + 8 TR - 1 (<= 72 bits)
             const int ny = ((Y >> 3) + TR), nz = ((Z >> 3) + TR);
             const int byte = (Y & 7) + 8 * (Z & 7);
+            if (RT > 0) {
+                // the row over the three tiles in 24 bits (bit 8 + X for
+                // X = -8 .. 15); bit x of the result ORs bits 8 + x - R ..
+                // 8 + x + R
+                uint32_t row = 0u;
+#pragma unroll
+                for (int tx2 = 0; tx2 < 3; ++tx2) {
+                    const int n = tx2 + 3 * (ny + 3 * nz);
+                    row |= ((nmask[n * 16 + (byte >> 2)] >> (8 * (byte & 3))) & 0xffu) << (8 * tx2);
+                }
+                uint32_t d = 0u;
+#pragma unroll
+                for (int sh = 8 - RT; sh <= 8 + RT; ++sh) d |= row >> sh;
+                s1[r] = (uint8_t)d;
+                continue;
+            }
             unsigned long long lo = 0ull, hi = 0ull;
             for (int tx2 = 0; tx2 < w; ++tx2) {
                 const int n = tx2 + w * (ny + w * nz);
@@ -412,14 +432,22 @@ __global__ void __launch_bounds__(64) k_tile_dilate(Grid g) {
         for (int r = lane; r < E * 8; r += 64) {            // y dilation
             const int y = r & 7, zp = r >> 3;
             uint32_t d = 0u;
-            for (int dy = -R; dy <= R; ++dy) d |= s1[(y + dy + R) + E * zp];
+#pragma unroll
+            for (int dy = 0; dy <= 2 * (RT > 0 ? RT : 8); ++dy)
+                if (RT > 0 || dy <= 2 * R) d |= s1[(y + dy) + E * zp];
+            if (RT == 0)
+                for (int dy = 17; dy <= 2 * R; ++dy) d |= s1[(y + dy) + E * zp];
             s2[r] = (uint8_t)d;
         }
         __syncthreads();
         {                                                   // z dilation, lane = y + 8z
             const int y = lane & 7, z = lane >> 3;
             uint32_t d = 0u;
-            for (int dz = -R; dz <= R; ++dz) d |= s2[y + 8 * (z + dz + R)];
+#pragma unroll
+            for (int dz = 0; dz <= 2 * (RT > 0 ? RT : 8); ++dz)
+                if (RT > 0 || dz <= 2 * R) d |= s2[y + 8 * (z + dz)];
+            if (RT == 0)
+                for (int dz = 17; dz <= 2 * R; ++dz) d |= s2[y + 8 * (z + dz)];
             dil[lane] = (uint8_t)d;
         }
         __syncthreads();
