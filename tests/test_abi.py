@@ -72,6 +72,29 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu(L):
     assert L.edt_clearance_fwd(None, 4, 4, 4, 0.2, 1.0, None, 1, 1, None, None) == -1
 
 
+def test_dense_context_validates_without_touching_the_gpu(L):
+    # workspace sizes: about 21 bytes per voxel plus the marks and the dedupe
+    # table; invalid extents, change capacities and arguments are refused
+    n = L.edt_dense_ctx_bytes(64, 32, 16, 100)
+    assert n >= 21 * 64 * 32 * 16
+    assert L.edt_dense_ctx_bytes(64, 32, 16, 1000) > n
+    assert L.edt_dense_ctx_bytes(0, 32, 16, 100) == -1
+    assert L.edt_dense_ctx_bytes(46341, 1, 1, 100) == -1
+    assert L.edt_dense_ctx_bytes(8, 8, 8, 0) == -1
+    out = ctypes.c_void_p()
+    assert L.edt_dense_ctx_create(8, 8, 8, 0, 16, None, 1 << 20, None, ctypes.byref(out)) == -1
+    assert L.edt_dense_ctx_create(8, 8, 8, -1, 16, ctypes.c_void_p(256), 1 << 20, None,
+                                  ctypes.byref(out)) == -1
+    assert L.edt_dense_ctx_create(8, 8, 8, 0, 16, ctypes.c_void_p(257), 1 << 20, None,
+                                  ctypes.byref(out)) == -1
+    assert L.edt_dense_ctx_create(8, 8, 8, 0, 16, ctypes.c_void_p(256), 64, None,
+                                  ctypes.byref(out)) == -3
+    assert L.edt_dense_ctx_update(None, None, None, 1, None) == -1
+    assert L.edt_dense_ctx_global(None, None, None) == -1
+    assert L.edt_dense_ctx_field(None) is None
+    assert L.edt_dense_ctx_get_error(None, None) == -1
+
+
 def test_product_package_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_2105_04419_amd")
     for dirpath, _, files in os.walk(pkg):
