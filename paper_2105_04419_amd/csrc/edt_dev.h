@@ -18,6 +18,9 @@
 //   g2     uint16 per voxel, layout (x + 8y) * 8 + z: min over dy of
 //          g1(x, y+dy, z) + dy^2, clamped to D (contiguous z-columns).
 //   s      uint16 per voxel, layout x + 8y + 64z: the field, min(D, |x-y|^2).
+//          g1, g2 and s hold integers, or for radii whose windowed minimum
+//          runs in binary16 (d_max <= 40) the binary16 bit patterns of the
+//          same integers.
 //   bmax   int32: max of s over the block (pruning bound for updates).
 //   flags  uint32: state bits (F_*).
 // Blocks exist exactly where s can differ from D: blocks that held an

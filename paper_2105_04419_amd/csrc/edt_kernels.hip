@@ -1137,6 +1137,17 @@ __global__ void __launch_bounds__(64) k_pass_z(Grid g, const int32_t* items, int
 // ---------------------------------------------------------------------------
 // windowed minimum along y or z for d_max <= 64 (core in edt_win.h)
 // ---------------------------------------------------------------------------
+// The stored field s holds integers (uint16), or for radii whose window runs
+// in binary16 (win_f16) the binary16 bit patterns of those integers, as the
+// window computes them; readers take the integer with s_int / s_pair_int.
+__device__ inline int s_int(const Grid& g, uint32_t bits) {
+    return win_f16(g.R) ? f16_int(bits) : (int)bits;
+}
+__device__ inline uint32_t s_pair_int(const Grid& g, uint32_t w) {
+    return win_f16(g.R) ? ((uint32_t)f16_int(w & 0xffffu) | ((uint32_t)f16_int(w >> 16) << 16))
+                        : w;
+}
+
 // Stores the results of one step of the windowed minimum: acc[o] holds output
 // row o of two consecutive blocks (low half: slot0, high half: slot1; a
 // negative slot has no storage and its half is dropped).  Pass Y writes g2
@@ -1172,15 +1183,13 @@ __device__ inline void win_store(const Grid& g, int32_t slot0, int32_t slot1, co
         if (slot0 >= 0) {
             uint16_t* d0 = g.s + (int64_t)slot0 * 512 + lane;
 #pragma unroll
-            for (int o = 0; o < 8; ++o)
-                d0[64 * o] = F16 ? (uint16_t)f16_int(acc[o].x) : acc[o].x;
+            for (int o = 0; o < 8; ++o) d0[64 * o] = acc[o].x;
             if (lane == 0) g.bmax[slot0] = F16 ? f16_int(m & 0xffffu) : (int)(m & 0xffffu);
         }
         if (slot1 >= 0) {
             uint16_t* d1 = g.s + (int64_t)slot1 * 512 + lane;
 #pragma unroll
-            for (int o = 0; o < 8; ++o)
-                d1[64 * o] = F16 ? (uint16_t)f16_int(acc[o].y) : acc[o].y;
+            for (int o = 0; o < 8; ++o) d1[64 * o] = acc[o].y;
             if (lane == 0) g.bmax[slot1] = F16 ? f16_int(m >> 16) : (int)(m >> 16);
         }
     }
@@ -1257,7 +1266,6 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
     const int64_t ncol = (int64_t)g.cnt[C_NTILE] * 64;
     const uint16_t* src = AXIS == 1 ? g.g1 : g.g2;
     constexpr bool F16 = win_f16(M);
-    const uint32_t Dp = (uint32_t)g.D | ((uint32_t)g.D << 16);       // integer D (field s)
     const uint32_t Dw = F16 ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
     const uint32_t Dpw = Dw | (Dw << 16);     // D in the window's representation
     for (int64_t it = blockIdx.x; it < ncol; it += gridDim.x) {
@@ -1298,7 +1306,7 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                     if (AXIS == 1) {
                         if (lane == 0) g.bmin2[slot] = (uint16_t)g.D;
                     } else {
-                        ((uint4*)(g.s + (int64_t)slot * 512))[lane] = make_uint4(Dp, Dp, Dp, Dp);
+                        ((uint4*)(g.s + (int64_t)slot * 512))[lane] = make_uint4(Dpw, Dpw, Dpw, Dpw);
                         if (lane == 0) g.bmax[slot] = g.D;
                     }
                 }
@@ -1361,6 +1369,8 @@ __global__ void __launch_bounds__(256) k_read_strip(Grid g, void* __restrict__ o
         if (KIND != RB_FIELD) bits[bb * 64 + lane] = ob;
         if (KIND == RB_OCC) continue;
         uint4 v = ((const uint4*)(g.s + (int64_t)slot * 512))[lane];
+        v = make_uint4(s_pair_int(g, v.x), s_pair_int(g, v.y), s_pair_int(g, v.z),
+                       s_pair_int(g, v.w));
         if (KIND == RB_SIGNED && __any(ob != 0u)) {
             // occupied voxels take their interior value (D without storage)
             const int32_t ii = g.iidx[slot];
@@ -1458,7 +1468,8 @@ __global__ void k_query_nearest(Grid g, const int32_t* __restrict__ xyz, int64_t
         int ox = -1, oy = -1, oz = -1;
         if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz) {
             const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
-            const int sv = slot < 0 ? g.D : g.s[(int64_t)slot * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+            const int sv = slot < 0 ? g.D
+                                    : s_int(g, g.s[(int64_t)slot * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)]);
             if (sv < g.D) {
                 // z offset
                 int kz = 0, t2 = -1;
@@ -1504,7 +1515,7 @@ __global__ void k_query(Grid g, const int32_t* __restrict__ xyz, int64_t n, int3
         int32_t v = g.D;
         if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz) {
             const int32_t slot = find_block(g, x >> 3, y >> 3, z >> 3);
-            if (slot >= 0) v = g.s[(int64_t)slot * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+            if (slot >= 0) v = s_int(g, g.s[(int64_t)slot * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)]);
         }
         out[i] = v;
     }
@@ -1525,9 +1536,7 @@ __device__ inline bool upd_winner(const Grid& g, int64_t i) {
 __device__ inline void init_slots(const Grid& g, int32_t slot) {
     unsigned long long m = __ballot(slot >= 0);
     const int lane = __lane_id();
-    const uint32_t d2 = (uint32_t)g.D | ((uint32_t)g.D << 16);
-    const uint4 dd = make_uint4(d2, d2, d2, d2);
-    // g1 and g2 hold D in their own representation (binary16 for small radii)
+    // g1, g2 and s hold D in their own representation (binary16 for small radii)
     const uint32_t dw = win_f16(g.R) ? f16_bits((uint32_t)g.D) : (uint32_t)g.D;
     const uint4 dg = make_uint4(dw | (dw << 16), dw | (dw << 16), dw | (dw << 16), dw | (dw << 16));
     while (m) {
@@ -1541,7 +1550,7 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
         }
         ((uint4*)(g.g1 + s * 512))[lane] = dg;
         ((uint4*)(g.g2 + s * 512))[lane] = dg;
-        ((uint4*)(g.s + s * 512))[lane] = dd;
+        ((uint4*)(g.s + s * 512))[lane] = dg;    // s holds D like g1, g2
         if (lane == 0) {
             g.bmax[s] = g.D;
             g.bmin1[s] = (uint16_t)g.D;
@@ -2534,7 +2543,7 @@ __device__ inline int32_t signed_at(const Grid& g, int x, int y, int z) {
         const int32_t ii = g.iidx[slot];
         return -(ii >= 0 ? (int32_t)g.ic1[(int64_t)ii * 512 + v] : g.D);
     }
-    return g.s[(int64_t)slot * 512 + v];
+    return s_int(g, g.s[(int64_t)slot * 512 + v]);
 }
 
 __global__ void k_query_signed(Grid g, const int32_t* __restrict__ xyz, int64_t n,
