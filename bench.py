@@ -531,8 +531,9 @@ def bench_readback(g, args, torch, np):
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = {"ms": round(ms, 4), "algorithmic_bytes": nbytes, "GB_per_s": round(gbs, 1),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    res["field_equals_oracle"] = g.get("parity_ref") is not None and bool(
-        np.array_equal(out.cpu().numpy(), g["parity_ref"]))
+    # None when the CPU oracle did not run (--no-cpu)
+    res["field_equals_oracle"] = (None if g.get("parity_ref") is None else
+                                  bool(np.array_equal(out.cpu().numpy(), g["parity_ref"])))
     return res
 
 
