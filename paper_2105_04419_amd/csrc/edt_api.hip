@@ -583,14 +583,15 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     // changes
     hipLaunchKernelGGL(k_upd_dedupe_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev,
                        gen);
-    hipLaunchKernelGGL(k_upd_dilate, dim3(grid_for((int64_t)n * w3, 256, 4096)), dim3(256), 0, st, g,
-                       gen);
-    hipLaunchKernelGGL(k_upd_apply, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev, gen);
+    // occupancy changes and the dilation of the listed blocks in one launch
+    const int td = grid_for((int64_t)n * w3, 256, 4096);
+    hipLaunchKernelGGL(k_upd_apply_dilate, dim3(tn + td), dim3(256), 0, st, g, d_xyz, d_state, n,
+                       n_dev, gen, tn);
     // fronts: one workgroup per seed block (at most one per change entry),
     // wide enough for the seed's whole neighbourhood when it has at most 1024
     // blocks
     const int fwg = w3 <= 256 ? 256 : (w3 <= 512 ? 512 : 1024);
-    hipLaunchKernelGGL(k_upd_fronts, dim3(grid_for(n, 1, 4096)), dim3(fwg), 0, st, g);
+    hipLaunchKernelGGL(k_upd_fronts, dim3(grid_for(n, 1, 4096)), dim3(fwg), 0, st, g, gen);
     // short work items: the recompute sets are small, and short runs give
     // more waves to hide each item's latency
     Grid gu = g;

@@ -46,11 +46,12 @@ enum : uint32_t {
     F_RAISE = 32u,   // marked by the raise front
     F_LOWER = 64u,   // marked by the lower front
     F_NEWDIL = 128u, // gains its first obstacle in the current update (listed for dilation)
+    F_DILNEW = 256u, // F_DILATED set by the current update (undone if the call is cancelled)
 };
 
 // device counters (int32 slots of the counter array).  C_ABORT: the global
-// transform ran out of pool; C_UABORT: nonzero (the call's number) while
-// the running update is cancelled, cleared by its last kernel.
+// transform ran out of pool; C_UABORT: the number of the last cancelled
+// update (calls are numbered from 1, so a stale value never matches).
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_UABORT,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,

@@ -959,7 +959,8 @@ __device__ inline void resolve_run(const Grid& g, int32_t* sl, uint8_t* mem, int
 __device__ inline void finish_run(const Grid& g, const int32_t* sl, int len, int axis,
                                   uint32_t runflag) {
     if (runflag == 0u) return;                  // global transform: no marks
-    const uint32_t clear = axis == 1 ? (F_YS | F_XS | F_SEED) : (F_DIRTY | F_RAISE | F_LOWER);
+    const uint32_t clear =
+        axis == 1 ? (F_YS | F_XS | F_SEED | F_DILNEW) : (F_DIRTY | F_RAISE | F_LOWER);
     const int lane = threadIdx.x;
     if (lane < len) atomicAnd(&g.flags[sl[g.R + lane]], ~clear);
 }
@@ -1571,7 +1572,7 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
 // update's counters are zeroed here by the first workgroup, except the
 // dilation list's (zeroed by the previous call's fronts kernel), to which
 // every workgroup of this kernel appends.  A cancelled update writes its
-// number `gen` (never 0) into C_UABORT; the fronts kernel clears it again.
+// number `gen` (never 0) into C_UABORT; later kernels compare with their own.
 __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
                                    const uint8_t* __restrict__ state, int64_t n0,
                                    const int32_t* n_dev, int32_t gen) {
@@ -1640,23 +1641,21 @@ __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
 // per block (the wave centres) and list the blocks that hold them.  The
 // voxel-keyed dedupe table is emptied here for the next call: each winner
 // clears its entry once it has read it (the entries that lose to it only
-// ever compare the stored index with their own), and a cancelled call clears
-// the entry of every input.
-__global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
-                            const uint8_t* __restrict__ state, int64_t n0, const int32_t* n_dev,
-                            int32_t gen) {
-    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+// ever compare the stored index with their own), and a call cancelled before
+// this kernel clears the entry of every input.  Workgroups vb of vgrid.
+__device__ inline void upd_apply_body(const Grid& g, const int32_t* __restrict__ xyz,
+                                      const uint8_t* __restrict__ state, int64_t n,
+                                      int32_t gen, int64_t vb, int64_t vgrid) {
+    const int64_t t0 = vb * blockDim.x + threadIdx.x, stride = vgrid * blockDim.x;
     {
-        // the blocks listed for dilation have been dilated (or the call is
-        // cancelled): their listing mark goes
+        // the blocks listed for dilation are being dilated by the other
+        // workgroups of this launch (or the call is cancelled): their
+        // listing mark goes
         const int64_t nd = g.cnt[C_NNEWDIL];
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nd;
-             i += (int64_t)gridDim.x * blockDim.x)
-            atomicAnd(&g.flags[g.list_newdil[i]], ~F_NEWDIL);
+        for (int64_t i = t0; i < nd; i += stride) atomicAnd(&g.flags[g.list_newdil[i]], ~F_NEWDIL);
     }
     if (g.cnt[C_UABORT] == gen) {
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t i = t0; i < n; i += stride) {
             const int32_t h = g.upos[i];
             if (h >= 0) {
                 g.ukeys[h] = KEY_EMPTY;
@@ -1665,11 +1664,10 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
         }
         return;
     }
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = t0; i - __lane_id() < n; i += stride) {
         bool add = false, rem = false, first_seed = false, new_dil = false;
         int32_t slot = -1;
-        if (upd_winner(g, i)) {
+        if (i < n && upd_winner(g, i)) {
             const int32_t h = g.upos[i];
             g.ukeys[h] = KEY_EMPTY;
             g.uvals[h] = -1;
@@ -1689,6 +1687,7 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
                         const uint32_t o = atomicOr(&g.flags[slot], F_DILATED | F_SEED);
                         new_dil = !(o & F_DILATED);
                         first_seed = !(o & F_SEED);
+                        if (new_dil) atomicOr(&g.flags[slot], F_DILNEW);
                     } else {
                         atomicAnd(&g.occ[w], ~bit);
                         atomicOr(&g.chg_rem[w], bit);
@@ -1710,15 +1709,14 @@ __global__ void k_upd_apply(Grid g, const int32_t* __restrict__ xyz,
     }
 }
 
-// Blocks that gain their first obstacle bring their R-neighbourhood in
-// (before the occupancy changes; a full pool cancels the call).
-__global__ void k_upd_dilate(Grid g, int32_t gen) {
+// Blocks that gain their first obstacle bring their R-neighbourhood in, one
+// thread per neighbour.  Workgroups vb of vgrid.
+__device__ inline void upd_dilate_body(const Grid& g, int32_t gen, int64_t vb, int64_t vgrid) {
     if (g.cnt[C_UABORT] == gen) return;
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NNEWDIL] * w3;
     const int lane = __lane_id();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i - lane < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = vb * blockDim.x + threadIdx.x; i - lane < total; i += vgrid * blockDim.x) {
         bool created = false;
         int64_t e = -1;
         unsigned long long key = 0;
@@ -1743,6 +1741,22 @@ __global__ void k_upd_dilate(Grid g, int32_t gen) {
         if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
         init_slots(g, sl);
     }
+}
+
+// The occupancy changes and the dilation of the listed blocks share a
+// launch: the first napply workgroups apply the entries, the others dilate.
+// The two never touch the same block (dilation only creates absent blocks;
+// every block an entry changes exists since the first kernel), so they need
+// no order.  A full pool found by the dilation cancels the call after the
+// bits may have changed: the fronts kernel then restores them from the
+// change masks (and undoes the call's F_DILATED marks), so a cancelled call
+// still leaves the map as it was.
+__global__ void k_upd_apply_dilate(Grid g, const int32_t* __restrict__ xyz,
+                                   const uint8_t* __restrict__ state, int64_t n0,
+                                   const int32_t* n_dev, int32_t gen, int napply) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n0;
+    if ((int)blockIdx.x < napply) upd_apply_body(g, xyz, state, n, gen, blockIdx.x, napply);
+    else upd_dilate_body(g, gen, (int64_t)blockIdx.x - napply, (int64_t)gridDim.x - napply);
 }
 
 // Bounding boxes (block-local) of the added and removed voxels of each seed.
@@ -1792,20 +1806,41 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
 //   xs:    blocks within R along x of a seed (their g1 can change)
 //   ys:    blocks within R in x and y of a seed (their g2 can change)
 // The seed's change masks are emptied for the next call once read, and the
-// call's cancel flag and dilation-list count are cleared (no later kernel of
-// the update reads them; the next call's first kernel appends to that list).
-__global__ void __launch_bounds__(1024) k_upd_fronts(Grid g) {
+// dilation-list count is cleared (no later kernel of the update reads it;
+// the next call's first kernel appends to that list).  In a call cancelled
+// after the occupancy changed (the pool filled during the dilation) the
+// workgroup instead restores the seed's bits from its change masks, drops
+// its marks and the F_DILATED it gained, and builds no fronts.
+__global__ void __launch_bounds__(1024) k_upd_fronts(Grid g, int32_t gen) {
     __shared__ int32_t rec[32];     // boxes, block coordinates, 27 tile positions
     __shared__ int wcnt[16][5];     // per wave: dirty, ys, xs, raise, lower
     __shared__ int bbase[3];        // the workgroup's list positions
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t ns = g.cnt[C_NSEED];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        g.cnt[C_UABORT] = 0;
-        g.cnt[C_NNEWDIL] = 0;
-    }
+    const bool cancel = g.cnt[C_UABORT] == gen;
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_NNEWDIL] = 0;
     for (int64_t si = blockIdx.x; si < ns; si += gridDim.x) {
+        if (cancel) {
+            if (wid == 0) {
+                const int32_t seed = g.list_seed[si];
+                if (lane < 16) {
+                    const int64_t w = (int64_t)seed * 16 + lane;
+                    const uint32_t a = g.chg_add[w], r = g.chg_rem[w];
+                    g.occ[w] = (g.occ[w] & ~a) | r;
+                    g.chg_add[w] = 0u;
+                    g.chg_rem[w] = 0u;
+                }
+                if (lane == 0) {
+                    const uint32_t f = atomicAnd(&g.flags[seed], ~(F_SEED | F_DILNEW));
+                    if (f & F_DILNEW) {
+                        atomicAnd(&g.flags[seed], ~F_DILATED);
+                        atomicSub(&g.cnt[C_NDIL], 1);
+                    }
+                }
+            }
+            continue;
+        }
         if (wid == 0) {
             const int32_t seed = g.list_seed[si];
             const uint32_t a = ((const uint8_t*)g.chg_add)[(int64_t)seed * 64 + lane];
