@@ -32,7 +32,6 @@ struct edt_ctx {
     int64_t ucap;       // update hash capacity
     int64_t stats_host[C_N];
     bool interior_valid;   // edt_interior ran after the last global / update
-    int32_t upd_gen;       // number of the current update call (1 .. 2^31 - 1)
     int32_t* scan_xyz;     // change list built by edt_integrate_scan
     uint8_t* scan_state;
     int32_t* scan_cnt;     // [0] free entries, [1] hit entries, [2] list length,
@@ -577,21 +576,18 @@ static edt_status run_update(edt_ctx* c, const int32_t* d_xyz, const uint8_t* d_
     // n, so its grids stay moderate
     const int tn = grid_for(n_dev && n > 65536 ? 65536 : n, 256, 4096);
     const int w3 = (2 * g.R + 1) * (2 * g.R + 1) * (2 * g.R + 1);
-    c->upd_gen = c->upd_gen >= 0x7ffffffe ? 1 : c->upd_gen + 1;
-    const int32_t gen = c->upd_gen;
     // dedupe, and every block the call needs exists before any occupancy
     // changes
-    hipLaunchKernelGGL(k_upd_dedupe_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev,
-                       gen);
+    hipLaunchKernelGGL(k_upd_dedupe_alloc, dim3(tn), dim3(256), 0, st, g, d_xyz, d_state, n, n_dev);
     // occupancy changes and the dilation of the listed blocks in one launch
     const int td = grid_for((int64_t)n * w3, 256, 4096);
     hipLaunchKernelGGL(k_upd_apply_dilate, dim3(tn + td), dim3(256), 0, st, g, d_xyz, d_state, n,
-                       n_dev, gen, tn);
+                       n_dev, tn);
     // fronts: one workgroup per seed block (at most one per change entry),
     // wide enough for the seed's whole neighbourhood when it has at most 1024
     // blocks
     const int fwg = w3 <= 256 ? 256 : (w3 <= 512 ? 512 : 1024);
-    hipLaunchKernelGGL(k_upd_fronts, dim3(grid_for(n, 1, 4096)), dim3(fwg), 0, st, g, gen);
+    hipLaunchKernelGGL(k_upd_fronts, dim3(grid_for(n, 1, 4096)), dim3(fwg), 0, st, g);
     // short work items: the recompute sets are small, and short runs give
     // more waves to hide each item's latency
     Grid gu = g;

@@ -77,7 +77,8 @@ __device__ inline uint32_t chunk_bits(const uint8_t* row, int x0, int nx, int la
 }
 
 // Marks of an incremental update (dense context).  cnt: [0] error word,
-// [1] number of the cancelled call, [2] rows listed, [3] y groups listed,
+// [1] the current call is cancelled (set by the dedupe, read by the apply
+// kernel, cleared by the pass-x kernel), [2] rows listed, [3] y groups listed,
 // [4] z groups listed.  A y group is (x / 64, z), a z group (x / 64, y); one
 // wave recomputes the group's 64 columns.
 struct DenseMarks {
@@ -108,6 +109,7 @@ __global__ void __launch_bounds__(64) k_dense_x(int nx, int ny, int nz,
     constexpr int64_t FAR = 1ll << 40;
     const int lane = threadIdx.x;
     const int nxc = (nx + 63) / 64;
+    if (INC && blockIdx.x == 0 && lane == 0) mk.cnt[DC_CANCEL] = 0;   // its last reader is done
     const int64_t rows = INC ? (int64_t)mk.cnt[DC_NROW] : (int64_t)ny * nz;
     for (int64_t ri = blockIdx.x; ri < rows; ri += gridDim.x) {
         const int64_t r = INC ? (int64_t)mk.rows[ri] : ri;
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, const 
 // update.  ukeys / uvals: open-addressing table of capacity umask + 1.
 __global__ void k_dn_dedupe(int nx, int ny, int nz, const int32_t* __restrict__ xyz, int64_t n,
                             unsigned long long* ukeys, int32_t* uvals, uint32_t umask,
-                            int32_t* upos, DenseMarks mk, int32_t gen) {
+                            int32_t* upos, DenseMarks mk) {
     if (blockIdx.x == 0 && threadIdx.x >= DC_NROW && threadIdx.x < DC_N) mk.cnt[threadIdx.x] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -360,7 +362,7 @@ __global__ void k_dn_dedupe(int nx, int ny, int nz, const int32_t* __restrict__ 
         upos[i] = -1;
         if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) {
             atomicCAS(&mk.cnt[DC_ERR], 0, -2 /* EDT_ERR_RANGE */);
-            mk.cnt[DC_CANCEL] = gen;
+            mk.cnt[DC_CANCEL] = 1;
             continue;
         }
         const unsigned long long key =
@@ -369,7 +371,7 @@ __global__ void k_dn_dedupe(int nx, int ny, int nz, const int32_t* __restrict__ 
         const int32_t h = hinsert(ukeys, umask, key, &created);
         if (h < 0) {                    // cannot happen: capacity >= 2 n
             atomicCAS(&mk.cnt[DC_ERR], 0, -3 /* EDT_ERR_CAPACITY */);
-            mk.cnt[DC_CANCEL] = gen;
+            mk.cnt[DC_CANCEL] = 1;
             continue;
         }
         upos[i] = h;
@@ -383,8 +385,8 @@ __global__ void k_dn_dedupe(int nx, int ny, int nz, const int32_t* __restrict__ 
 __global__ void k_dn_apply(int nx, int ny, const int32_t* __restrict__ xyz,
                            const uint8_t* __restrict__ state, int64_t n, uint8_t* occ,
                            unsigned long long* ukeys, int32_t* uvals, const int32_t* upos,
-                           DenseMarks mk, int32_t gen) {
-    const bool cancel = mk.cnt[DC_CANCEL] == gen;
+                           DenseMarks mk) {
+    const bool cancel = mk.cnt[DC_CANCEL] != 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t h = upos[i];
@@ -518,7 +520,6 @@ struct edt_dense_ctx {
     DenseLayout L;
     char* ws;
     DenseMarks mk;
-    int32_t gen;             // number of the current update (cancel marks)
 };
 
 extern "C" {
@@ -607,7 +608,6 @@ edt_status edt_dense_ctx_update(edt_dense_ctx* c, const int32_t* d_xyz, const ui
     if (!d_xyz || !d_state) return EDT_ERR_ARG;
     if (n > c->max_changes) return EDT_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;
-    c->gen = c->gen >= 0x7ffffffe ? 1 : c->gen + 1;
     const DenseLayout& L = c->L;
     char* b = c->ws;
     const int nx = c->nx, ny = c->ny, nz = c->nz, nxc = (nx + 63) / 64;
@@ -621,9 +621,9 @@ edt_status edt_dense_ctx_update(edt_dense_ctx* c, const int32_t* d_xyz, const ui
     int2* env = (int2*)(b + L.env);
     const int tn = grid_of((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_dn_dedupe, dim3(tn), dim3(256), 0, st, nx, ny, nz, d_xyz, n, ukeys, uvals,
-                       (uint32_t)(L.ucap - 1), upos, c->mk, c->gen);
+                       (uint32_t)(L.ucap - 1), upos, c->mk);
     hipLaunchKernelGGL(k_dn_apply, dim3(tn), dim3(256), 0, st, nx, ny, d_xyz, d_state, n, occ,
-                       ukeys, uvals, (const int32_t*)upos, c->mk, c->gen);
+                       ukeys, uvals, (const int32_t*)upos, c->mk);
     // listed rows (at most n), then the listed y and z groups
     const int32_t cap = c->d_max > 0 ? c->d_max * c->d_max : DINF;
     hipLaunchKernelGGL(k_dense_x<true>, dim3(grid_of(n, 65536)), dim3(64), 0, st, nx, ny, nz,

@@ -50,8 +50,9 @@ enum : uint32_t {
 };
 
 // device counters (int32 slots of the counter array).  C_ABORT: the global
-// transform ran out of pool; C_UABORT: the number of the last cancelled
-// update (calls are numbered from 1, so a stale value never matches).
+// transform ran out of pool; C_UABORT: nonzero once the current update is
+// cancelled (read by the first three kernels of the update, cleared by the
+// fourth, so a captured update replays with the same arguments).
 enum {
     C_NBLK = 0, C_NDIL, C_ERR, C_ABORT, C_NINT, C_UABORT,
     C_NYI, C_NZI, C_NADD, C_NREM, C_NSEED, C_NDIRTY, C_NRAISE, C_NLOWER,

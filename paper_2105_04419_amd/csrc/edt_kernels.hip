@@ -834,6 +834,8 @@ __global__ void __launch_bounds__(64) k_pass_x(Grid g, const int32_t* list, int 
 // pass x.
 __global__ void __launch_bounds__(64) k_upd_x_items(Grid g, int nxw) {
     __shared__ int32_t nb[72];
+    // no kernel from here on reads the cancel mark: clear it for the next call
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_UABORT] = 0;
     if ((int)blockIdx.x < nxw) pass_x_body(g, g.list_xs, C_NXS, blockIdx.x, nxw, nb);
     else items_update_body(g, (int64_t)blockIdx.x - nxw, (int64_t)gridDim.x - nxw);
 }
@@ -1571,11 +1573,11 @@ __device__ inline void init_slots(const Grid& g, int32_t slot) {
 // creator appends it; for an existing block the listing flag decides).  The
 // update's counters are zeroed here by the first workgroup, except the
 // dilation list's (zeroed by the previous call's fronts kernel), to which
-// every workgroup of this kernel appends.  A cancelled update writes its
-// number `gen` (never 0) into C_UABORT; later kernels compare with their own.
+// every workgroup of this kernel appends.  A cancelled update sets
+// C_UABORT, which the x-items kernel clears after its last reader.
 __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
                                    const uint8_t* __restrict__ state, int64_t n0,
-                                   const int32_t* n_dev, int32_t gen) {
+                                   const int32_t* n_dev) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
     if (blockIdx.x == 0 && threadIdx.x >= C_NYI && threadIdx.x < C_N &&
         threadIdx.x != C_NNEWDIL)
@@ -1590,7 +1592,7 @@ __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
             g.upos[i] = -1;
             if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz) {
                 set_error(g, -2);
-                g.cnt[C_UABORT] = gen;
+                g.cnt[C_UABORT] = 1;
             } else {
                 const unsigned long long key = (unsigned long long)x +
                     (unsigned long long)g.nx * ((unsigned long long)y + (unsigned long long)g.ny * z);
@@ -1598,7 +1600,7 @@ __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
                 const int32_t h = hinsert(g.ukeys, g.umask, key, &created);
                 if (h < 0) {
                     set_error(g, -3);
-                    g.cnt[C_UABORT] = gen;
+                    g.cnt[C_UABORT] = 1;
                 } else {
                     g.upos[i] = h;
                     atomicMax(&g.uvals[h], (int32_t)i);
@@ -1615,11 +1617,11 @@ __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
             e = insert_block(g, bx, by, bz, &created);
             if (e < 0) {
                 set_error(g, -3);
-                g.cnt[C_UABORT] = gen;
+                g.cnt[C_UABORT] = 1;
             }
         }
         const int32_t sl = claim_slots(g, created, e, key, 0u);
-        if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
+        if (created && sl < 0) g.cnt[C_UABORT] = 1;   // pool full
         init_slots(g, sl);
         bool newdil = created && sl >= 0;
         int32_t dslot = sl;
@@ -1645,7 +1647,7 @@ __global__ void k_upd_dedupe_alloc(Grid g, const int32_t* __restrict__ xyz,
 // this kernel clears the entry of every input.  Workgroups vb of vgrid.
 __device__ inline void upd_apply_body(const Grid& g, const int32_t* __restrict__ xyz,
                                       const uint8_t* __restrict__ state, int64_t n,
-                                      int32_t gen, int64_t vb, int64_t vgrid) {
+                                      int64_t vb, int64_t vgrid) {
     const int64_t t0 = vb * blockDim.x + threadIdx.x, stride = vgrid * blockDim.x;
     {
         // the blocks listed for dilation are being dilated by the other
@@ -1654,7 +1656,7 @@ __device__ inline void upd_apply_body(const Grid& g, const int32_t* __restrict__
         const int64_t nd = g.cnt[C_NNEWDIL];
         for (int64_t i = t0; i < nd; i += stride) atomicAnd(&g.flags[g.list_newdil[i]], ~F_NEWDIL);
     }
-    if (g.cnt[C_UABORT] == gen) {
+    if (g.cnt[C_UABORT] != 0) {
         for (int64_t i = t0; i < n; i += stride) {
             const int32_t h = g.upos[i];
             if (h >= 0) {
@@ -1711,8 +1713,8 @@ __device__ inline void upd_apply_body(const Grid& g, const int32_t* __restrict__
 
 // Blocks that gain their first obstacle bring their R-neighbourhood in, one
 // thread per neighbour.  Workgroups vb of vgrid.
-__device__ inline void upd_dilate_body(const Grid& g, int32_t gen, int64_t vb, int64_t vgrid) {
-    if (g.cnt[C_UABORT] == gen) return;
+__device__ inline void upd_dilate_body(const Grid& g, int64_t vb, int64_t vgrid) {
+    if (g.cnt[C_UABORT] != 0) return;
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t total = (int64_t)g.cnt[C_NNEWDIL] * w3;
     const int lane = __lane_id();
@@ -1733,12 +1735,12 @@ __device__ inline void upd_dilate_body(const Grid& g, int32_t gen, int64_t vb, i
                 e = insert_block(g, bx, by, bz, &created);
                 if (e < 0) {
                     set_error(g, -3);
-                    g.cnt[C_UABORT] = gen;
+                    g.cnt[C_UABORT] = 1;
                 }
             }
         }
         const int32_t sl = claim_slots(g, created, e, key, 0u);
-        if (created && sl < 0) g.cnt[C_UABORT] = gen;   // pool full
+        if (created && sl < 0) g.cnt[C_UABORT] = 1;   // pool full
         init_slots(g, sl);
     }
 }
@@ -1753,10 +1755,10 @@ __device__ inline void upd_dilate_body(const Grid& g, int32_t gen, int64_t vb, i
 // still leaves the map as it was.
 __global__ void k_upd_apply_dilate(Grid g, const int32_t* __restrict__ xyz,
                                    const uint8_t* __restrict__ state, int64_t n0,
-                                   const int32_t* n_dev, int32_t gen, int napply) {
+                                   const int32_t* n_dev, int napply) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n0;
-    if ((int)blockIdx.x < napply) upd_apply_body(g, xyz, state, n, gen, blockIdx.x, napply);
-    else upd_dilate_body(g, gen, (int64_t)blockIdx.x - napply, (int64_t)gridDim.x - napply);
+    if ((int)blockIdx.x < napply) upd_apply_body(g, xyz, state, n, blockIdx.x, napply);
+    else upd_dilate_body(g, (int64_t)blockIdx.x - napply, (int64_t)gridDim.x - napply);
 }
 
 // Bounding boxes (block-local) of the added and removed voxels of each seed.
@@ -1811,14 +1813,14 @@ __device__ inline int box_dist2(int32_t pk, int sx, int sy, int sz, int bx, int 
 // after the occupancy changed (the pool filled during the dilation) the
 // workgroup instead restores the seed's bits from its change masks, drops
 // its marks and the F_DILATED it gained, and builds no fronts.
-__global__ void __launch_bounds__(1024) k_upd_fronts(Grid g, int32_t gen) {
+__global__ void __launch_bounds__(1024) k_upd_fronts(Grid g) {
     __shared__ int32_t rec[32];     // boxes, block coordinates, 27 tile positions
     __shared__ int wcnt[16][5];     // per wave: dirty, ys, xs, raise, lower
     __shared__ int bbase[3];        // the workgroup's list positions
     const int R = g.R, w = 2 * R + 1, w3 = w * w * w;
     const int64_t ns = g.cnt[C_NSEED];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    const bool cancel = g.cnt[C_UABORT] == gen;
+    const bool cancel = g.cnt[C_UABORT] != 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[C_NNEWDIL] = 0;
     for (int64_t si = blockIdx.x; si < ns; si += gridDim.x) {
         if (cancel) {

@@ -2,14 +2,16 @@
 (HIP graphs through torch.cuda.CUDAGraph) and replayed on new inputs written
 into the captured buffers: every replay, with eager work and synchronisation
 in between, must equal the same call made eagerly, a cancelled replay
-included."""
+included (and the replays after it: the cancel mark is state on the device,
+cleared within the call, since a captured call keeps its arguments).  The
+dense context's update likewise."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import workloads
-from paper_2105_04419_amd import Field
+from paper_2105_04419_amd import DenseField, Field
 
 pytestmark = pytest.mark.gpu
 
@@ -105,3 +107,50 @@ def test_scan_integration_graph_replays_match_eager():
         assert np.array_equal(g_field.occupancy().cpu().numpy(), e_field.occupancy().cpu().numpy())
         assert np.array_equal(g_field.dense().cpu().numpy(), e_field.dense().cpu().numpy()), t
         assert g_field.error() == 0
+
+
+def test_dense_context_graph_replays_match_eager():
+    occ = workloads.dense_boxes(4)
+    nz, ny, nx = occ.shape
+    n = 128
+    rng = np.random.default_rng(21)
+    g_field = DenseField((nx, ny, nz), 0, max_changes=n)
+    e_field = DenseField((nx, ny, nz), 0, max_changes=n)
+    g_field.global_(torch.from_numpy(occ).cuda())
+    e_field.global_(torch.from_numpy(occ).cuda())
+    xyz_buf = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+    st_buf = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    xyz_buf[:, 0] = 1                     # a valid batch for the capture's warm-up
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g_field.update(xyz_buf, st_buf)
+    torch.cuda.current_stream().wait_stream(s)
+    e_field.update(xyz_buf, st_buf)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g_field.update(xyz_buf, st_buf)
+    torch.cuda.synchronize()
+    cur = occ.copy()
+    cur[0, 0, 1] = 0
+    for t in range(6):
+        xyz = np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n), rng.integers(0, nz, n)],
+                       1).astype(np.int32)
+        st = (rng.random(n) < 0.5).astype(np.uint8)
+        cancelled = t in (2, 3)                  # two cancelled replays in a row, then more
+        if cancelled:
+            xyz[5] = [0, ny, 0]
+        xyz_buf.copy_(torch.from_numpy(xyz))
+        st_buf.copy_(torch.from_numpy(st))
+        graph.replay()
+        e_field.update(torch.from_numpy(xyz).cuda(), torch.from_numpy(st).cuda())
+        torch.cuda.synchronize()
+        if not cancelled:
+            for (x, y, z), v in zip(xyz, st):
+                cur[z, y, x] = v
+        got = g_field.field().cpu().numpy()
+        assert np.array_equal(got, e_field.field().cpu().numpy()), f"replay {t}"
+        assert np.array_equal(got, oracle.edt_uncapped(cur)), f"replay {t} vs oracle"
+        assert g_field.error() == (-2 if cancelled else 0)
+        assert e_field.error() == (-2 if cancelled else 0)

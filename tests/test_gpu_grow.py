@@ -50,6 +50,30 @@ def test_full_pool_cancels_update_then_grow_and_repeat():
     assert np.array_equal(f.occupancy().cpu().numpy(), occ)
 
 
+def test_pool_full_in_the_first_kernel_leaves_the_map():
+    # 4 free slots, 6 new blocks: the call is cancelled before any bit
+    # changes (the case above fills the pool only during the dilation, after
+    # the bits changed, and is rolled back)
+    nx, ny, nz = 96, 96, 40
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    occ[4, 4, 4] = 1
+    f = Field((nx, ny, nz), 8, max_blocks=12)
+    f.global_(cu(occ))
+    before, occ_before = f.dense().cpu().numpy(), f.occupancy().cpu().numpy()
+    xyz = np.array([[5, 4, 4]] + [[20 + 12 * i, 50, 30] for i in range(6)], np.int32)
+    f.update(cu(xyz), cu(np.ones(len(xyz), np.uint8)))
+    assert f.error() == -3
+    assert np.array_equal(f.dense().cpu().numpy(), before)
+    assert np.array_equal(f.occupancy().cpu().numpy(), occ_before)
+    # the cancelled call left nothing behind that a fitting one would see
+    near = np.array([[5, 4, 4], [4, 4, 4]], np.int32)
+    f.update(cu(near), cu(np.array([1, 0], np.uint8)))
+    assert f.error() == 0
+    occ[4, 4, 5], occ[4, 4, 4] = 1, 0
+    assert np.array_equal(f.dense().cpu().numpy(), oracle.edt_separable(occ, 8))
+    assert np.array_equal(f.occupancy().cpu().numpy(), occ)
+
+
 @pytest.mark.parametrize("dmax", [6, 20, 70])
 def test_updates_grow_the_pool_on_demand(dmax):
     rng = np.random.default_rng(dmax)
