@@ -15,7 +15,8 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
   clearance      clearance cost forward + backward on the 64x64x32 map field
                  with 4096 x 64 waypoints, points per second;
   batched        64 dense room maps (sides 32..256, d_max 24): autotuned
-                 fused persistent launch vs per-map launches;
+                 launch (fused persistent or one launch per pass, and the
+                 schedule) vs per-map launches;
   dense_small    the 64x64x32 boxes map (d_max 20), microseconds per
                  global transform;
   interior       interior distances (edt_interior) of the tunnel map's
@@ -581,36 +582,45 @@ def bench_clearance(args, torch, np):
 
 def bench_batch(args, torch, np):
     import workloads
-    from paper_2105_04419_amd import FUSED, PER_MAP, DEFAULT_TUNE, Batch, autotune
+    from paper_2105_04419_amd import FUSED, PER_MAP, PHASED, DEFAULT_TUNE, Batch, autotune
     maps = workloads.batch_maps(args.seed)
     b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
     occ = b.pack(maps)
     out = torch.empty(b.total, dtype=torch.int32, device=b.device)
     best, results = autotune.tune(b, occ, out, reps=3)
+    best_of = {m: min((r for r in results if r[0]["mode"] == m), key=lambda r: r[1])[0]
+               for m in (FUSED, PHASED)}
     reps = 10
     t_tuned = autotune.time_config(b, occ, out, best, reps)
-    t_default = autotune.time_config(b, occ, out, DEFAULT_TUNE, reps)
+    t_mode = {m: autotune.time_config(b, occ, out, c, reps) for m, c in best_of.items()}
+    t_default = autotune.time_config(b, occ, out, DEFAULT_TUNE, reps, mode=FUSED)
     per_map_cfg = dict(DEFAULT_TUNE, lrun=best["lrun"])
     t_per_map = autotune.time_config(b, occ, out, per_map_cfg, reps, mode=PER_MAP)
-    fused = b.run(occ, mode=FUSED, tune=best)
+    tuned = b.run(occ, tune=best).clone()
     per_map = b.run(occ, mode=PER_MAP, tune=per_map_cfg)
+    fused = b.run(occ, tune=best_of[FUSED])
     nvox = b.total
+    names = {FUSED: "fused", PHASED: "phased"}
     return {
         "maps": len(maps),
         "voxels": nvox,
         "d_max": 24,
-        "fused_ms": round(t_tuned, 4),
-        "fused_voxels_per_s": nvox / (t_tuned * 1e-3),
+        "tuned_ms": round(t_tuned, 4),
+        "tuned_voxels_per_s": nvox / (t_tuned * 1e-3),
+        "tuned_schedule": dict(best, mode=names[best["mode"]]),
+        "fused_ms": round(t_mode[FUSED], 4),
+        "phased_ms": round(t_mode[PHASED], 4),
         "fused_default_schedule_ms": round(t_default, 4),
         "per_map_ms": round(t_per_map, 4),
         "per_map_voxels_per_s": nvox / (t_per_map * 1e-3),
-        "speedup_fused_vs_per_map": round(t_per_map / t_tuned, 3),
-        "tuned_schedule": best,
-        "search_space": {k: v for k, v in autotune.SPACE.items()},
+        "speedup_tuned_vs_per_map": round(t_per_map / t_tuned, 3),
+        "search_space": {k: ([names[m] for m in v] if k == "mode" else v)
+                         for k, v in autotune.SPACE.items()},
         "trials": len(results),
+        "tuned_equals_per_map": bool(torch.equal(tuned, per_map)),
         "fused_equals_per_map": bool(torch.equal(fused, per_map)),
         # floor: 1 B of occupancy read and 4 B of int32 written per voxel
-        "fused_hbm_frac_floor": round(5 * nvox / (t_tuned * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_frac_floor": round(5 * nvox / (t_tuned * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
     }
 
 
@@ -797,7 +807,7 @@ def main():
         out["integrate"] = bench_integrate(g, args, torch, np)
         log("[bench] clearance 4096 x 64")
         out["clearance"] = bench_clearance(args, torch, np)
-        log("[bench] batched: 64 dense maps, autotuned fused launch vs per-map launches")
+        log("[bench] batched: 64 dense maps, autotuned launch vs per-map launches")
         out["batched"] = bench_batch(args, torch, np)
         log("[bench] dense 64x64x32 global transform")
         out["dense_small"] = bench_dense_small(args, torch, np)

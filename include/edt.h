@@ -301,8 +301,14 @@ typedef struct {
 
 /* EDT_BATCH_FUSED: one persistent cooperative launch for all maps and
  * passes, a grid-wide barrier between the x, y and z passes.
- * EDT_BATCH_PER_MAP: three launches (x, y, z) per map. */
-typedef enum { EDT_BATCH_FUSED = 0, EDT_BATCH_PER_MAP = 1 } edt_batch_mode;
+ * EDT_BATCH_PER_MAP: three launches (x, y, z) per map.
+ * EDT_BATCH_PHASED: three launches (x, y, z) for all maps, with the fused
+ * launch's schedule; each launch holds the code of its pass only. */
+typedef enum {
+    EDT_BATCH_FUSED = 0,
+    EDT_BATCH_PER_MAP = 1,
+    EDT_BATCH_PHASED = 2
+} edt_batch_mode;
 
 typedef struct edt_batch edt_batch;
 

@@ -21,7 +21,7 @@ import torch
 
 __all__ = ["Field", "ClearanceCost", "clearance_cost", "clearance_fwd", "clearance_bwd", "lib",
            "EdtError", "LIB_PATH",
-           "Batch", "batch_global", "FUSED", "PER_MAP", "DenseField", "dense_global"]
+           "Batch", "batch_global", "FUSED", "PER_MAP", "PHASED", "DenseField", "dense_global"]
 
 LIB_PATH = os.environ.get("EDT_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                        "libedt.so")
@@ -561,7 +561,7 @@ def clearance_cost(s, wp, h: float = 0.2, margin: float = 1.0):
 # ---------------------------------------------------------------------------
 # batched dense maps
 # ---------------------------------------------------------------------------
-FUSED, PER_MAP = 0, 1
+FUSED, PER_MAP, PHASED = 0, 1, 2
 DEFAULT_TUNE = {"lrun": 8, "waves_per_cu": 8, "chunk": 4, "schedule": 0, "wg_waves": 4}
 
 
@@ -617,8 +617,12 @@ class Batch:
         return [out[o:o + nx * ny * nz].view(nz, ny, nx)
                 for o, (nx, ny, nz) in zip(self.offsets, self.shapes)]
 
-    def run(self, occ_flat: torch.Tensor, out: torch.Tensor | None = None, mode: int = FUSED,
+    def run(self, occ_flat: torch.Tensor, out: torch.Tensor | None = None, mode: int | None = None,
             tune: dict | None = None, stream=None) -> torch.Tensor:
+        """mode: FUSED, PHASED or PER_MAP; None takes the schedule's "mode"
+        entry (as the autotuner returns it), else FUSED."""
+        if mode is None:
+            mode = (tune or {}).get("mode", FUSED)
         occ_flat = _dev_tensor(occ_flat, torch.uint8, (self.total,))
         if out is None:
             out = torch.empty(self.total, dtype=torch.int32, device=self.device)
@@ -632,7 +636,7 @@ class Batch:
         return out
 
 
-def batch_global(maps, d_max: int, mode: int = FUSED, tune: dict | None = None):
+def batch_global(maps, d_max: int, mode: int | None = None, tune: dict | None = None):
     """Transform a list of dense (nz, ny, nx) uint8 maps; returns int32 fields."""
     shapes = [(m.shape[2], m.shape[1], m.shape[0]) for m in maps]
     b = Batch(shapes, d_max)

@@ -1,10 +1,13 @@
 """Autotuner for the batched transform's schedule.
 
-The search space is the schedule of the fused persistent launch:
+The search space is the launch mode and its schedule:
+  mode          FUSED (one persistent launch, grid barriers between the
+                passes) or PHASED (one launch per pass)
   lrun          blocks per work item along y and z
   chunk         work items taken per queue atomic
   waves_per_cu  waves resident per compute unit (grid size of the launch)
   schedule      0 = dynamic queue, 1 = static stride
+  wg_waves      waves per workgroup
 Each candidate is timed with HIP events (median of `reps` runs after one
 warm-up run) on the caller's batch; the winner is cached in a JSON file keyed
 by GPU architecture, total-size bucket (log2 of voxels) and d_max.  Every
@@ -20,14 +23,15 @@ import os
 
 import torch
 
-from . import FUSED, Batch
+from . import FUSED, PHASED, Batch
 
 SPACE = {
-    "lrun": [2, 4, 8, 16],
-    "chunk": [1, 4, 16],
-    "waves_per_cu": [4, 8, 16],
+    "mode": [FUSED, PHASED],
+    "lrun": [4, 8, 16, 32],
+    "chunk": [4, 16],
+    "waves_per_cu": [8, 16, 32],
     "schedule": [0, 1],
-    "wg_waves": [1, 2, 4, 8],
+    "wg_waves": [1, 4, 8],
 }
 
 
@@ -68,8 +72,11 @@ def store(batch: Batch, cfg: dict):
     os.replace(tmp, path)
 
 
-def time_config(batch: Batch, occ, out, cfg: dict, reps: int = 5, mode: int = FUSED) -> float:
-    """Median milliseconds of one batched run with schedule `cfg`."""
+def time_config(batch: Batch, occ, out, cfg: dict, reps: int = 5, mode: int | None = None) -> float:
+    """Median milliseconds of one batched run with schedule `cfg` (launch
+    mode: `mode`, else the schedule's own, else FUSED)."""
+    if mode is None:
+        mode = cfg.get("mode", FUSED)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     batch.run(occ, out, mode=mode, tune=cfg)

@@ -13,7 +13,10 @@
 // launch: waves take items from a per-phase queue (chunks of `chunk` items
 // through one atomic, or a static stride), and a grid-wide barrier separates
 // the phases, so a map's y pass starts only after every x item is written.
-// PER_MAP launches the same phase code three times per map.
+// PHASED runs the same schedule as three plain launches, one per phase, each
+// a kernel of its own phase only (its own register and LDS footprint; the
+// kernel boundary replaces the grid barrier).  PER_MAP launches the phase
+// kernels three times per map.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
@@ -71,20 +74,20 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
 // inside each block), 7 integer ops per voxel; M = ceil(d_max / 8) blocks of
 // context cover d_max.  Results gather in LDS in the g1 block layout
 // (y + 8x + 64z) and leave as 16-byte stores.
-// LDS of item_x: each wave owns 8 blocks of XLS u16 (padded from 512); the
-// workgroup's share is sized at launch, one slice per wave
-constexpr int XLS = 514;
-constexpr size_t XBYTES_PER_WAVE = 8 * XLS * sizeof(uint16_t);
+// LDS of item_x: each wave owns the row words of its window (64 rows of up to
+// three 64-bit words), which one block of results (512 u16) reuses once they
+// are read; the workgroup's share is sized at launch, one slice per wave
+constexpr size_t XBYTES_PER_WAVE = 64 * 3 * sizeof(unsigned long long);
 extern __shared__ __align__(16) uint16_t xlds[];
 
 template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
-    constexpr int LS = XLS;
     constexpr int NBYTES = 64 + 16 * M;          // window bytes per row
     constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
     constexpr int RB = 16;                       // rows whose loads are in flight together
     constexpr int NB = 8 + 2 * M;                // window blocks
-    uint16_t* buf = xlds + (threadIdx.x >> 6) * (8 * LS);
+    static_assert(NWIN <= 3, "row words per lane");
+    uint16_t* buf = xlds + (threadIdx.x >> 6) * (XBYTES_PER_WAVE / sizeof(uint16_t));
     // the rows' window words (row r, word w at rowbits[NWIN r + w]) share the
     // buffer: they are read back before any result is written
     unsigned long long* rowbits = (unsigned long long*)buf;
@@ -162,6 +165,9 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
         R = bj ? (uint32_t)(__ffs(bj) - 1) : R + 8u;
     }
     const int rofs = (lane & 7) + 64 * (lane >> 3);      // this row in the g1 block layout
+    const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
+    // the row words are in registers from here on: the buffer takes results
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const uint32_t bj = b[M + j];
@@ -176,19 +182,16 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
             rr = (rr + 1u) & ~mk[x];
             const uint32_t v = min(min(d[x], rr), dmax);
             // g1 in the window's representation (binary16 for small radii)
-            buf[j * LS + rofs + 8 * x] = win_f16(M)
+            buf[rofs + 8 * x] = win_f16(M)
                 ? __builtin_bit_cast(uint16_t, (_Float16)(v * v)) : (uint16_t)(v * v);
         }
-    }
-    // block j: lane writes g1 elements 8 lane .. 8 lane + 7 (16 bytes)
-    const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int bx = bx0 + j;
-        if (bx >= m.nbx) break;
-        const uint32_t* src = (const uint32_t*)(buf + j * LS) + 4 * lane;
-        const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
-        *(uint4*)(a.g1 + (brow + bx) * 512 + 8 * lane) = v;
+        // block j: lane writes g1 elements 8 lane .. 8 lane + 7 (16 bytes);
+        // the wave's LDS operations complete in order, the barriers keep the
+        // compiler from moving them across
+        __builtin_amdgcn_wave_barrier();
+        const uint4 v = ((const uint4*)buf)[lane];
+        __builtin_amdgcn_wave_barrier();
+        if (bx0 + j < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j) * 512 + 8 * lane) = v;
     }
 }
 
@@ -264,25 +267,28 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     window_min<M, true, win_f16(M)>(bz0, len, Dp, blk, emit);
 }
 
-template <int M>
-__device__ inline void run_item(const BArgs& a, int phase, int gi, uint32_t Dp) {
-    const int* pref = a.pref + phase * (a.n_maps + 1);
-    const int mi = a.itemmap[phase * a.icap + gi];
+template <int M, int PHASE>
+__device__ inline void run_item(const BArgs& a, int gi, uint32_t Dp) {
+    const int* pref = a.pref + PHASE * (a.n_maps + 1);
+    const int mi = a.itemmap[PHASE * a.icap + gi];
     const MapDev m = a.maps[mi];
     const int li = gi - pref[mi];
-    if (phase == 0) item_x<M>(a, m, li);
-    else if (phase == 1) item_y<M>(a, m, li, Dp);
+    if (PHASE == 0) item_x<M>(a, m, li);
+    else if (PHASE == 1) item_y<M>(a, m, li, Dp);
     else item_z<M>(a, m, li, Dp);
 }
 
-// Items [lo, hi) of `phase`; one wave per item.  Dynamic schedule: a wave
-// takes `chunk` items per atomic on the phase's counter (cidx); static: wave
-// w takes items lo + w, lo + w + nwaves, ...
-template <int M>
-__device__ void run_phase(const BArgs& a, int phase, int lo, int hi, int cidx) {
+// Items [lo, hi) of phase PHASE; one wave per item.  Dynamic schedule: a
+// wave takes `chunk` items per atomic on the phase's counter (cidx); static:
+// wave w takes items lo + w, lo + w + nwaves, ...
+template <int M, int PHASE>
+__device__ void run_phase(const BArgs& a, int lo, int hi, int cidx) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    const int wid = blockIdx.x * wpb + (threadIdx.x >> 6);
+    // item indices are wave-uniform: kept in scalar registers, so the map
+    // record, the item's block coordinates and the row addresses derived
+    // from them are scalar too
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
     const int nwaves = gridDim.x * wpb;
     const uint32_t Dw = win_f16(M) ? f16_bits((uint32_t)a.D) : (uint32_t)a.D;
     const uint32_t Dp = Dw | (Dw << 16);        // D in the window's representation
@@ -290,13 +296,13 @@ __device__ void run_phase(const BArgs& a, int phase, int lo, int hi, int cidx) {
         for (;;) {
             int base = 0;
             if (lane == 0) base = atomicAdd(&a.queues[cidx], a.chunk);
-            base = __shfl(base, 0) + lo;
+            base = __builtin_amdgcn_readfirstlane(base) + lo;   // lane 0's grab
             if (base >= hi) break;
             const int end = min(base + a.chunk, hi);
-            for (int i = base; i < end; ++i) run_item<M>(a, phase, i, Dp);
+            for (int i = base; i < end; ++i) run_item<M, PHASE>(a, i, Dp);
         }
     } else {
-        for (int i = lo + wid; i < hi; i += nwaves) run_item<M>(a, phase, i, Dp);
+        for (int i = lo + wid; i < hi; i += nwaves) run_item<M, PHASE>(a, i, Dp);
     }
 }
 
@@ -306,18 +312,20 @@ __global__ void __launch_bounds__(512) k_batch_fused(BArgs a) {
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
     const int n = a.n_maps;
-    for (int phase = 0; phase < 3; ++phase) {
-        const int* pref = a.pref + phase * (n + 1);
-        run_phase<M>(a, phase, pref[0], pref[n], phase * (n + 1) + n);
-        if (phase < 2) grid.sync();
-    }
+    run_phase<M, 0>(a, a.pref[0], a.pref[n], n);
+    grid.sync();
+    run_phase<M, 1>(a, a.pref[n + 1], a.pref[2 * n + 1], 2 * n + 1);
+    grid.sync();
+    run_phase<M, 2>(a, a.pref[2 * n + 2], a.pref[3 * n + 2], 3 * n + 2);
 }
 
-// PER_MAP: one phase of one map.
-template <int M>
-__global__ void __launch_bounds__(512) k_batch_phase(BArgs a, int phase, int map) {
-    const int* pref = a.pref + phase * (a.n_maps + 1);
-    run_phase<M>(a, phase, pref[map], pref[map + 1], phase * (a.n_maps + 1) + map);
+// PHASED: one phase of all maps (map = -1), PER_MAP: one phase of one map.
+template <int M, int PHASE>
+__global__ void __launch_bounds__(512) k_batch_phase(BArgs a, int map) {
+    const int n = a.n_maps;
+    const int* pref = a.pref + PHASE * (n + 1);
+    if (map < 0) run_phase<M, PHASE>(a, pref[0], pref[n], PHASE * (n + 1) + n);
+    else run_phase<M, PHASE>(a, pref[map], pref[map + 1], PHASE * (n + 1) + map);
 }
 
 // Item prefix sums of the three phases over the maps (processing order), one
@@ -467,6 +475,29 @@ edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu
             return EDT_ERR_HIP;
         return EDT_OK;
     }
+    // only the x phase uses LDS
+    const void* kern[3] = {(const void*)k_batch_phase<M, 0>, (const void*)k_batch_phase<M, 1>,
+                           (const void*)k_batch_phase<M, 2>};
+    const size_t klds[3] = {lds, 0, 0};
+    const int wpc = waves_per_cu > 0 ? waves_per_cu : 8;
+    if (mode == EDT_BATCH_PHASED) {
+        // as many waves as the fused launch would have, per phase
+        for (int phase = 0; phase < 3; ++phase) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern[phase], bs,
+                                                             klds[phase]) != hipSuccess)
+                return EDT_ERR_HIP;
+            const int wgs_per_cu = (wpc + wg_waves - 1) / wg_waves;
+            const int g = b->cus * (wgs_per_cu < per_cu ? wgs_per_cu : per_cu);
+            if (g < 1) return EDT_ERR_HIP;
+            int map = -1;
+            void* args[] = {(void*)&a, (void*)&map};
+            if (hipLaunchKernel(kern[phase], dim3(g), dim3(bs), args, klds[phase], st) !=
+                hipSuccess)
+                return EDT_ERR_HIP;
+        }
+        return EDT_OK;
+    }
     // PER_MAP: three launches per map, each sized to the map's items
     for (int mi = 0; mi < b->n; ++mi) {
         const MapDev& m = b->host_maps[mi];
@@ -475,9 +506,12 @@ edt_status launch_batch(edt_batch* b, const BArgs& a, int mode, int waves_per_cu
             (int64_t)m.nbx * m.nbz * ((m.nby + a.lrun - 1) / a.lrun),
             (int64_t)m.nxr * m.ny * ((m.nbz + a.lrun - 1) / a.lrun)};
         for (int phase = 0; phase < 3; ++phase) {
-            const int waves = grid_cap(items[phase], b->cus * (waves_per_cu > 0 ? waves_per_cu : 8));
-            hipLaunchKernelGGL(k_batch_phase<M>, dim3((waves + wg_waves - 1) / wg_waves), dim3(bs),
-                               lds, st, a, phase, mi);
+            const int waves = grid_cap(items[phase], b->cus * wpc);
+            int map = mi;
+            void* args[] = {(void*)&a, (void*)&map};
+            if (hipLaunchKernel(kern[phase], dim3((waves + wg_waves - 1) / wg_waves), dim3(bs),
+                                args, klds[phase], st) != hipSuccess)
+                return EDT_ERR_HIP;
         }
     }
     return hipGetLastError() == hipSuccess ? EDT_OK : EDT_ERR_HIP;
@@ -583,7 +617,8 @@ edt_status edt_batch_destroy(edt_batch* b) {
 edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int32_t mode,
                          const edt_tune* tune, void* stream) {
     if (!b || !d_occ || !d_out) return EDT_ERR_ARG;
-    if (mode != EDT_BATCH_FUSED && mode != EDT_BATCH_PER_MAP) return EDT_ERR_ARG;
+    if (mode != EDT_BATCH_FUSED && mode != EDT_BATCH_PER_MAP && mode != EDT_BATCH_PHASED)
+        return EDT_ERR_ARG;
     edt_tune t = {8, 8, 4, 0, 4};
     if (tune) t = *tune;
     if (t.wg_waves == 0) t.wg_waves = 4;

@@ -1,13 +1,13 @@
 """Batched transform of many dense maps: the fused persistent launch, the
-per-map launches and the CPU oracle agree bit for bit on every map, for
-every schedule the autotuner may pick."""
+launch per pass, the per-map launches and the CPU oracle agree bit for bit
+on every map, for every schedule the autotuner may pick."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import workloads
-from paper_2105_04419_amd import FUSED, PER_MAP, Batch
+from paper_2105_04419_amd import FUSED, PER_MAP, PHASED, Batch
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_small_batch_all_modes(dmax):
     check(b, maps, f, dmax, "fused")
     p = b.run(occ, mode=PER_MAP)
     assert torch.equal(f, p)
+    assert torch.equal(b.run(occ, mode=PHASED), p)
 
 
 @pytest.mark.parametrize("tune", [
@@ -66,7 +67,10 @@ def test_schedules_are_bit_identical(tune):
     ref = b.run(occ, mode=PER_MAP)
     check(b, maps, ref, 24, "per_map")
     assert torch.equal(b.run(occ, mode=FUSED, tune=tune), ref)
+    assert torch.equal(b.run(occ, mode=PHASED, tune=tune), ref)
     assert torch.equal(b.run(occ, mode=PER_MAP, tune=tune), ref)
+    # the autotuner's form: the mode inside the schedule
+    assert torch.equal(b.run(occ, tune=dict(tune, mode=PHASED)), ref)
 
 
 def test_rejects_bad_schedule():
@@ -79,17 +83,23 @@ def test_rejects_bad_schedule():
         t.update(bad)
         with pytest.raises(EdtError):
             b.run(occ, mode=FUSED, tune=t)
+        with pytest.raises(EdtError):
+            b.run(occ, mode=PHASED, tune=t)
+    with pytest.raises(EdtError):
+        b.run(occ, mode=3)
 
 
 def test_full_batch_of_64_room_maps():
     """64 maps with sides U{32..256}, density U(1%, 30%) plus room layouts,
-    d_max 24: fused == per-map == oracle for every map."""
+    d_max 24: fused == phased == per-map == oracle for every map."""
     maps = workloads.batch_maps(0)
     b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 24)
     occ = b.pack(maps)
     f = b.run(occ, mode=FUSED)
     p = b.run(occ, mode=PER_MAP)
     assert torch.equal(f, p)
+    tuned = {"lrun": 16, "chunk": 4, "schedule": 1, "waves_per_cu": 16, "wg_waves": 4}
+    assert torch.equal(b.run(occ, mode=PHASED, tune=tuned), p)
     check(b, maps, f, 24, "fused 64 maps")
 
 
@@ -117,6 +127,7 @@ def test_degenerate_and_extreme_maps():
         f = b.run(occ, mode=FUSED)
         check(b, maps, f, dmax, f"degenerate d={dmax}")
         assert torch.equal(f, b.run(occ, mode=PER_MAP))
+        assert torch.equal(f, b.run(occ, mode=PHASED))
     single = Batch([(33, 17, 5)], 24)
     m = (rng.random((5, 17, 33)) < 0.05).astype(np.uint8)
     out = single.run(single.pack([m]), mode=FUSED)
@@ -133,3 +144,21 @@ def test_run_length_changes_between_runs():
     for lrun in (2, 16, 2, 8, 16):
         t = {"lrun": lrun, "chunk": 4, "schedule": 1, "waves_per_cu": 8, "wg_waves": 4}
         assert torch.equal(b.run(occ, mode=FUSED, tune=t), ref), lrun
+        assert torch.equal(b.run(occ, mode=PHASED, tune=t), ref), lrun
+
+
+def test_autotuner_picks_a_launch_mode_and_schedule(tmp_path, monkeypatch):
+    from paper_2105_04419_amd import autotune
+    monkeypatch.setenv("VDBEDT_CACHE", str(tmp_path))
+    maps = small_maps(5, 6, 8, 60)
+    b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], 16)
+    occ = b.pack(maps)
+    space = {"mode": [FUSED, PHASED], "lrun": [4, 16], "chunk": [4], "waves_per_cu": [8],
+             "schedule": [0, 1], "wg_waves": [4]}
+    best, results = autotune.tune(b, occ, space=space, reps=1)
+    assert len(results) == 8 and best in [r[0] for r in results]
+    assert best["mode"] in (FUSED, PHASED)
+    ref = b.run(occ, mode=PER_MAP)
+    check(b, maps, ref, 16, "per_map")
+    assert torch.equal(b.run(occ, tune=best), ref)
+    assert autotune.load(b) == best
