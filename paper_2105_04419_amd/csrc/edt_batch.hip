@@ -37,6 +37,7 @@ struct MapDev {
     int64_t occ_off;         // bytes into the occupancy input
     int64_t out_off;         // int32 elements into the output
     int64_t blk_off;         // blocks into g1 / g2
+    int64_t pad2;            // (64 bytes: read as four 16-byte words)
 };
 
 struct BArgs {
@@ -68,17 +69,29 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
 // phase 0: squared distance along x for a strip of 8 blocks.  The wave walks
 // the strip's 64 rows (y, z); for each row the lanes read the window
 // x = 8 (bx0 - M) .. 8 (bx0 + 8 + M) - 1 with coalesced byte loads (64 + 16M
-// bytes, up to three per lane) and ballots make it a bit string, which goes
-// through LDS to lane r.  Then every lane holds its own row and
-// sweeps it with a carried distance (left to right, then right to left
-// inside each block), 7 integer ops per voxel; M = ceil(d_max / 8) blocks of
-// context cover d_max.  Results gather in LDS in the g1 block layout
-// (y + 8x + 64z) and leave as 16-byte stores.
-// LDS of item_x: each wave owns the row words of its window (64 rows of up to
-// three 64-bit words), which one block of results (512 u16) reuses once they
-// are read; the workgroup's share is sized at launch, one slice per wave
-constexpr size_t XBYTES_PER_WAVE = 64 * 3 * sizeof(unsigned long long);
+// bytes, up to three per lane), ballots make it a bit string, which goes
+// through LDS to lane r.  Then
+// every lane holds its own row and sweeps it with carried distances, in
+// packed 16-bit pairs: blocks j and j + 4 of the strip at once (the carry
+// into block 4 comes from the bits of blocks 0..3, the carry out of block 3
+// from those of blocks 4..7), about 6 operations per voxel; M = ceil(d_max /
+// 8) blocks of context cover d_max.  Results gather in LDS in the g1 block
+// layout (y + 8x + 64z), two blocks at a time, and leave as 16-byte stores.
+// LDS of item_x: the row words of the window (64 rows of up to three 64-bit
+// words), which two result blocks (2 x 512 u16) reuse once they are read;
+// the workgroup's share is sized at launch, one slice per wave
+constexpr size_t XBYTES_PER_WAVE = 2 * 512 * sizeof(uint16_t);
 extern __shared__ __align__(16) uint16_t xlds[];
+
+// each 16-bit half of t: all ones if its bit 15 is set, else zero.  Written
+// as the instruction itself: as plain code the compiler turns the masks into
+// per-half compares and selects, three times the work of this one operation.
+__device__ inline uint32_t pk_sign_mask(uint32_t t) {
+    uint32_t r;
+    // op_sel_hi:[0,1]: the high half shifts by the constant's low half too
+    asm("v_pk_ashrrev_i16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(r) : "v"(t));
+    return r;
+}
 
 template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
@@ -86,11 +99,7 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
     constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
     constexpr int RB = 16;                       // rows whose loads are in flight together
     constexpr int NB = 8 + 2 * M;                // window blocks
-    static_assert(NWIN <= 3, "row words per lane");
     uint16_t* buf = xlds + (threadIdx.x >> 6) * (XBYTES_PER_WAVE / sizeof(uint16_t));
-    // the rows' window words (row r, word w at rowbits[NWIN r + w]) share the
-    // buffer: they are read back before any result is written
-    unsigned long long* rowbits = (unsigned long long*)buf;
     const int lane = threadIdx.x & 63;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int bx0 = 8 * (li % m.nxr);
@@ -109,6 +118,10 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
     }
     const uint8_t* base = a.occ + m.occ_off;
     const int64_t zst = (int64_t)ny * nx;
+    // the rows' window words (row r, word w at rowbits[NWIN r + w]) share the
+    // buffer: they are read back before any result is written
+    static_assert(NWIN * 64 * sizeof(unsigned long long) <= XBYTES_PER_WAVE, "row words");
+    unsigned long long* rowbits = (unsigned long long*)buf;
 #pragma unroll
     for (int r0 = 0; r0 < 64; r0 += RB) {
         uint32_t bt[RB][NWIN];
@@ -127,7 +140,8 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
 #pragma unroll
             for (int w = 0; w < NWIN; ++w) {
                 // every lane stores the same word (no per-lane branch)
-                rowbits[NWIN * r + w] = __ballot(rok && vx[w] && bt[k][w] != 0u);
+                rowbits[NWIN * r + w] =
+                    __builtin_amdgcn_ballot_w64(rok && vx[w] && bt[k][w] != 0u);
             }
         }
     }
@@ -146,12 +160,17 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
         const int w = k >> 3, h = (k >> 2) & 1, sh = 8 * (k & 3);
         b[k] = ((h ? rhi[w] : rlo[w]) >> sh) & 0xffu;
     }
-    constexpr uint32_t FAR = 1u << 20;
+    // "no obstacle": beyond every radius, and small enough that the carried
+    // distances (at most 16 (M + 8) more) stay within 16 bits
+    constexpr uint32_t FAR = 0x3000u;
     const uint32_t dmax = (uint32_t)a.dmax;
     // distance from the last voxel before the strip back to the nearest obstacle
     uint32_t L = FAR;
 #pragma unroll
     for (int k = 0; k < M; ++k) L = b[k] ? (uint32_t)__clz(b[k]) - 24u : L + 8u;
+    // the same from the last voxel of strip block 3
+    const uint32_t W0 = b[M] | (b[M + 1] << 8) | (b[M + 2] << 16) | (b[M + 3] << 24);
+    const uint32_t L4 = W0 ? (uint32_t)__clz(W0) : L + 32u;
     // rc[j]: distance from the first voxel after strip block j to the nearest
     // obstacle at or after it
     uint32_t rc[8];
@@ -168,30 +187,47 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
     const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
     // the row words are in registers from here on: the buffer takes results
     __builtin_amdgcn_wave_barrier();
+    const u16x2 one = {1, 1};
+    const u16x2 dmp = {(unsigned short)dmax, (unsigned short)dmax};
+    uint32_t Lp = L | (L4 << 16);       // blocks 0..3 | blocks 4..7
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t bj = b[M + j];
-        uint32_t mk[8], d[8];
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t bp = b[M + j] | (b[M + j + 4] << 16);
+        uint32_t mk[8];
+        u16x2 dp[8];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) mk[x] = (uint32_t)((int32_t)(bj << (31 - x)) >> 31);
+        for (int x = 0; x < 8; ++x)      // all ones where voxel x of the block is occupied
+            mk[x] = pk_sign_mask(bp << (15 - x));
 #pragma unroll
-        for (int x = 0; x < 8; ++x) { L = (L + 1u) & ~mk[x]; d[x] = L; }
-        uint32_t rr = rc[j];
+        for (int x = 0; x < 8; ++x) {
+            Lp = as_u32(as_u16x2(Lp) + one) & ~mk[x];
+            dp[x] = as_u16x2(Lp);
+        }
+        uint32_t rr = rc[j] | (rc[j + 4] << 16);
 #pragma unroll
         for (int x = 7; x >= 0; --x) {
-            rr = (rr + 1u) & ~mk[x];
-            const uint32_t v = min(min(d[x], rr), dmax);
+            rr = as_u32(as_u16x2(rr) + one) & ~mk[x];
+            const u16x2 v =
+                __builtin_elementwise_min(__builtin_elementwise_min(dp[x], as_u16x2(rr)), dmp);
+            const u16x2 sq = v * v;
             // g1 in the window's representation (binary16 for small radii)
-            buf[rofs + 8 * x] = win_f16(M)
-                ? __builtin_bit_cast(uint16_t, (_Float16)(v * v)) : (uint16_t)(v * v);
+            if (win_f16(M)) {
+                buf[rofs + 8 * x] = __builtin_bit_cast(uint16_t, (_Float16)sq.x);
+                buf[512 + rofs + 8 * x] = __builtin_bit_cast(uint16_t, (_Float16)sq.y);
+            } else {
+                buf[rofs + 8 * x] = sq.x;
+                buf[512 + rofs + 8 * x] = sq.y;
+            }
         }
-        // block j: lane writes g1 elements 8 lane .. 8 lane + 7 (16 bytes);
-        // the wave's LDS operations complete in order, the barriers keep the
-        // compiler from moving them across
+        // blocks j and j + 4: lane writes g1 elements 8 lane .. 8 lane + 7 of
+        // each (16 bytes); the wave's LDS operations complete in order, the
+        // barriers keep the compiler from moving them across
         __builtin_amdgcn_wave_barrier();
-        const uint4 v = ((const uint4*)buf)[lane];
+        const uint4 v0 = ((const uint4*)buf)[lane];
+        const uint4 v1 = ((const uint4*)buf)[64 + lane];
         __builtin_amdgcn_wave_barrier();
-        if (bx0 + j < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j) * 512 + 8 * lane) = v;
+        if (bx0 + j < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j) * 512 + 8 * lane) = v0;
+        if (bx0 + j + 4 < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j + 4) * 512 + 8 * lane) = v1;
     }
 }
 
@@ -267,12 +303,28 @@ __device__ void item_z(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     window_min<M, true, win_f16(M)>(bz0, len, Dp, blk, emit);
 }
 
+// The item -> map table, the map records and the item offsets are read-only
+// while the batch runs, and an item's index is wave-uniform: read through
+// the constant address space they become scalar loads, so the map record and
+// everything derived from it stay in scalar registers.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ inline MapDev load_map(const MapDev* maps, int mi) {
+    static_assert(sizeof(MapDev) == 4 * sizeof(i32x4), "map record size");
+    const auto* p = as_const((const i32x4*)(maps + mi));
+    struct { i32x4 w0, w1, w2, w3; } r = {p[0], p[1], p[2], p[3]};
+    return __builtin_bit_cast(MapDev, r);
+}
+
 template <int M, int PHASE>
 __device__ inline void run_item(const BArgs& a, int gi, uint32_t Dp) {
-    const int* pref = a.pref + PHASE * (a.n_maps + 1);
-    const int mi = a.itemmap[PHASE * a.icap + gi];
-    const MapDev m = a.maps[mi];
-    const int li = gi - pref[mi];
+    const int mi = as_const(a.itemmap)[PHASE * a.icap + gi];
+    const MapDev m = load_map(a.maps, mi);
+    const int li = gi - as_const(a.pref)[PHASE * (a.n_maps + 1) + mi];
     if (PHASE == 0) item_x<M>(a, m, li);
     else if (PHASE == 1) item_y<M>(a, m, li, Dp);
     else item_z<M>(a, m, li, Dp);
