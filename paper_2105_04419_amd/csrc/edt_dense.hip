@@ -349,6 +349,151 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, const 
     }
 }
 
+// Lower envelope of the finite values in[q] (q = qb .. qe - 1, step `stride`
+// from src) of one column, kept as entries (q, f) at E[k * ncols]; returns
+// the index of the top entry (-1: none).  The top three entries are held in
+// registers so a pop needs no load; the column is read CH values at a time,
+// the next CH in flight while the current ones are pushed.
+template <int CH>
+__device__ inline int build_envelope(const int32_t* src, int64_t stride, int qb, int qe,
+                                     int2* E, int64_t ncols) {
+    int k = -1;
+    int v0 = 0, v1 = 0, v2 = 0;
+    int64_t F0 = 0, F1 = 0, F2 = 0;                  // f + v^2
+    int32_t buf[CH], nbuf[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) buf[u] = qb + u < qe ? src[stride * (qb + u)] : DINF;
+    for (int q0 = qb; q0 < qe; q0 += CH) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            nbuf[u] = q0 + CH + u < qe ? src[stride * (q0 + CH + u)] : DINF;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int q = q0 + u;
+            const int32_t f = buf[u];
+            if (f == DINF) continue;
+            const int64_t Fq = (int64_t)f + (int64_t)q * q;
+            while (k >= 1 && (Fq - F1) * (int64_t)(v1 - v0) <= (F1 - F0) * (int64_t)(q - v1)) {
+                --k;
+                v1 = v0;
+                F1 = F0;
+                v0 = v2;
+                F0 = F2;
+                if (k >= 2) {
+                    const int2 e = E[(int64_t)(k - 2) * ncols];
+                    v2 = e.x;
+                    F2 = (int64_t)e.y + (int64_t)e.x * e.x;
+                }
+            }
+            ++k;
+            E[(int64_t)k * ncols] = make_int2(q, f);
+            v2 = v0;
+            F2 = F0;
+            v0 = v1;
+            F0 = F1;
+            v1 = q;
+            F1 = Fq;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) buf[u] = nbuf[u];
+    }
+    return k;
+}
+
+// Read-off state of one envelope: entry j covers q while the next one is not
+// yet lower; the entry after next is fetched one step ahead.
+struct EnvCursor {
+    const int2* E;
+    int64_t ncols;
+    int k, j;
+    int2 cur, nxt, nx2;
+    __device__ void init(const int2* e, int64_t nc, int top) {
+        E = e;
+        ncols = nc;
+        k = top;
+        j = 0;
+        cur = nxt = nx2 = make_int2(0, 0);
+        if (k >= 0) {
+            cur = E[0];
+            nxt = k >= 1 ? E[ncols] : cur;
+            nx2 = k >= 2 ? E[2 * ncols] : nxt;
+        }
+    }
+    // the envelope's value at q (rows taken in increasing order); INT64_MAX
+    // for an empty envelope
+    __device__ int64_t at(int q) {
+        if (k < 0) return INT64_MAX;
+        while (j < k) {
+            const int64_t Fc = (int64_t)cur.y + (int64_t)cur.x * cur.x;
+            const int64_t Fn = (int64_t)nxt.y + (int64_t)nxt.x * nxt.x;
+            if (Fn - Fc > 2ll * q * (int64_t)(nxt.x - cur.x)) break;
+            ++j;
+            cur = nxt;
+            nxt = nx2;
+            if (j + 2 <= k) nx2 = E[(int64_t)(j + 2) * ncols];
+        }
+        return (int64_t)(q - cur.x) * (q - cur.x) + cur.y;
+    }
+};
+
+// Pass y of the global dense transform with two lanes per column: lanes
+// 0..31 take rows [0, n0) of 32 columns, lanes 32..63 rows [n0, ny) of the
+// same columns, and each builds the envelope of its own half.  The envelope
+// of all of a column's sites is the pointwise minimum of the envelopes of
+// the two halves, so each lane reads its own envelope and its partner's over
+// its rows.  Long y columns give few column groups (2,048 at 1024 x 1024 x
+// 128, two waves per SIMD); this form has twice as many waves, each with
+// half the build and twice the read-off.  No cap (the z pass caps).  `in`
+// and `out` may be the same array: every lane of the wave has read its rows
+// before any lane writes.
+template <int CH>
+__global__ void __launch_bounds__(64) k_dense_col_y2(int nx, int ny, int nz,
+                                                     const int32_t* in, int32_t* out,
+                                                     int2* env) {
+    const int lane = threadIdx.x, half = lane >> 5;
+    const int n0 = (ny + 1) / 2;
+    const int qb = half ? n0 : 0, qe = half ? ny : n0;
+    const int64_t stride = nx;
+    const int nxc = (nx + 31) / 32;
+    const int64_t ncols = (int64_t)nx * nz;
+    const int64_t waves = (int64_t)nxc * nz;
+    for (int64_t wv = blockIdx.x; wv < waves; wv += gridDim.x) {
+        const int x = (int)(wv % nxc) * 32 + (lane & 31);
+        const int w = (int)(wv / nxc);
+        const bool live = x < nx;
+        const int64_t base = (int64_t)x + (int64_t)nx * ny * w;
+        const int64_t col = (int64_t)x + (int64_t)nx * w;
+        // half h keeps its entries from row h n0 of the column's envelope space
+        int2* E = env + col + (int64_t)qb * ncols;
+        const int k = live ? build_envelope<CH>(in + base, stride, qb, qe, E, ncols) : -1;
+        // the partner's entries were written by this wave: complete them
+        // before they are read
+        __threadfence_block();
+        const int ko = __shfl_xor(k, 32);
+        EnvCursor own, oth;
+        own.init(E, ncols, k);
+        oth.init(env + col + (int64_t)(half ? 0 : n0) * ncols, ncols, ko);
+        int32_t* dst = out + base;
+        for (int q0 = qb; q0 < qe; q0 += CH) {
+            int32_t res[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int q = q0 + u;
+                res[u] = DINF;
+                if (live && q < qe) {
+                    const int64_t d = min(own.at(q), oth.at(q));
+                    res[u] = d >= (int64_t)DINF ? DINF : (int32_t)d;
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (q0 + u < qe) dst[stride * (q0 + u)] = res[u];
+            }
+        }
+    }
+}
+
 // Incremental update of the dense context, step 1: range check and
 // voxel-keyed dedupe (the last entry of a voxel wins), as in the sparse
 // update.  ukeys / uvals: open-addressing table of capacity umask + 1.
@@ -441,9 +586,9 @@ edt_status launch_dense3(int32_t nx, int32_t ny, int32_t nz, int32_t d_max, cons
                        nx, ny, nz, d_occ, g1, none);
     // chunk lengths measured on a 1024x1024x128 extent: 16 for the long y
     // columns, 8 for z (fewer registers, more resident waves)
-    hipLaunchKernelGGL((k_dense_col<1, 16, false>), dim3(grid_of((int64_t)nxc * nz, 65536)),
-                       dim3(64), 0, st, nx, ny, nz, (const int32_t*)g1, g2, env, (int32_t)DINF,
-                       none);
+    const int nxc32 = (nx + 31) / 32;
+    hipLaunchKernelGGL((k_dense_col_y2<8>), dim3(grid_of((int64_t)nxc32 * nz, 65536)), dim3(64),
+                       0, st, nx, ny, nz, (const int32_t*)g1, g2, env);
     hipLaunchKernelGGL((k_dense_col<2, 8, false>), dim3(grid_of((int64_t)nxc * ny, 65536)),
                        dim3(64), 0, st, nx, ny, nz, (const int32_t*)g2, s, env, cap, none);
     if (hipGetLastError() != hipSuccess) return EDT_ERR_HIP;
