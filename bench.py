@@ -11,7 +11,8 @@ HBM.  `value` is extent voxels per second.  The same JSON line also reports:
                  same map;
   incremental    p50 / p99 latency of edt_update over simulated range scans
                  along the tunnels, plus an incremental == global check, and
-                 the same scans replayed from one captured HIP graph;
+                 the same scans replayed from one captured HIP graph, and
+                 the whole stream of scans back to back and as one graph;
   clearance      clearance cost forward + backward on the 64x64x32 map field
                  with 4096 x 64 waypoints, points per second;
   batched        64 dense room maps (sides 32..256, d_max 24): autotuned
@@ -377,6 +378,7 @@ def bench_incremental(g, args, torch, np):
     h.global_(torch.from_numpy(final).cuda())
     same = bool(torch.equal(h.dense(), f.dense()))
     graph = bench_incremental_graph(g, args, torch, np, dev, h)
+    stream = bench_incremental_stream(g, args, torch, np, dev, h)
     return {
         "scans": len(dev_ms),
         "p50_ms": round(pct(dev_ms, 50), 4),
@@ -387,6 +389,65 @@ def bench_incremental(g, args, torch, np):
         "dirty_blocks_mean": round(float(np.mean(dirty)), 1),
         "incremental_equals_global": same,
         "graph": graph,
+        "stream": stream,
+    }
+
+
+def bench_incremental_stream(g, args, torch, np, dev, final_field):
+    """The scans as one stream of updates: enqueued back to back with no
+    synchronisation between them, and captured together into one HIP graph
+    (every scan's own change list, unpadded) that one launch runs.  Device
+    time per scan over the whole stream; the field after it against the
+    global transform of the final map."""
+    from paper_2105_04419_amd import Field
+    todo = [(x, s) for x, s in dev if x.shape[0] > 0]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    # back to back, eager
+    f = Field(g["f"].shape, args.dmax)
+    f.global_blocks(g["xyz_d"], g["occ_d"])
+    torch.cuda.synchronize()
+    e0.record()
+    for x, s in todo:
+        f.update(x, s)
+    e1.record()
+    e1.synchronize()
+    eager_ms = e0.elapsed_time(e1)
+    eager_same = bool(torch.equal(final_field.dense(), f.dense())) and f.error() == 0
+    # one graph of all the scans' updates; warm-up on another field
+    w = Field(g["f"].shape, args.dmax)
+    w.global_blocks(g["xyz_d"], g["occ_d"])
+    q = Field(g["f"].shape, args.dmax)
+    q.global_blocks(g["xyz_d"], g["occ_d"])
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        w.update(*todo[0])
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for x, s in todo:
+            q.update(x, s)
+    torch.cuda.synchronize()
+    # the first launch uploads the graph; the second runs the same absolute
+    # changes again from the final map, which ends at the same map
+    times = []
+    for _ in range(2):
+        e0.record()
+        graph.replay()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    graph_same = bool(torch.equal(final_field.dense(), q.dense())) and q.error() == 0
+    del graph
+    return {
+        "scans": len(todo),
+        "eager_back_to_back_ms_per_scan": round(eager_ms / len(todo), 4),
+        "one_graph_ms_per_scan": round(times[-1] / len(todo), 4),
+        "one_graph_first_launch_ms_per_scan": round(times[0] / len(todo), 4),
+        "kernels_per_scan": 6,
+        "stream_equals_global": eager_same and graph_same,
     }
 
 

@@ -4,7 +4,8 @@ into the captured buffers: every replay, with eager work and synchronisation
 in between, must equal the same call made eagerly, a cancelled replay
 included (and the replays after it: the cancel mark is state on the device,
 cleared within the call, since a captured call keeps its arguments).  The
-dense context's update likewise."""
+dense context's update likewise, and a stream of several scans' updates
+captured into one graph and run by one launch."""
 import numpy as np
 import pytest
 import torch
@@ -154,3 +155,45 @@ def test_dense_context_graph_replays_match_eager():
         assert np.array_equal(got, oracle.edt_uncapped(cur)), f"replay {t} vs oracle"
         assert g_field.error() == (-2 if cancelled else 0)
         assert e_field.error() == (-2 if cancelled else 0)
+
+
+def test_stream_of_updates_in_one_graph():
+    # several scans' updates (each its own change list) captured together
+    # and run by one graph launch equal the same updates made eagerly
+    occ = workloads.dense_boxes(6)
+    nz, ny, nx = occ.shape
+    rng = np.random.default_rng(5)
+    lists = []
+    cur = occ.copy()
+    for t in range(6):
+        n = int(rng.integers(20, 300))
+        xyz = np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n), rng.integers(0, nz, n)],
+                       1).astype(np.int32)
+        st = (rng.random(n) < (0.6 if t % 2 == 0 else 0.3)).astype(np.uint8)
+        lists.append((torch.from_numpy(xyz).cuda(), torch.from_numpy(st).cuda()))
+        for (x, y, z), v in zip(xyz, st):
+            cur[z, y, x] = v
+    fields = [Field((nx, ny, nz), 16) for _ in range(3)]
+    for f in fields:
+        f.global_(torch.from_numpy(occ).cuda())
+    eager, warm, g_field = fields
+    for x, s in lists:
+        eager.update(x, s)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        warm.update(*lists[0])
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for x, s in lists:
+            g_field.update(x, s)
+    torch.cuda.synchronize()
+    want = oracle.edt_separable(cur, 16)
+    assert np.array_equal(eager.dense().cpu().numpy(), want)
+    for rep in range(2):           # the same absolute changes again end at the same map
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(g_field.dense().cpu().numpy(), want), f"launch {rep}"
+        assert g_field.error() == 0
