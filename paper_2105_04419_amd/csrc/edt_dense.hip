@@ -330,9 +330,14 @@ __global__ void __launch_bounds__(64) k_dense_col(int nx, int ny, int nz, const 
                 res[u] = (k < 0 || d >= (int64_t)cap) ? cap : (int32_t)d;
             }
             if (live) {
+                // the global transform's z pass writes the result, which it
+                // does not read again: non-temporal (2% on the tunnel extent)
 #pragma unroll
-                for (int u = 0; u < CH; ++u)
-                    if (q0 + u < n) dst[stride * (q0 + u)] = res[u];
+                for (int u = 0; u < CH; ++u) {
+                    if (q0 + u >= n) continue;
+                    if (AXIS == 2 && !INC) __builtin_nontemporal_store(res[u], &dst[stride * (q0 + u)]);
+                    else dst[stride * (q0 + u)] = res[u];
+                }
             }
             if (INC && AXIS == 1) {
                 // y = q0 + u changed in some column of the group: list the z
