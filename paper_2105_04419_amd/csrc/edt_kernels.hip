@@ -1259,6 +1259,8 @@ __global__ void __launch_bounds__(64) k_pass_win(Grid g, const int32_t* items, i
     }
 }
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 // Tile form for the global transform: one wave per column of 8 blocks along
 // the pass axis inside a tile (64 columns per tile), with M blocks of context
 // on each side taken from the neighbouring tiles.  Absent blocks hold no
@@ -1303,7 +1305,8 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                 // every block of the window is D everywhere, so is every
                 // output: pass Y records the block minimum D and stores no
                 // g2 (its readers take the shared D block); pass Z stores s
-                // as whole D blocks, 16 bytes per lane, and the maximum D
+                // as whole D blocks, 16 bytes per lane (non-temporal, as
+                // every store of s), and the maximum D
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int32_t slot = __builtin_amdgcn_readfirstlane(sl[M + j]);
@@ -1311,7 +1314,8 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
                     if (AXIS == 1) {
                         if (lane == 0) g.bmin2[slot] = (uint16_t)g.D;
                     } else {
-                        ((uint4*)(g.s + (int64_t)slot * 512))[lane] = make_uint4(Dpw, Dpw, Dpw, Dpw);
+                        __builtin_nontemporal_store((u32x4){Dpw, Dpw, Dpw, Dpw},
+                                                    (u32x4*)(g.s + (int64_t)slot * 512) + lane);
                         if (lane == 0) g.bmax[slot] = g.D;
                     }
                 }
