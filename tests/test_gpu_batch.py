@@ -39,7 +39,7 @@ def check(b, maps, out, dmax, what):
                                  f"first {bad[0]}")
 
 
-@pytest.mark.parametrize("dmax", [1, 5, 8, 13, 24, 33, 64])
+@pytest.mark.parametrize("dmax", [1, 5, 8, 13, 24, 30, 33, 45, 50, 64])   # every window size M
 def test_small_batch_all_modes(dmax):
     maps = small_maps(dmax, 7, 3, 70)
     b = Batch([(m.shape[2], m.shape[1], m.shape[0]) for m in maps], dmax)
