@@ -646,6 +646,9 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
     for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
         const int32_t* ti = g.tinfo + (it >> 6) * 8;
         const int jy = (int)(it & 7), jz = (int)((it >> 3) & 7);
+        // raised priority for the chain of lookups and loads, as in the
+        // window passes
+        __builtin_amdgcn_s_setprio(2);
         if (lane < NB) sl[lane] = axis_slot(g, ti[1], ti[0], ti[2], lane - M, 8 * jy + 64 * jz, 1);
         __syncthreads();
         bool any = false;
@@ -660,6 +663,7 @@ __global__ void __launch_bounds__(64) k_pass_x_rows(Grid g) {
                 b[k] = s2 >= 0 ? (uint32_t)occ8[(int64_t)s2 * 64 + lane] : 0u;
                 orb |= b[k];
             }
+            __builtin_amdgcn_s_setprio(0);
             if (!__any(orb != 0u)) {
                 // no obstacle in the strip or its context: every g1 is D,
                 // and a block that is D everywhere needs only its minimum
@@ -1278,6 +1282,11 @@ __global__ void __launch_bounds__(64) k_pass_win_tiles(Grid g) {
     for (int64_t it = blockIdx.x; it < ncol; it += gridDim.x) {
         const int32_t* ti = g.tinfo + (it >> 6) * 8;
         const int ca = (int)(it & 7), cb = (int)((it >> 3) & 7);
+        // the lookups and the window's first loads form a chain of
+        // dependent loads; a raised wave priority issues its links ahead of
+        // the other waves' window arithmetic (back to normal once the first
+        // window blocks are requested)
+        __builtin_amdgcn_s_setprio(2);
         if (lane < NB)
             sl[lane] = AXIS == 1 ? axis_slot(g, ti[3], ti[0], ti[4], lane - M, ca + 64 * cb, 8)
                                  : axis_slot(g, ti[5], ti[0], ti[6], lane - M, ca + 8 * cb, 64);

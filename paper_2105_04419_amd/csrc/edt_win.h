@@ -142,6 +142,9 @@ __device__ inline void window_min(int first, int count, uint32_t Dp, Blk&& blk, 
         }
         Wl = W[NW - 1];
     }
+    // a caller may raise the wave's priority for its lookups and the loads
+    // above; the window arithmetic runs at the normal priority
+    __builtin_amdgcn_s_setprio(0);
     for (int ob = first; ob < first + count; ob += 2) {
         const uint4 N0 = blk(ob + M + 2), N1 = blk(ob + M + 3);
         u16x2 acc[8];
