@@ -48,9 +48,10 @@ struct BArgs {
     int64_t icap;
     const uint8_t* occ;
     int32_t* out;
-    uint16_t* g1;
+    uint8_t* g1;             // distance along x, min(d, d_max) (8 bits per voxel)
     uint16_t* g2;
     const uint16_t* dblock;
+    const uint8_t* dblock8;  // g1 of blocks beyond a map: d_max everywhere
     uint32_t* dummy;
     int n_maps;
     int dmax, D;
@@ -66,7 +67,37 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
     return (const uint4*)arr + b * 64 + lane;
 }
 
-// phase 0: squared distance along x for a strip of 8 blocks.  The wave walks
+// g1 of block (bx, by, bz): this lane's 8 bytes (the 8 values along y of
+// column x + 8z), or the d_max block beyond the map.
+__device__ inline const uint2* blk_ptr8(const uint8_t* arr, const MapDev& m, int bx, int by,
+                                        int bz, const uint8_t* dblock8, int lane) {
+    if (bx < 0 || by < 0 || bz < 0 || bx >= m.nbx || by >= m.nby || bz >= m.nbz)
+        return (const uint2*)dblock8 + lane;
+    const int64_t b = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx + bx;
+    return (const uint2*)arr + b * 64 + lane;
+}
+
+// Eight 8-bit distances (at most 64) to their squares in the window's
+// representation, packed in 16-bit pairs in order.  v_perm builds each pair
+// with the high bytes 0x64 (F16: 0x64nn is the binary16 of 1024 + n, exact,
+// so subtracting 1024 leaves n, and n^2 <= 1600 is exact) or zero (integer
+// squares <= 4096).
+template <bool F16>
+__device__ inline uint4 g1_squares(uint2 w) {
+    const uint32_t hi = F16 ? 0x64646464u : 0u;
+    auto pair = [&](uint32_t word, uint32_t k) -> uint32_t {
+        const uint32_t x = __builtin_amdgcn_perm(hi, word, k | (4u << 8) | ((k + 1u) << 16) | (4u << 24));
+        if (F16) {
+            const h16x2 f = as_h16x2(as_u16x2(x)) - (h16x2){(_Float16)1024, (_Float16)1024};
+            return as_u32(as_u16x2(f * f));
+        }
+        const u16x2 v = as_u16x2(x);
+        return as_u32(v * v);
+    };
+    return make_uint4(pair(w.x, 0u), pair(w.x, 2u), pair(w.y, 0u), pair(w.y, 2u));
+}
+
+// phase 0: distance along x for a strip of 8 blocks.  The wave walks
 // the strip's 64 rows (y, z); for each row the lanes read the window
 // x = 8 (bx0 - M) .. 8 (bx0 + 8 + M) - 1 with coalesced byte loads (64 + 16M
 // bytes, up to three per lane), ballots make it a bit string, which goes
@@ -75,8 +106,10 @@ __device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int
 // packed 16-bit pairs: blocks j and j + 4 of the strip at once (the carry
 // into block 4 comes from the bits of blocks 0..3, the carry out of block 3
 // from those of blocks 4..7), about 6 operations per voxel; M = ceil(d_max /
-// 8) blocks of context cover d_max.  Results gather in LDS in the g1 block
-// layout (y + 8x + 64z), two blocks at a time, and leave as 16-byte stores.
+// 8) blocks of context cover d_max.  Results, min(d, d_max) in one byte
+// (phase 1 squares them as it loads them: half the bytes of a stored
+// square), gather in LDS in the g1 block layout (y + 8x + 64z), two blocks
+// at a time, and leave as 8-byte stores.
 // LDS of item_x: the row words of the window (64 rows of up to three 64-bit
 // words), which two result blocks (2 x 512 u16) reuse once they are read;
 // the workgroup's share is sized at launch, one slice per wave
@@ -184,6 +217,7 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
         R = bj ? (uint32_t)(__ffs(bj) - 1) : R + 8u;
     }
     const int rofs = (lane & 7) + 64 * (lane >> 3);      // this row in the g1 block layout
+    uint8_t* buf8 = (uint8_t*)buf;
     const int64_t brow = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx;
     // the row words are in registers from here on: the buffer takes results
     __builtin_amdgcn_wave_barrier();
@@ -209,25 +243,18 @@ __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
             rr = as_u32(as_u16x2(rr) + one) & ~mk[x];
             const u16x2 v =
                 __builtin_elementwise_min(__builtin_elementwise_min(dp[x], as_u16x2(rr)), dmp);
-            const u16x2 sq = v * v;
-            // g1 in the window's representation (binary16 for small radii)
-            if (win_f16(M)) {
-                buf[rofs + 8 * x] = __builtin_bit_cast(uint16_t, (_Float16)sq.x);
-                buf[512 + rofs + 8 * x] = __builtin_bit_cast(uint16_t, (_Float16)sq.y);
-            } else {
-                buf[rofs + 8 * x] = sq.x;
-                buf[512 + rofs + 8 * x] = sq.y;
-            }
+            buf8[rofs + 8 * x] = (uint8_t)v.x;
+            buf8[512 + rofs + 8 * x] = (uint8_t)v.y;
         }
         // blocks j and j + 4: lane writes g1 elements 8 lane .. 8 lane + 7 of
-        // each (16 bytes); the wave's LDS operations complete in order, the
+        // each (8 bytes); the wave's LDS operations complete in order, the
         // barriers keep the compiler from moving them across
         __builtin_amdgcn_wave_barrier();
-        const uint4 v0 = ((const uint4*)buf)[lane];
-        const uint4 v1 = ((const uint4*)buf)[64 + lane];
+        const uint2 v0 = ((const uint2*)buf8)[lane];
+        const uint2 v1 = ((const uint2*)buf8)[64 + lane];
         __builtin_amdgcn_wave_barrier();
-        if (bx0 + j < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j) * 512 + 8 * lane) = v0;
-        if (bx0 + j + 4 < m.nbx) *(uint4*)(a.g1 + (brow + bx0 + j + 4) * 512 + 8 * lane) = v1;
+        if (bx0 + j < m.nbx) *(uint2*)(a.g1 + (brow + bx0 + j) * 512 + 8 * lane) = v0;
+        if (bx0 + j + 4 < m.nbx) *(uint2*)(a.g1 + (brow + bx0 + j + 4) * 512 + 8 * lane) = v1;
     }
 }
 
@@ -243,7 +270,9 @@ __device__ void item_y(const BArgs& a, const MapDev& m, int li, uint32_t Dp) {
     const int by0 = seg * a.lrun;
     const int len = min(a.lrun, m.nby - by0);
     const int out_lane = (lane & 7) * 8 + (lane >> 3);
-    auto blk = [&](int b) -> uint4 { return *blk_ptr(a.g1, m, bx, b, bz, a.dblock, lane); };
+    auto blk = [&](int b) -> uint4 {
+        return g1_squares<win_f16(M)>(*blk_ptr8(a.g1, m, bx, b, bz, a.dblock8, lane));
+    };
     // the block bases are uniform (scalar branch, scalar base, immediate row
     // offsets)
     auto emit = [&](int ob, const u16x2* acc, bool has1) {
@@ -446,8 +475,8 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 struct BLayout {
-    int64_t off_maps, off_pref, off_queues, off_itemmap, off_g1, off_g2, off_dblock, off_dummy,
-        total;
+    int64_t off_maps, off_pref, off_queues, off_itemmap, off_g1, off_g2, off_dblock,
+        off_dblock8, off_dummy, total;
     int64_t nblocks;
     int64_t icap;            // item-map entries per phase
 };
@@ -476,9 +505,10 @@ bool blayout(const edt_batch_map* maps, int n, int dmax, BLayout* L) {
     L->off_queues = o; o += align256((int64_t)3 * (n + 1) * 4);
     L->off_itemmap = o; o += align256(3 * icap * 4);
     L->icap = icap;
-    L->off_g1 = o; o += align256(nb * 1024);
+    L->off_g1 = o; o += align256(nb * 512);
     L->off_g2 = o; o += align256(nb * 1024);
     L->off_dblock = o; o += 1024;
+    L->off_dblock8 = o; o += 512;
     L->off_dummy = o; o += align256(256 * 64 * 4 + 1024);
     L->total = o;
     L->nblocks = nb;
@@ -649,6 +679,9 @@ edt_status edt_batch_create(const edt_batch_map* maps, int32_t n_maps, int32_t d
                                      : (uint32_t)(d_max * d_max);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (uint32_t*)(b->ws + L.off_dblock),
                        (int64_t)256, D | (D << 16));
+    // and the x distance d_max, one byte per voxel, for g1
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(128), 0, st, (uint32_t*)(b->ws + L.off_dblock8),
+                       (int64_t)128, (uint32_t)d_max * 0x01010101u);
     if (hipStreamSynchronize(st) != hipSuccess) {   // the host map table may go away now
         free(b->host_maps);
         free(b);
@@ -686,9 +719,10 @@ edt_status edt_batch_run(edt_batch* b, const uint8_t* d_occ, int32_t* d_out, int
     a.queues = (int32_t*)(b->ws + L.off_queues);
     a.occ = d_occ;
     a.out = d_out;
-    a.g1 = (uint16_t*)(b->ws + L.off_g1);
+    a.g1 = (uint8_t*)(b->ws + L.off_g1);
     a.g2 = (uint16_t*)(b->ws + L.off_g2);
     a.dblock = (const uint16_t*)(b->ws + L.off_dblock);
+    a.dblock8 = (const uint8_t*)(b->ws + L.off_dblock8);
     a.dummy = (uint32_t*)(b->ws + L.off_dummy);
     a.n_maps = b->n;
     a.dmax = b->dmax;
