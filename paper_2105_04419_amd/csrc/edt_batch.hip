@@ -130,7 +130,10 @@ template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
     constexpr int NBYTES = 64 + 16 * M;          // window bytes per row
     constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
-    constexpr int RB = 16;                       // rows whose loads are in flight together
+    // rows whose loads are in flight together (32: 0.742 ms for the 64 room
+    // maps against 0.764 ms with 16 and 0.78 ms with all 64, which needs 143
+    // registers)
+    constexpr int RB = 32;
     constexpr int NB = 8 + 2 * M;                // window blocks
     uint16_t* buf = xlds + (threadIdx.x >> 6) * (XBYTES_PER_WAVE / sizeof(uint16_t));
     const int lane = threadIdx.x & 63;
