@@ -59,14 +59,6 @@ struct BArgs {
 };
 
 
-__device__ inline const uint4* blk_ptr(const uint16_t* arr, const MapDev& m, int bx, int by, int bz,
-                                       const uint16_t* dblock, int lane) {
-    if (bx < 0 || by < 0 || bz < 0 || bx >= m.nbx || by >= m.nby || bz >= m.nbz)
-        return (const uint4*)dblock + lane;
-    const int64_t b = m.blk_off + ((int64_t)bz * m.nby + by) * m.nbx + bx;
-    return (const uint4*)arr + b * 64 + lane;
-}
-
 // g1 of block (bx, by, bz): this lane's 8 bytes (the 8 values along y of
 // column x + 8z), or the d_max block beyond the map.
 __device__ inline const uint2* blk_ptr8(const uint8_t* arr, const MapDev& m, int bx, int by,
@@ -86,7 +78,8 @@ template <bool F16>
 __device__ inline uint4 g1_squares(uint2 w) {
     const uint32_t hi = F16 ? 0x64646464u : 0u;
     auto pair = [&](uint32_t word, uint32_t k) -> uint32_t {
-        const uint32_t x = __builtin_amdgcn_perm(hi, word, k | (4u << 8) | ((k + 1u) << 16) | (4u << 24));
+        const uint32_t sel = k | (4u << 8) | ((k + 1u) << 16) | (4u << 24);
+        const uint32_t x = __builtin_amdgcn_perm(hi, word, sel);
         if (F16) {
             const h16x2 f = as_h16x2(as_u16x2(x)) - (h16x2){(_Float16)1024, (_Float16)1024};
             return as_u32(as_u16x2(f * f));
@@ -111,7 +104,7 @@ __device__ inline uint4 g1_squares(uint2 w) {
 // square), gather in LDS in the g1 block layout (y + 8x + 64z), two blocks
 // at a time, and leave as 8-byte stores.
 // LDS of item_x: the row words of the window (64 rows of up to three 64-bit
-// words), which two result blocks (2 x 512 u16) reuse once they are read;
+// words), which two result blocks (2 x 512 bytes) reuse once they are read;
 // the workgroup's share is sized at launch, one slice per wave
 constexpr size_t XBYTES_PER_WAVE = 2 * 512 * sizeof(uint16_t);
 extern __shared__ __align__(16) uint16_t xlds[];
@@ -130,9 +123,8 @@ template <int M>
 __device__ void item_x(const BArgs& a, const MapDev& m, int li) {
     constexpr int NBYTES = 64 + 16 * M;          // window bytes per row
     constexpr int NWIN = (NBYTES + 63) / 64;     // 64-bit words of the window
-    // rows whose loads are in flight together (32: 0.742 ms for the 64 room
-    // maps against 0.764 ms with 16 and 0.78 ms with all 64, which needs 143
-    // registers)
+    // rows whose loads are in flight together (32 measured fastest: 16 keeps
+    // fewer loads in flight, 64 needs 143 registers)
     constexpr int RB = 32;
     constexpr int NB = 8 + 2 * M;                // window blocks
     uint16_t* buf = xlds + (threadIdx.x >> 6) * (XBYTES_PER_WAVE / sizeof(uint16_t));
